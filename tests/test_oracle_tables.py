@@ -1,0 +1,152 @@
+"""Pins of the oracle's physics tables against closed forms and library routines.
+
+Each check uses a route other than the oracle's own formula: the range-energy
+law integrated numerically, relativistic kinematics written from momentum,
+scipy quadrature, scipy's Gamma density, and textbook limiter values.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+pytestmark = pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
+
+
+def test_stopping_power_integrates_to_bragg_kleeman_range(oracle_mod, inputs):
+    """int_E1^E2 dE / S(E) = alpha (E2^p - E1^p) above the floor (Bragg-Kleeman range-energy law)."""
+    ph = inputs.PHYS
+    for e1, e2 in [(2.0, 50.0), (10.0, 100.0), (50.0, 230.0)]:
+        val, _ = integrate.quad(lambda e: 1.0 / oracle_mod.stopping(ph, e), e1, e2, epsabs=0, epsrel=1e-12)
+        exact = ph["bk_alpha"] * (e2 ** ph["bk_p"] - e1 ** ph["bk_p"])
+        assert abs(val - exact) < 1e-10 * exact
+    # R15: below the floor the coefficient is frozen at its floor value
+    assert oracle_mod.stopping(ph, 0.0) == oracle_mod.stopping(ph, ph["e_floor"])
+    assert oracle_mod.stopping(ph, 0.3) == oracle_mod.stopping(ph, ph["e_floor"])
+
+
+def test_scattering_power_matches_highland_from_momentum(oracle_mod, inputs):
+    ph = inputs.PHYS
+    for T in [1.5, 10.0, 100.0, 230.0]:
+        m = ph["mp"]
+        p = math.sqrt(T * T + 2 * T * m)           # MeV/c
+        beta = p / (T + m)
+        pv = p * beta
+        ref = (ph["highland_es"] / pv) ** 2 / ph["x0_water"]
+        assert abs(oracle_mod.scatpower(ph, T) - ref) < 1e-14 * ref
+
+
+def test_group_means_against_quadrature(oracle_mod, inputs):
+    c = inputs.small(ng=9, e_hi=45.0)
+    o = oracle_mod.Oracle(c["grid"], c["phys"])
+    ph = c["phys"]
+    for g in range(o.G):
+        a, b = o.E_face[g], o.E_face[g + 1]
+        kq, _ = integrate.quad(lambda e: ph["kappa0"] * (1 - math.exp(-e / ph["e_c"])), a, b, epsrel=1e-13)
+        assert abs(o.kappa[g] - kq / (b - a)) < 1e-12 * o.kappa[g]
+        sq, _ = integrate.quad(lambda e: oracle_mod.scatpower(ph, e), a, b, epsrel=1e-12,
+                               points=[ph["e_floor"]] if a < ph["e_floor"] < b else None, limit=200)
+        # 8-point Gauss-Legendre: near exact on smooth groups, ~1e-2 on the group holding the floor kink
+        tol = 2e-2 if a < ph["e_floor"] < b else 1e-9
+        assert abs(o.sig_tr[g] - sq / (b - a)) < tol * o.sig_tr[g]
+    assert np.allclose(o.E_mid, 0.5 * (o.E_face[1:] + o.E_face[:-1]), rtol=0, atol=1e-13)
+    assert np.allclose(np.diff(o.E_face), (c["grid"]["e_hi"] - c["grid"]["e_lo"]) / o.G, rtol=1e-13)
+
+
+def test_nuclear_energy_transfer_table(oracle_mod, inputs):
+    c = inputs.small(ng=12, e_hi=60.0)
+    o = oracle_mod.Oracle(c["grid"], c["phys"])
+    lam = c["phys"]["lambda_nuc"]
+    P1 = o.P1
+    assert np.allclose(P1.sum(axis=1), 1.0, rtol=0, atol=1e-14)        # normalised per source group
+    assert np.all(P1[np.triu_indices(o.G, 1)] == 0)        # P1[source, dest]: only down-scatter
+    assert np.all(P1[np.tril_indices(o.G)] > 0)
+    for gs in range(1, o.G):
+        r = P1[gs, 1:gs + 1] / P1[gs, :gs]
+        # exp(-lambda (E_g' - E_g)): one group closer to the source gains exp(lambda dE)
+        assert np.allclose(r, np.exp(lam * np.diff(o.E_mid)[:gs]), rtol=1e-13)
+
+
+def test_deflection_angle_matches_paper_arccos(oracle_mod):
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        u, v, up, vp = rng.uniform(-0.6, 0.6, 4)
+        Th = (1 + u * up + v * vp) / math.sqrt((1 + u * u + v * v) * (1 + up * up + vp * vp))
+        ref = math.acos(min(1.0, Th))
+        got = oracle_mod.defl_angle(u, v, up, vp)
+        if ref > 1e-3:
+            assert abs(got - ref) < 1e-11
+        assert abs(got - oracle_mod.defl_angle(up, vp, u, v)) < 1e-16
+    assert oracle_mod.defl_angle(0.1, -0.2, 0.1, -0.2) == 0.0
+
+
+def test_angular_transfer_is_gamma_law_normalised_over_destinations(oracle_mod, inputs):
+    c = inputs.small(nth=8, th_half=0.2)
+    o = oracle_mod.Oracle(c["grid"], c["phys"])
+    ph = c["phys"]
+    th = o.theta()
+    m = o.m
+    P2 = o.P2
+    assert np.allclose(P2.sum(axis=1), 1.0, atol=1e-14)
+    gam = stats.gamma(a=ph["gamma_a"], scale=1.0 / ph["gamma_b"])
+    for src in [0, m * m // 2, 5]:
+        up, vp = th[src // m], th[src % m]
+        ang = np.array([math.acos(min(1.0, (1 + th[a // m] * up + th[a % m] * vp) /
+                                  math.sqrt((1 + th[a // m] ** 2 + th[a % m] ** 2) * (1 + up ** 2 + vp ** 2))))
+                        for a in range(m * m)])
+        pdf = gam.pdf(ang)
+        ok = ang > 1e-3
+        ratio = P2[src, ok] / pdf[ok]
+        assert np.allclose(ratio, ratio[0], rtol=1e-9)          # proportional to the Gamma density
+        assert P2[src, src] == 0.0                              # alpha = 2: no zero-angle transfer
+    # isotropy: the kernel depends on the deflection angle only -> unnormalised kernel symmetric
+    K = P2 / P2.max(axis=1, keepdims=True)
+    f = np.array([[gam.pdf(oracle_mod.defl_angle(th[a // m], th[a % m], th[b // m], th[b % m]))
+                   for a in range(m * m)] for b in range(m * m)])
+    assert np.allclose(f, f.T, rtol=1e-12, atol=0)
+    assert np.allclose(P2, f / f.sum(axis=1, keepdims=True), rtol=1e-10, atol=1e-300)
+    del K
+
+
+@pytest.mark.parametrize("theta,eta", [(-1.0, 0.0), (0.0, 0.0), (0.25, 0.5), (0.5, 1.0), (0.75, 1.0), (1.0, 1.0),
+                                       (1.5, 1.5), (2.0, 2.0), (3.0, 2.0), (100.0, 2.0)])
+def test_superbee_textbook_values(oracle_mod, theta, eta):
+    assert oracle_mod.superbee(theta) == pytest.approx(eta, abs=1e-15)
+
+
+def test_initial_state_projection(oracle_mod, inputs):
+    c = inputs.small(nth=6, ng=10, e0=25.0, e_hi=40.0)
+    o = oracle_mod.Oracle(c["grid"], c["phys"])
+    b = c["beam"]
+    st = o.initial(b)
+    assert np.allclose(st[1:], 0)
+    g0 = st[0]
+    # exactly one proton in the discrete measure
+    assert abs(o.number_content(g0).sum() - 1.0) < 1e-13
+    # only the theta = 0 node is populated
+    m = o.m
+    ac = (m // 2) * m + m // 2
+    assert o.theta()[m // 2] == pytest.approx(0.0, abs=1e-15)
+    mask = np.ones(o.NA, bool)
+    mask[ac] = False
+    assert np.all(g0[:, :, mask, :] == 0)
+    # lateral cell averages of the Gaussian (scipy normal cdf), energy L2 projection (scipy quad)
+    gd = c["grid"]
+    xe = np.linspace(-gd["x_half"], gd["x_half"], gd["nx"] + 1)
+    ye = np.linspace(-gd["y_half"], gd["y_half"], gd["ny"] + 1)
+    Lx = np.diff(stats.norm.cdf(xe, b["x0"], b["sigma_x"])) / np.diff(xe)
+    Ly = np.diff(stats.norm.cdf(ye, b["y0"], b["sigma_y"])) / np.diff(ye)
+    lat = np.outer(Lx, Ly).reshape(-1)
+    E1 = np.zeros(o.G)
+    E2 = np.zeros(o.G)
+    pdf = stats.norm(b["e0"], b["sigma_e"]).pdf
+    for g in range(o.G):
+        a, bb = o.E_face[g], o.E_face[g + 1]
+        d = bb - a
+        E1[g] = integrate.quad(pdf, a, bb, epsabs=1e-15)[0] / d
+        E2[g] = 3.0 / d * integrate.quad(lambda e: pdf(e) * 2.0 * (e - 0.5 * (a + bb)) / d, a, bb, epsabs=1e-15)[0]
+    ref1 = np.outer(E1, lat) / o.dth ** 2
+    ref2 = np.outer(E2, lat) / o.dth ** 2
+    scale = g0[:, 0, ac, :].sum() / ref1.sum()
+    assert np.allclose(g0[:, 0, ac, :], scale * ref1, rtol=1e-9, atol=1e-12 * ref1.max())
+    assert np.allclose(g0[:, 1, ac, :], scale * ref2, rtol=1e-8, atol=1e-10 * abs(ref2).max())
