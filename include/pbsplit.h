@@ -1,0 +1,162 @@
+/*
+ * pbsplit.h -- C ABI of libpbsplit, a gfx950 (MI355X) implementation of the
+ * depth-splitting solver for one mono-directional proton pencil beam
+ * (Zhang, Bai, Tang: "A deterministic solver for the linear Boltzmann model
+ * of a single mono-directional proton beam").
+ *
+ * What is solved (paper section 2, eq:(f-e), and the scattering
+ * decomposition eqn:(pri-se) of section 3.1): the Fermi-Eyges reduction of
+ * the linear Boltzmann equation with continuous slowing down, small-angle
+ * elastic scattering (angular Laplacian) and catastrophic nuclear removal /
+ * re-emission, marched in depth z.  Unknowns are the DG-P1 energy
+ * coefficients (psi^1, psi^2) of every energy group on a lateral finite-volume
+ * grid (x, y) and an angular node grid (theta_x, theta_y), for the primary
+ * generation and K scattered generations (source iteration).
+ *
+ * One depth step (section 3.3, Strang splitting, Crank-Nicolson in every
+ * sub-step):   E(dz/2)  T(dz/2)  A(dz)  T(dz/2)  E(dz/2)
+ *   E: energy loss by stopping power + nuclear removal + source (eq:(0041-d)),
+ *   T: lateral transport, MUSCL with the superbee limiter (eq:(distansport)),
+ *   A: angular diffusion, 5-point Laplacian by sine transform (eq:(sd)).
+ * The dose (section 4, eq:(en_d)) is the energy lost by the proton
+ * population in the energy sub-steps, per voxel, divided by rho * volume.
+ *
+ * Conventions
+ *   - Every call returns a pbs_status; no exception or abort crosses the ABI.
+ *     pbs_last_error() gives the text (with the HIP error string for
+ *     PBS_EDEVICE).
+ *   - The library never allocates device memory.  The caller allocates one
+ *     device workspace of pbs_workspace_bytes() bytes and passes it to
+ *     pbs_bind() with a HIP stream; all work is enqueued on that stream.
+ *     The library never frees caller memory; host buffers are only read or
+ *     written during the call that receives them.
+ *   - State machine: create -> bind -> set_phantom -> set_beam ->
+ *     step_depth / run_beam -> get_dose.  set_beam may be called again to
+ *     start a new beam; set_phantom again before set_beam to change the
+ *     densities.  Out-of-order calls return PBS_ESTATE.
+ *   - Floating point: the fluence is stored and swept in the precision given
+ *     to pbs_create (PBS_FP32 or PBS_FP64); the dose is accumulated in FP64
+ *     in both.  Tables are built on the host in FP64.
+ */
+#ifndef PBSPLIT_H
+#define PBSPLIT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PBS_OK = 0,
+    PBS_EINVAL = -1,       /* bad argument (shape, NaN, non-positive density, too small workspace ...) */
+    PBS_ESTATE = -2,       /* call out of order */
+    PBS_ENOMEM = -3,       /* host allocation failed */
+    PBS_EDEVICE = -4,      /* a HIP call failed */
+    PBS_EUNSUPPORTED = -5  /* valid request this build does not implement */
+} pbs_status;
+
+enum { PBS_FP32 = 0, PBS_FP64 = 1 };
+
+/* Grid (section 3.3 depth steps; section 3.4 lateral cells and angular nodes;
+ * section 3.2 energy groups).
+ *   nx, ny     lateral cells along x (index p) and y (index q), nx*ny >= 1
+ *   nth        angular nodes per axis, even, >= 4: nodes theta_n = -th_half + n*dth,
+ *              n = 0..nth-1, dth = 2 th_half/nth; node 0 and the implicit node nth
+ *              are held at zero, so the unknowns are n = 1..nth-1 (node nth/2 is theta = 0)
+ *   ng         energy groups, uniform on [e_lo, e_hi] (MeV), ng >= 2
+ *   nz         depth steps of length dz (cm); voxel layer s spans [s dz, (s+1) dz]
+ *   ngen       generations 1 + K (primary + K catastrophic-scatter generations), 1..8
+ *   x_half, y_half  lateral half-widths (cm), the grid is centred on x = y = 0 */
+typedef struct pbs_grid {
+    int nx, ny, nth, ng, nz, ngen;
+    double x_half, y_half, th_half, e_lo, e_hi, dz;
+} pbs_grid;
+
+/* Beam: the boundary distribution eq:(bdy) (section 4) -- Gaussian in x, y
+ * (centre x0, y0, widths sigma_x, sigma_y, cm) and in energy (e0, sigma_e,
+ * MeV), mono-directional (all protons on the theta = 0 node).  The initial
+ * fluence carries one proton. */
+typedef struct pbs_beam {
+    double e0, sigma_e, x0, y0, sigma_x, sigma_y;
+} pbs_beam;
+
+/* Physics record.  Materials enter through the density only (water-
+ * equivalent per unit mass).
+ *   bk_alpha, bk_p  Bragg-Kleeman range R = alpha E^p (cm water): S = 1/(alpha p E^(p-1))
+ *   e_floor         coefficients are evaluated at max(E, e_floor) (MeV)
+ *   highland_es, x0_water, mp   scattering power sigma_tr = (E_s/pv)^2 / X0 (Highland form),
+ *                   group-averaged with 8-point Gauss-Legendre
+ *   kappa0, e_c     nuclear removal per unit mass kappa(E) = kappa0 (1 - exp(-E/e_c)) (cm^2/g)
+ *   lambda_nuc      energy transfer of re-emission  ~ exp(-lambda (E_g' - E_g)) (App. A.4)
+ *   gamma_a, gamma_b  angular transfer ~ theta^(a-1) exp(-b theta) of the deflection angle */
+typedef struct pbs_physics {
+    double bk_alpha, bk_p, e_floor, highland_es, x0_water, mp;
+    double kappa0, e_c, lambda_nuc, gamma_a, gamma_b;
+} pbs_physics;
+
+typedef struct pbs_ctx pbs_ctx; /* opaque; host-side metadata only */
+
+/* Create a context for one grid and physics record.  precision: PBS_FP32 or
+ * PBS_FP64.  *out receives the context (NULL on error).  Host memory only. */
+pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precision, pbs_ctx **out);
+
+/* Device workspace the caller must provide (bytes, 256-byte aligned start). */
+pbs_status pbs_workspace_bytes(const pbs_ctx *ctx, size_t *bytes);
+
+/* Bind the caller's device workspace and HIP stream (hipStream_t, NULL = the
+ * null stream).  The workspace must stay valid until pbs_destroy or the next
+ * bind; rebinding invalidates phantom, beam and dose. */
+pbs_status pbs_bind(pbs_ctx *ctx, void *dev_workspace, size_t bytes, void *hip_stream);
+
+/* Densities rho[s][p][q] (g/cm^3) on the computational grid, host array of
+ * nz*nx*ny doubles, C order.  Every value must be finite and > 0 (else
+ * PBS_EINVAL).  Copied; the caller keeps ownership. */
+pbs_status pbs_set_phantom(pbs_ctx *ctx, const double *rho, size_t n);
+
+/* Start a beam: builds the initial fluence (eq:(bdy) projected on the grid),
+ * zeroes the scattered generations and the dose, sets the step counter to 0. */
+pbs_status pbs_set_beam(pbs_ctx *ctx, const pbs_beam *beam);
+
+/* Advance n >= 0 depth steps (asynchronous on the bound stream).  The last
+ * energy half-step of the last advanced step is deferred and fused with the
+ * first half-step of the next one; run_beam applies the closing half-step.
+ * Splitting a march into chunks gives bitwise the same result as one call.
+ * *step_out (may be NULL) receives the number of steps done so far. */
+pbs_status pbs_step_depth(pbs_ctx *ctx, int n, int *step_out);
+
+/* March the remaining steps and apply the closing energy half-step. */
+pbs_status pbs_run_beam(pbs_ctx *ctx);
+
+/* Dose D = E_dep / (rho dx dy dz) (MeV/g per incident proton) on [nz][nx][ny],
+ * FP64, n = nz*nx*ny.  out is host memory (out_is_device = 0; the call
+ * synchronises the stream) or device memory (1; the copy is enqueued). */
+pbs_status pbs_get_dose(pbs_ctx *ctx, double *out, size_t n, int out_is_device);
+
+/* Diagnostics (used by the parity tests): read / write the fluence of all
+ * generations as FP64 host arrays in the order [k][g][l][a][p*ny+q], with
+ * a = i*(nth-1) + j over the interior angular nodes.  n = ngen*ng*2*(nth-1)^2*nx*ny.
+ * set_state requires a beam to have been set and resets nothing else. */
+pbs_status pbs_get_state(pbs_ctx *ctx, double *out, size_t n);
+pbs_status pbs_set_state(pbs_ctx *ctx, const double *in, size_t n);
+
+/* Diagnostics: apply one sub-step to the current fluence of every generation
+ * with the densities of layer `layer`:
+ *   PBS_OP_E  energy CN step of length h, generations in order with the
+ *             trapezoidal catastrophic source; the deposited energy is added
+ *             to the dose of `layer`
+ *   PBS_OP_T  lateral transport CN step of length h
+ *   PBS_OP_A  angular diffusion CN step of length h */
+enum { PBS_OP_E = 1, PBS_OP_T = 2, PBS_OP_A = 3 };
+pbs_status pbs_apply(pbs_ctx *ctx, int op, int layer, double h);
+
+/* Text of the last error of this context (never NULL). */
+const char *pbs_last_error(const pbs_ctx *ctx);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+void pbs_destroy(pbs_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBSPLIT_H */

@@ -1,0 +1,687 @@
+// libpbsplit host side: context, FP64 tables, workspace carving, the depth march schedule and
+// the C ABI declared in include/pbsplit.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pbs_common.h"
+#include "pbsplit.h"
+
+using namespace pbs;
+
+namespace {
+
+enum { ST_CREATED = 0, ST_BOUND = 1, ST_PHANTOM = 2, ST_BEAM = 3 };
+
+// 8-point Gauss-Legendre rule on [-1, 1] (Abramowitz & Stegun, table 25.4).
+const double GL8_X[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+const double GL8_W[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct pbs_ctx {
+    pbs_grid g;
+    pbs_physics ph;
+    int prec = PBS_FP32;
+    int tsz = 4;                          // sizeof(T)
+    int m = 0, NA = 0, NP = 0, NPB = 0, NPpad = 0;
+    long NLINE = 0;
+    double dx = 0, dy = 0, dth = 0;
+    // host tables (FP64)
+    std::vector<double> E_face, E_mid, dE, S_face, sig_tr, kappa, Sm, Sp, wc, wdec, invdE, dA, dB, dInj, theta, sinS,
+        lam, P2T;
+    double dBot = 0;
+    // workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    size_t o_psi = 0, o_W = 0, o_Q = 0, o_dep = 0, o_edep = 0, o_dout = 0, o_rhoT = 0, o_rhoD = 0, o_tabT = 0,
+           o_tabD = 0, total = 0;
+    // table offsets (elements) inside the T and double table blocks
+    size_t t_Sm, t_Sp, t_kap, t_wc, t_wdec, t_invdE, t_sig, t_theta, t_S, t_lam, t_P2T, t_count;
+    size_t d_A, d_B, d_Inj, d_E1, d_E2, d_lat, d_count;
+    int state = ST_CREATED;
+    int step = 0;
+    bool closed = false;
+    std::vector<double> rho_host;
+    std::string err;
+
+    template <typename T> T *psi(int k) { return reinterpret_cast<T *>(ws + o_psi) + (size_t)k * G() * 2 * NLINE; }
+    template <typename T> T *W() { return reinterpret_cast<T *>(ws + o_W); }
+    template <typename T> T *Q() { return reinterpret_cast<T *>(ws + o_Q); }
+    template <typename T> T *tabT() { return reinterpret_cast<T *>(ws + o_tabT); }
+    template <typename T> T *rhoT(int s) { return reinterpret_cast<T *>(ws + o_rhoT) + (size_t)s * NPpad; }
+    double *tabD() { return reinterpret_cast<double *>(ws + o_tabD); }
+    double *dep(int half, int k) { return reinterpret_cast<double *>(ws + o_dep) + ((size_t)half * g.ngen + k) * NLINE; }
+    double *edep(int s) { return reinterpret_cast<double *>(ws + o_edep) + (size_t)s * NP; }
+    double *dout() { return reinterpret_cast<double *>(ws + o_dout); }
+    double *rhoD() { return reinterpret_cast<double *>(ws + o_rhoD); }
+    int G() const { return g.ng; }
+};
+
+namespace {
+
+pbs_status fail(pbs_ctx *c, pbs_status st, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+pbs_status hip_fail(pbs_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, PBS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr)                                                   \
+    do {                                                                  \
+        hipError_t e_ = (expr);                                           \
+        if (e_ != hipSuccess) return hip_fail((c), e_, #expr);            \
+    } while (0)
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0; }
+
+// ------------------------------------------------------------------------------ host tables
+double stopping_power(const pbs_physics &ph, double E)
+{
+    const double e = std::max(E, ph.e_floor);
+    return 1.0 / (ph.bk_alpha * ph.bk_p * std::pow(e, ph.bk_p - 1.0));
+}
+
+double scattering_power(const pbs_physics &ph, double E)
+{
+    const double e = std::max(E, ph.e_floor);
+    const double pc2 = e * (e + 2.0 * ph.mp);           // (pc)^2
+    const double pv = pc2 / (e + ph.mp);                // p v = (pc)^2 / total energy
+    const double r = ph.highland_es / pv;
+    return r * r / ph.x0_water;
+}
+
+// angle between (1,u,v) and (1,u',v'), stable near zero
+double deflection(double u, double v, double up, double vp)
+{
+    const double c0 = u * vp - v * up, c1 = v - vp, c2 = up - u;
+    return std::atan2(std::sqrt(c0 * c0 + c1 * c1 + c2 * c2), 1.0 + u * up + v * vp);
+}
+
+void build_tables(pbs_ctx *c)
+{
+    const pbs_grid &g = c->g;
+    const pbs_physics &ph = c->ph;
+    const int G = g.ng, m = c->m, N = g.nth, NA = c->NA;
+    c->E_face.resize(G + 1);
+    c->E_mid.resize(G);
+    c->dE.resize(G);
+    for (int f = 0; f <= G; ++f) c->E_face[f] = g.e_lo + (g.e_hi - g.e_lo) * f / G;
+    for (int k = 0; k < G; ++k) {
+        c->E_mid[k] = 0.5 * (c->E_face[k] + c->E_face[k + 1]);
+        c->dE[k] = c->E_face[k + 1] - c->E_face[k];
+    }
+    c->S_face.resize(G + 1);
+    for (int f = 0; f <= G; ++f) c->S_face[f] = stopping_power(ph, c->E_face[f]);
+    c->sig_tr.assign(G, 0.0);
+    c->kappa.assign(G, 0.0);
+    for (int k = 0; k < G; ++k) {
+        double s = 0;
+        for (int t = 0; t < 4; ++t)
+            for (int sgn = -1; sgn <= 1; sgn += 2)
+                s += 0.5 * GL8_W[t] * scattering_power(ph, c->E_mid[k] + sgn * 0.5 * c->dE[k] * GL8_X[t]);
+        c->sig_tr[k] = s;
+        const double a = c->E_face[k], b = c->E_face[k + 1];
+        // mean of kappa0 (1 - exp(-E/e_c)) over [a, b]
+        c->kappa[k] = ph.kappa0 * (1.0 - ph.e_c * (std::exp(-a / ph.e_c) - std::exp(-b / ph.e_c)) / (b - a));
+    }
+    c->Sm.resize(G);
+    c->Sp.resize(G);
+    c->invdE.resize(G);
+    for (int k = 0; k < G; ++k) {
+        c->Sm[k] = c->S_face[k] / c->dE[k];
+        c->Sp[k] = c->S_face[k + 1] / c->dE[k];
+        c->invdE[k] = 1.0 / c->dE[k];
+    }
+    // re-emission energy law lambda exp(-lambda (E_g' - E_g)), normalised per source group g':
+    // W_g = (1/dE_g) U_g,  U_g = wc_g psi1_g + wdec_g U_{g+1}
+    c->wc.resize(G);
+    c->wdec.resize(G);
+    for (int k = 0; k < G; ++k) {
+        double Z = 0;
+        for (int j = 0; j <= k; ++j) Z += std::exp(-ph.lambda_nuc * (c->E_mid[k] - c->E_mid[j]));
+        c->wc[k] = c->kappa[k] * c->dE[k] / Z;
+        c->wdec[k] = k + 1 < G ? std::exp(-ph.lambda_nuc * (c->E_mid[k + 1] - c->E_mid[k])) : 0.0;
+    }
+    // deposit functional: -(energy rate of the rho-free energy operator)
+    c->dA.resize(G);
+    c->dB.resize(G);
+    c->dInj.resize(G);
+    for (int k = 0; k < G; ++k) {
+        const double Sbar = 0.5 * (c->S_face[k] + c->S_face[k + 1]);
+        const double dS = c->S_face[k + 1] - c->S_face[k];
+        c->dA[k] = c->dE[k] * (Sbar + c->kappa[k] * c->E_mid[k]);
+        c->dB[k] = c->dE[k] * (dS + c->kappa[k] * c->dE[k]) / 6.0;
+        c->dInj[k] = c->dE[k] * c->E_mid[k];
+    }
+    c->dBot = c->S_face[0] * c->E_face[0];
+    // angular tables
+    c->theta.resize(m);
+    for (int i = 0; i < m; ++i) c->theta[i] = -g.th_half + (i + 1) * c->dth;
+    c->sinS.resize((size_t)m * m);
+    for (int M = 1; M < N; ++M)
+        for (int n = 1; n < N; ++n) c->sinS[(size_t)(M - 1) * m + (n - 1)] = std::sin(M_PI * M * n / N);
+    c->lam.resize(m);
+    for (int M = 1; M < N; ++M) c->lam[M - 1] = (2.0 * std::cos(M_PI * M / N) - 2.0) / (c->dth * c->dth);
+    // nuclear angular transfer: Gamma law of the deflection angle, normalised over destinations
+    c->P2T.assign((size_t)NA * NA, 0.0);
+    const double cst = std::pow(ph.gamma_b, ph.gamma_a) / std::tgamma(ph.gamma_a);
+    std::vector<double> row(NA);
+    for (int src = 0; src < NA; ++src) {
+        const double up = c->theta[src / m], vp = c->theta[src % m];
+        double K = 0;
+        for (int dst = 0; dst < NA; ++dst) {
+            const double th = deflection(c->theta[dst / m], c->theta[dst % m], up, vp);
+            row[dst] = cst * std::pow(th, ph.gamma_a - 1.0) * std::exp(-ph.gamma_b * th);
+            K += row[dst];
+        }
+        for (int dst = 0; dst < NA; ++dst) c->P2T[(size_t)dst * NA + src] = row[dst] / K;
+    }
+}
+
+void layout(pbs_ctx *c)
+{
+    const size_t T = c->tsz;
+    const int G = c->G(), K1 = c->g.ngen;
+    size_t o = 0;
+    c->o_psi = o;
+    o = align256(o + (size_t)K1 * G * 2 * c->NLINE * T);
+    c->o_W = c->o_Q = o;
+    if (K1 > 1) {
+        c->o_W = o;
+        o = align256(o + (size_t)3 * G * c->NLINE * T);
+        c->o_Q = o;
+        o = align256(o + (size_t)3 * G * c->NLINE * T);
+    }
+    c->o_dep = o;
+    o = align256(o + (size_t)2 * K1 * c->NLINE * sizeof(double));
+    c->o_edep = o;
+    o = align256(o + (size_t)c->g.nz * c->NP * sizeof(double));
+    c->o_dout = o;
+    o = align256(o + (size_t)c->g.nz * c->NP * sizeof(double));
+    c->o_rhoT = o;
+    o = align256(o + (size_t)c->g.nz * c->NPpad * T);
+    c->o_rhoD = o;
+    o = align256(o + (size_t)c->g.nz * c->NP * sizeof(double));
+    // T tables
+    size_t e = 0;
+    c->t_Sm = e; e += G;
+    c->t_Sp = e; e += G;
+    c->t_kap = e; e += G;
+    c->t_wc = e; e += G;
+    c->t_wdec = e; e += G;
+    c->t_invdE = e; e += G;
+    c->t_sig = e; e += G;
+    c->t_theta = e; e += c->m;
+    c->t_S = e; e += (size_t)c->m * c->m;
+    c->t_lam = e; e += c->m;
+    c->t_P2T = e; e += (size_t)c->NA * c->NA;
+    c->t_count = e;
+    c->o_tabT = o;
+    o = align256(o + e * T);
+    size_t d = 0;
+    c->d_A = d; d += G;
+    c->d_B = d; d += G;
+    c->d_Inj = d; d += G;
+    c->d_E1 = d; d += G;
+    c->d_E2 = d; d += G;
+    c->d_lat = d; d += c->NP;
+    c->d_count = d;
+    c->o_tabD = o;
+    o = align256(o + d * sizeof(double));
+    c->total = o;
+}
+
+template <typename T>
+pbs_status upload_tables(pbs_ctx *c)
+{
+    std::vector<T> t(c->t_count);
+    auto put = [&](size_t off, const std::vector<double> &v) {
+        for (size_t i = 0; i < v.size(); ++i) t[off + i] = (T)v[i];
+    };
+    put(c->t_Sm, c->Sm);
+    put(c->t_Sp, c->Sp);
+    put(c->t_kap, c->kappa);
+    put(c->t_wc, c->wc);
+    put(c->t_wdec, c->wdec);
+    put(c->t_invdE, c->invdE);
+    put(c->t_sig, c->sig_tr);
+    put(c->t_theta, c->theta);
+    put(c->t_S, c->sinS);
+    put(c->t_lam, c->lam);
+    put(c->t_P2T, c->P2T);
+    std::vector<double> d(c->d_count, 0.0);
+    std::memcpy(&d[c->d_A], c->dA.data(), c->G() * sizeof(double));
+    std::memcpy(&d[c->d_B], c->dB.data(), c->G() * sizeof(double));
+    std::memcpy(&d[c->d_Inj], c->dInj.data(), c->G() * sizeof(double));
+    HIPCHK(c, hipMemcpyAsync(c->tabT<T>(), t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->tabD(), d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PBS_OK;
+}
+
+// ---------------------------------------------------------------------------- march schedule
+template <typename T>
+EParams<T> eparams(pbs_ctx *c, int k, int lay_c, int lay_o, double h)
+{
+    EParams<T> P;
+    T *tb = c->tabT<T>();
+    double *db = c->tabD();
+    P.psi = c->psi<T>(k);
+    P.Q = (k > 0) ? c->Q<T>() : nullptr;
+    P.W = (k + 1 < c->g.ngen) ? c->W<T>() : nullptr;
+    P.rho_c = lay_c >= 0 ? c->rhoT<T>(lay_c) : nullptr;
+    P.rho_o = lay_o >= 0 ? c->rhoT<T>(lay_o) : nullptr;
+    P.dep_c = c->dep(0, k);
+    P.dep_o = c->dep(1, k);
+    P.Sm = tb + c->t_Sm;
+    P.Sp = tb + c->t_Sp;
+    P.kap = tb + c->t_kap;
+    P.wc = tb + c->t_wc;
+    P.wdec = tb + c->t_wdec;
+    P.invdE = tb + c->t_invdE;
+    P.dA = db + c->d_A;
+    P.dB = db + c->d_B;
+    P.dInj = db + c->d_Inj;
+    P.dBot = c->dBot;
+    P.scale = c->dth * c->dth * c->dx * c->dy;
+    P.h = (T)h;
+    P.G = c->G();
+    P.NLINE = c->NLINE;
+    P.NAPT = (long)c->NA * PBS_PT;
+    return P;
+}
+
+// Energy half-step(s) for all generations in order.  mode: close the layer lay_c (state 0 -> 1),
+// open the layer lay_o (state 1 -> 2), or both in one sweep.  Deposits go to the FP64 dose.
+template <typename T>
+pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
+{
+    const int K1 = c->g.ngen;
+    for (int k = 0; k < K1; ++k) {
+        EParams<T> P = eparams<T>(c, k, (mode & MODE_CLOSE) ? lay_c : -1, (mode & MODE_OPEN) ? lay_o : -1, h);
+        HIPCHK(c, launch_epass<T>(P, mode, c->stream));
+        if (k + 1 < K1) {
+            QParams<T> Q;
+            Q.P2T = c->tabT<T>() + c->t_P2T;
+            Q.W = c->W<T>();
+            Q.Q = c->Q<T>();
+            Q.NA = c->NA;
+            Q.NPB = c->NPB;
+            Q.G = c->G();
+            Q.NLINE = c->NLINE;
+            Q.s0 = (mode == MODE_OPEN) ? 1 : 0;
+            Q.ns = (mode == MODE_PAIR) ? 3 : 2;
+            HIPCHK(c, launch_qgemm<T>(Q, c->stream));
+        }
+    }
+    if (mode & MODE_CLOSE)
+        HIPCHK(c, launch_dose_reduce(c->edep(lay_c), c->dep(0, 0), K1, c->NA, c->NLINE, c->NP, c->stream));
+    if (mode & MODE_OPEN)
+        HIPCHK(c, launch_dose_reduce(c->edep(lay_o), c->dep(1, 0), K1, c->NA, c->NLINE, c->NP, c->stream));
+    return PBS_OK;
+}
+
+template <typename T>
+pbs_status transport(pbs_ctx *c, double h)
+{
+    TParams<T> P;
+    P.psi = c->psi<T>(0);
+    P.theta = c->tabT<T>() + c->t_theta;
+    P.h_half_over_dx = (T)(0.5 * h / c->dx);
+    P.h_half_over_dy = (T)(0.5 * h / c->dy);
+    P.nx = c->g.nx;
+    P.ny = c->g.ny;
+    P.m = c->m;
+    P.NA = c->NA;
+    P.NLINE = c->NLINE;
+    P.nplanes = (long)c->g.ngen * c->G() * 2 * c->NA;
+    HIPCHK(c, launch_tpass<T>(P, c->stream));
+    return PBS_OK;
+}
+
+template <typename T>
+pbs_status angular(pbs_ctx *c, int layer, double h)
+{
+    AParams<T> P;
+    T *tb = c->tabT<T>();
+    P.psi = c->psi<T>(0);
+    P.rho = c->rhoT<T>(layer);
+    P.sig = tb + c->t_sig;
+    P.S = tb + c->t_S;
+    P.lam = tb + c->t_lam;
+    P.h = (T)h;
+    P.G = c->G();
+    P.NA = c->NA;
+    P.NPB = c->NPB;
+    P.NLINE = c->NLINE;
+    HIPCHK(c, launch_apass<T>(P, c->g.nth, (long)c->g.ngen * c->G() * 2, c->stream));
+    return PBS_OK;
+}
+
+template <typename T>
+pbs_status one_step(pbs_ctx *c)
+{
+    const int s = c->step;
+    const double dz = c->g.dz;
+    pbs_status r = (s == 0) ? energy_chain<T>(c, MODE_OPEN, -1, 0, 0.5 * dz)
+                            : energy_chain<T>(c, MODE_PAIR, s - 1, s, 0.5 * dz);
+    if (r != PBS_OK) return r;
+    if ((r = transport<T>(c, 0.5 * dz)) != PBS_OK) return r;
+    if ((r = angular<T>(c, s, dz)) != PBS_OK) return r;
+    if ((r = transport<T>(c, 0.5 * dz)) != PBS_OK) return r;
+    c->step = s + 1;
+    return PBS_OK;
+}
+
+template <typename T>
+pbs_status steps(pbs_ctx *c, int n)
+{
+    for (int i = 0; i < n; ++i) {
+        pbs_status r = one_step<T>(c);
+        if (r != PBS_OK) return r;
+    }
+    return PBS_OK;
+}
+
+template <typename T>
+pbs_status close_beam(pbs_ctx *c)
+{
+    if (c->step == 0) return PBS_OK;
+    return energy_chain<T>(c, MODE_CLOSE, c->step - 1, -1, 0.5 * c->g.dz);
+}
+
+template <typename T>
+pbs_status start_beam(pbs_ctx *c, const pbs_beam &b)
+{
+    const pbs_grid &g = c->g;
+    HIPCHK(c, launch_fill<T>(c->psi<T>(0), T(0), (long)g.ngen * c->G() * 2 * c->NLINE, c->stream));
+    HIPCHK(c, launch_fill<double>(c->edep(0), 0.0, (long)g.nz * c->NP, c->stream));
+    // initial condition: eq:(bdy) projected (lateral cell averages, DG-P1 energy moments, theta = 0 node)
+    auto ncdf = [](double x) { return 0.5 * std::erfc(-x / std::sqrt(2.0)); };
+    auto npdf = [](double x) { return std::exp(-0.5 * x * x) / std::sqrt(2.0 * M_PI); };
+    std::vector<double> Lx(g.nx), Ly(g.ny), E1(c->G()), E2(c->G()), lat(c->NP);
+    double tx = 0, ty = 0, te = 0;
+    for (int p = 0; p < g.nx; ++p) {
+        const double lo = -g.x_half + p * c->dx;
+        const double w = ncdf((lo + c->dx - b.x0) / b.sigma_x) - ncdf((lo - b.x0) / b.sigma_x);
+        Lx[p] = w / c->dx;
+        tx += w;
+    }
+    for (int q = 0; q < g.ny; ++q) {
+        const double lo = -g.y_half + q * c->dy;
+        const double w = ncdf((lo + c->dy - b.y0) / b.sigma_y) - ncdf((lo - b.y0) / b.sigma_y);
+        Ly[q] = w / c->dy;
+        ty += w;
+    }
+    for (int k = 0; k < c->G(); ++k) {
+        const double lo = c->E_face[k], hi = c->E_face[k + 1], d = hi - lo;
+        const double za = (lo - b.e0) / b.sigma_e, zb = (hi - b.e0) / b.sigma_e;
+        const double mass = ncdf(zb) - ncdf(za);
+        // first moment about the group centre
+        const double mom = b.sigma_e * (npdf(za) - npdf(zb)) + (b.e0 - c->E_mid[k]) * mass;
+        E1[k] = mass / d;
+        E2[k] = 6.0 * mom / (d * d);
+        te += mass;
+    }
+    if (!(tx > 0 && ty > 0 && te > 0)) return fail(c, PBS_EINVAL, "beam does not overlap the grid");
+    const double C = 1.0 / (tx * ty * te * c->dth * c->dth);
+    for (int p = 0; p < g.nx; ++p)
+        for (int q = 0; q < g.ny; ++q) lat[(size_t)p * g.ny + q] = C * Lx[p] * Ly[q];
+    double *db = c->tabD();
+    HIPCHK(c, hipMemcpyAsync(db + c->d_E1, E1.data(), E1.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(db + c->d_E2, E2.data(), E2.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(db + c->d_lat, lat.data(), lat.size() * 8, hipMemcpyHostToDevice, c->stream));
+    const long center = (long)(c->m / 2) * c->m + c->m / 2;
+    HIPCHK(c, launch_initial<T>(c->psi<T>(0), db + c->d_E1, db + c->d_E2, db + c->d_lat, center, c->G(), c->NA,
+                                c->NPB, c->NP, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PBS_OK;
+}
+
+template <typename T>
+pbs_status get_state(pbs_ctx *c, double *out)
+{
+    const size_t per = (size_t)c->G() * 2 * c->NLINE;
+    std::vector<T> buf(per * c->g.ngen);
+    HIPCHK(c, hipMemcpyAsync(buf.data(), c->psi<T>(0), buf.size() * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    size_t o = 0;
+    for (int k = 0; k < c->g.ngen; ++k)
+        for (int gl = 0; gl < c->G() * 2; ++gl)
+            for (int a = 0; a < c->NA; ++a)
+                for (int pq = 0; pq < c->NP; ++pq)
+                    out[o++] = (double)buf[k * per + gl * c->NLINE + ((size_t)(pq / PBS_PT) * c->NA + a) * PBS_PT +
+                                           pq % PBS_PT];
+    return PBS_OK;
+}
+
+template <typename T>
+pbs_status set_state(pbs_ctx *c, const double *in)
+{
+    const size_t per = (size_t)c->G() * 2 * c->NLINE;
+    std::vector<T> buf(per * c->g.ngen, T(0));
+    size_t o = 0;
+    for (int k = 0; k < c->g.ngen; ++k)
+        for (int gl = 0; gl < c->G() * 2; ++gl)
+            for (int a = 0; a < c->NA; ++a)
+                for (int pq = 0; pq < c->NP; ++pq)
+                    buf[k * per + gl * c->NLINE + ((size_t)(pq / PBS_PT) * c->NA + a) * PBS_PT + pq % PBS_PT] =
+                        (T)in[o++];
+    HIPCHK(c, hipMemcpyAsync(c->psi<T>(0), buf.data(), buf.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PBS_OK;
+}
+
+template <typename T>
+pbs_status set_phantom(pbs_ctx *c, const double *rho)
+{
+    const pbs_grid &g = c->g;
+    std::vector<T> rt((size_t)g.nz * c->NPpad, T(1));
+    for (int s = 0; s < g.nz; ++s)
+        for (int pq = 0; pq < c->NP; ++pq) rt[(size_t)s * c->NPpad + pq] = (T)rho[(size_t)s * c->NP + pq];
+    HIPCHK(c, hipMemcpyAsync(c->rhoT<T>(0), rt.data(), rt.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->rhoD(), rho, (size_t)g.nz * c->NP * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PBS_OK;
+}
+
+#define DISPATCH(c, fn, ...) ((c)->prec == PBS_FP64 ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__))
+
+}  // namespace
+
+// =================================================================================== C ABI
+extern "C" {
+
+pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precision, pbs_ctx **out)
+{
+    if (!out) return PBS_EINVAL;
+    *out = nullptr;
+    if (!grid || !phys) return PBS_EINVAL;
+    if (precision != PBS_FP32 && precision != PBS_FP64) return PBS_EINVAL;
+    const pbs_grid &g = *grid;
+    if (g.nx < 1 || g.ny < 1 || g.ny > 64 * PBS_MAX_NSEG || g.ng < 2 || g.nz < 1 || g.ngen < 1 || g.ngen > 8)
+        return PBS_EINVAL;
+    if (g.nth < 4 || g.nth % 2) return PBS_EINVAL;
+    if (!finite_pos(g.x_half) || !finite_pos(g.y_half) || !finite_pos(g.th_half) || !finite_pos(g.dz) ||
+        !std::isfinite(g.e_lo) || g.e_lo < 0 || !(g.e_hi > g.e_lo) || !std::isfinite(g.e_hi))
+        return PBS_EINVAL;
+    const pbs_physics &ph = *phys;
+    const double vals[] = {ph.bk_alpha, ph.bk_p, ph.e_floor, ph.highland_es, ph.x0_water, ph.mp,
+                           ph.kappa0,   ph.e_c,  ph.lambda_nuc, ph.gamma_a, ph.gamma_b};
+    for (double v : vals)
+        if (!std::isfinite(v)) return PBS_EINVAL;
+    if (!finite_pos(ph.bk_alpha) || !finite_pos(ph.bk_p) || !finite_pos(ph.e_floor) || !finite_pos(ph.x0_water) ||
+        !finite_pos(ph.mp) || ph.kappa0 < 0 || !finite_pos(ph.e_c) || ph.lambda_nuc < 0 || !(ph.gamma_a >= 1.0) ||
+        !finite_pos(ph.gamma_b))
+        return PBS_EINVAL;
+    if (!apass_supported(g.nth)) return PBS_EUNSUPPORTED;
+    pbs_ctx *c = new (std::nothrow) pbs_ctx();
+    if (!c) return PBS_ENOMEM;
+    c->g = g;
+    c->ph = ph;
+    c->prec = precision;
+    c->tsz = precision == PBS_FP64 ? 8 : 4;
+    c->m = g.nth - 1;
+    c->NA = c->m * c->m;
+    c->NP = g.nx * g.ny;
+    c->NPB = (c->NP + PBS_PT - 1) / PBS_PT;
+    c->NPpad = c->NPB * PBS_PT;
+    c->NLINE = (long)c->NPB * c->NA * PBS_PT;
+    c->dx = 2.0 * g.x_half / g.nx;
+    c->dy = 2.0 * g.y_half / g.ny;
+    c->dth = 2.0 * g.th_half / g.nth;
+    try {
+        build_tables(c);
+    } catch (...) {
+        delete c;
+        return PBS_ENOMEM;
+    }
+    layout(c);
+    *out = c;
+    return PBS_OK;
+}
+
+pbs_status pbs_workspace_bytes(const pbs_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return PBS_EINVAL;
+    *bytes = c->total;
+    return PBS_OK;
+}
+
+pbs_status pbs_bind(pbs_ctx *c, void *ws, size_t bytes, void *stream)
+{
+    if (!c) return PBS_EINVAL;
+    if (!ws || ((uintptr_t)ws & 255)) return fail(c, PBS_EINVAL, "workspace is NULL or not 256-byte aligned");
+    if (bytes < c->total) return fail(c, PBS_EINVAL, "workspace too small");
+    c->ws = (char *)ws;
+    c->ws_bytes = bytes;
+    c->stream = (hipStream_t)stream;
+    c->state = ST_CREATED;
+    pbs_status r = DISPATCH(c, upload_tables, c);
+    if (r != PBS_OK) return r;
+    c->state = ST_BOUND;
+    return PBS_OK;
+}
+
+pbs_status pbs_set_phantom(pbs_ctx *c, const double *rho, size_t n)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->state < ST_BOUND) return fail(c, PBS_ESTATE, "set_phantom before bind");
+    if (!rho || n != (size_t)c->g.nz * c->NP) return fail(c, PBS_EINVAL, "phantom size must be nz*nx*ny");
+    for (size_t i = 0; i < n; ++i)
+        if (!finite_pos(rho[i])) return fail(c, PBS_EINVAL, "densities must be finite and > 0");
+    pbs_status r = DISPATCH(c, set_phantom, c, rho);
+    if (r != PBS_OK) return r;
+    c->rho_host.assign(rho, rho + n);
+    c->state = ST_PHANTOM;
+    return PBS_OK;
+}
+
+pbs_status pbs_set_beam(pbs_ctx *c, const pbs_beam *b)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->state < ST_PHANTOM) return fail(c, PBS_ESTATE, "set_beam before set_phantom");
+    if (!b) return fail(c, PBS_EINVAL, "beam is NULL");
+    if (!std::isfinite(b->e0) || !finite_pos(b->sigma_e) || !std::isfinite(b->x0) || !std::isfinite(b->y0) ||
+        !finite_pos(b->sigma_x) || !finite_pos(b->sigma_y))
+        return fail(c, PBS_EINVAL, "bad beam parameters");
+    pbs_status r = DISPATCH(c, start_beam, c, *b);
+    if (r != PBS_OK) return r;
+    c->step = 0;
+    c->closed = false;
+    c->state = ST_BEAM;
+    return PBS_OK;
+}
+
+pbs_status pbs_step_depth(pbs_ctx *c, int n, int *step_out)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "step_depth before set_beam");
+    if (c->closed) return fail(c, PBS_ESTATE, "beam already finished by run_beam");
+    if (n < 0 || n > c->g.nz - c->step) return fail(c, PBS_EINVAL, "n must be in [0, nz - steps done]");
+    pbs_status r = DISPATCH(c, steps, c, n);
+    if (step_out) *step_out = c->step;
+    return r;
+}
+
+pbs_status pbs_run_beam(pbs_ctx *c)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "run_beam before set_beam");
+    if (c->closed) return fail(c, PBS_ESTATE, "beam already finished by run_beam");
+    pbs_status r = DISPATCH(c, steps, c, c->g.nz - c->step);
+    if (r != PBS_OK) return r;
+    r = DISPATCH(c, close_beam, c);
+    if (r != PBS_OK) return r;
+    c->closed = true;
+    return PBS_OK;
+}
+
+pbs_status pbs_get_dose(pbs_ctx *c, double *out, size_t n, int out_is_device)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "get_dose before set_beam");
+    const size_t tot = (size_t)c->g.nz * c->NP;
+    if (!out || n != tot) return fail(c, PBS_EINVAL, "dose buffer must hold nz*nx*ny doubles");
+    const double vol = c->dx * c->dy * c->g.dz;
+    double *dst = out_is_device ? out : c->dout();
+    HIPCHK(c, launch_dose_finalize(dst, c->edep(0), c->rhoD(), vol, (long)tot, c->stream));
+    if (!out_is_device) {
+        HIPCHK(c, hipMemcpyAsync(out, c->dout(), tot * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return PBS_OK;
+}
+
+pbs_status pbs_get_state(pbs_ctx *c, double *out, size_t n)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "get_state before set_beam");
+    if (!out || n != (size_t)c->g.ngen * c->G() * 2 * c->NA * c->NP) return fail(c, PBS_EINVAL, "bad state size");
+    return DISPATCH(c, get_state, c, out);
+}
+
+pbs_status pbs_set_state(pbs_ctx *c, const double *in, size_t n)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "set_state before set_beam");
+    if (!in || n != (size_t)c->g.ngen * c->G() * 2 * c->NA * c->NP) return fail(c, PBS_EINVAL, "bad state size");
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(in[i])) return fail(c, PBS_EINVAL, "state must be finite");
+    return DISPATCH(c, set_state, c, in);
+}
+
+pbs_status pbs_apply(pbs_ctx *c, int op, int layer, double h)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "apply before set_beam");
+    if (layer < 0 || layer >= c->g.nz || !std::isfinite(h) || h < 0) return fail(c, PBS_EINVAL, "bad layer or h");
+    switch (op) {
+    case PBS_OP_E: return DISPATCH(c, energy_chain, c, MODE_OPEN, -1, layer, h);
+    case PBS_OP_T: return DISPATCH(c, transport, c, h);
+    case PBS_OP_A: return DISPATCH(c, angular, c, layer, h);
+    default: return fail(c, PBS_EINVAL, "unknown op");
+    }
+}
+
+const char *pbs_last_error(const pbs_ctx *c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+void pbs_destroy(pbs_ctx *c) { delete c; }
+
+}  // extern "C"

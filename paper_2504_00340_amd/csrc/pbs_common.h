@@ -1,0 +1,88 @@
+// Internal declarations shared by the host side and the kernels of libpbsplit.
+//
+// Device layout of one generation of fluence (element type T = float|double):
+//   psi[g][l][pb][a][pt]      g = energy group, l = DG coefficient (0: psi^1, 1: psi^2),
+//                             a = i*m + j interior angular node (m = nth-1),
+//                             lateral cell pq = p*ny + q split as pb = pq / PT, pt = pq % PT.
+// A "line" is one (pb, a, pt) triple: line = (pb*NA + a)*PT + pt; the (g, l) slab of a
+// generation is contiguous, so element (g, l, line) sits at (g*2 + l)*NLINE + line.
+// Source and scan buffers use [state][g][line].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PBS_PT 32            // lateral tile: 32 consecutive cells = 128 B of FP32
+#define PBS_MAX_NSEG 4       // transport sweep supports ny <= 64 * PBS_MAX_NSEG
+
+namespace pbs {
+
+enum { MODE_CLOSE = 1, MODE_OPEN = 2, MODE_PAIR = 3 };
+
+template <typename T>
+struct EParams {
+    T *psi;                 // one generation
+    const T *Q;             // [3][G][NLINE] catastrophic source without the density factor, or null
+    T *W;                   // [3][G][NLINE] energy-scanned psi^1 for the next generation, or null
+    const T *rho_c;         // densities of the closing half-step layer [NPpad] (MODE_CLOSE bit)
+    const T *rho_o;         // densities of the opening half-step layer [NPpad] (MODE_OPEN bit)
+    double *dep_c;          // [NLINE] deposited energy of the closing half-step (MeV)
+    double *dep_o;          // [NLINE] deposited energy of the opening half-step
+    const T *Sm, *Sp, *kap; // S_{g-1/2}/dE_g, S_{g+1/2}/dE_g, kappa_g
+    const T *wc, *wdec, *invdE;   // energy re-emission scan: weight, decay to g-1, 1/dE_g
+    const double *dA, *dB, *dInj; // deposit functional weights (per group)
+    double dBot;            // S_{1/2} E_{1/2}: energy carried through the bottom face
+    double scale;           // dth^2 dx dy
+    T h;                    // length of each CN half-step
+    int G;
+    long NLINE, NAPT;       // lines per (g,l) slab; NA*PT
+};
+
+template <typename T>
+struct TParams {
+    T *psi;                 // base of the planes (generation 0)
+    const T *theta;         // [m] angular coordinates of the interior nodes
+    T h_half_over_dx, h_half_over_dy;   // h/(2 dx), h/(2 dy)
+    int nx, ny, m, NA;
+    long NLINE;
+    long nplanes;           // ngen*G*2*NA
+};
+
+template <typename T>
+struct AParams {
+    T *psi;
+    const T *rho;           // [NPpad] densities of the layer
+    const T *sig;           // [G] group-mean scattering power
+    const T *S;             // [(N-1)*(N-1)] sin(pi M n / N)
+    const T *lam;           // [N-1] (2cos(pi M/N) - 2)/dth^2
+    T h;                    // CN step length
+    int G, NA, NPB;
+    long NLINE;
+};
+
+template <typename T>
+struct QParams {
+    const T *P2T;           // [NA][NA]: P2T[a][a'] = probability a' -> a
+    const T *W;             // [3][G][NLINE]
+    T *Q;                   // [3][G][NLINE]
+    int NA, NPB, G;
+    int s0, ns;             // states s0 .. s0+ns-1
+    long NLINE;
+};
+
+// launchers (explicitly instantiated for float and double); return hipGetLastError()
+template <typename T> hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st);
+template <typename T> hipError_t launch_tpass(const TParams<T> &P, hipStream_t st);
+template <typename T> hipError_t launch_apass(const AParams<T> &P, int nth, long nstack, hipStream_t st);
+template <typename T> hipError_t launch_qgemm(const QParams<T> &P, hipStream_t st);
+template <typename T> hipError_t launch_fill(T *p, T v, long n, hipStream_t st);
+hipError_t launch_dose_reduce(double *edep_layer, const double *dep, int ngen, int NA, long NLINE, int NP,
+                              hipStream_t st);
+hipError_t launch_dose_finalize(double *out, const double *edep, const double *rho, double vol, long n,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_initial(T *psi0, const double *E1, const double *E2, const double *lat, long center_a, int G,
+                          int NA, int NPB, int NP, hipStream_t st);
+
+bool apass_supported(int nth);
+
+}  // namespace pbs

@@ -1,0 +1,545 @@
+// HIP kernels of libpbsplit for gfx950 (CDNA4, wave64).
+//
+//   epass   energy CN half-steps (section 3.2 DG-P1 operator eq:(0041-d); section 3.3 CN), one
+//           thread per (lateral cell, angle) line sweeping the groups from the top; the closing
+//           half of step s-1 and the opening half of step s are done in the same sweep (one read
+//           and one write of the fluence).  Also the catastrophic-source energy scan for the
+//           next generation and the FP64 deposit of eq:(en_d).
+//   tpass   lateral transport CN half-step (section 3.4, eq:(distansport), superbee slopes frozen
+//           at the old level), one wave per (x, y) plane walking the rows in the upwind order;
+//           the implicit upwind solve along a row is a first-order linear recurrence done as a
+//           64-lane affine scan.
+//   apass   angular diffusion CN step (section 3.4, eq:(sd), eq:(eqn_fly)) by the discrete sine
+//           transform with the even/odd split of the sine matrix, staged through LDS.
+//   qgemm   angular part of the catastrophic source: Q = P2^T W for every (state, group,
+//           lateral tile).
+//   dose    deterministic per-voxel reduction of the per-line deposits.
+#include "pbs_common.h"
+
+namespace pbs {
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
+// ------------------------------------------------------------------------------- energy pass
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
+{
+    constexpr bool CL = (MODE & MODE_CLOSE) != 0;
+    constexpr bool OP = (MODE & MODE_OPEN) != 0;
+    const long line = (long)blockIdx.x * 256 + threadIdx.x;
+    if (line >= P.NLINE) return;
+    const long pq = (line / P.NAPT) * PBS_PT + (line % PBS_PT);
+    const long S = P.NLINE;
+    const long QS = (long)P.G * S;
+    const double rc = CL ? (double)P.rho_c[pq] : 0.0;
+    const double ro = OP ? (double)P.rho_o[pq] : 0.0;
+    const double dac = 0.5 * (double)P.h * rc, dao = 0.5 * (double)P.h * ro;
+    const T ac = (T)dac, ao = (T)dao;
+    T fin = 0, fcl = 0, fop = 0;    // psi1 - psi2 of group g+1: input, after close, after open
+    T U0 = 0, U1 = 0, U2 = 0;       // re-emission energy scans of states 0, 1, 2
+    double ph0 = 0, ph1 = 0, ph2 = 0, injc = 0, injo = 0;
+    const bool hasQ = P.Q != nullptr, hasW = P.W != nullptr;
+    for (int g = P.G - 1; g >= 0; --g) {
+        T *p1 = P.psi + (2L * g) * S + line;
+        T *p2 = p1 + S;
+        const T x1 = *p1, x2 = *p2;
+        const T sm = P.Sm[g], sp = P.Sp[g], kp = P.kap[g];
+        // rho-free operator: psi1 row [-(S-+k), S-], psi2 row [-3S+, -(S+ + 2S- + k)], coupling S+[1,3]
+        const T d11 = -(sm + kp), d12 = sm, d21 = T(-3) * sp, d22 = -(sp + T(2) * sm + kp);
+        const T c1 = sp, c2 = T(3) * sp;
+        T q0 = 0, q1 = 0, q2 = 0;
+        if (hasQ) {
+            const long o = (long)g * S + line;
+            if (CL) q0 = P.Q[o];
+            q1 = P.Q[QS + o];
+            if (OP) q2 = P.Q[2 * QS + o];
+        }
+        T y1 = x1, y2 = x2;
+        if (CL) {
+            const T f = fin + fcl;
+            const T r1 = x1 + ac * (d11 * x1 + d12 * x2 + c1 * f + q0 + q1);
+            const T r2 = x2 + ac * (d21 * x1 + d22 * x2 + c2 * f);
+            const T m11 = T(1) - ac * d11, m12 = -ac * d12, m21 = -ac * d21, m22 = T(1) - ac * d22;
+            const T inv = fast_rcp(m11 * m22 - m12 * m21);
+            y1 = (r1 * m22 - m12 * r2) * inv;
+            y2 = (m11 * r2 - m21 * r1) * inv;
+        }
+        T z1 = y1, z2 = y2;
+        if (OP) {
+            const T f = (CL ? fcl : fin) + fop;
+            const T r1 = y1 + ao * (d11 * y1 + d12 * y2 + c1 * f + q1 + q2);
+            const T r2 = y2 + ao * (d21 * y1 + d22 * y2 + c2 * f);
+            const T m11 = T(1) - ao * d11, m12 = -ao * d12, m21 = -ao * d21, m22 = T(1) - ao * d22;
+            const T inv = fast_rcp(m11 * m22 - m12 * m21);
+            z1 = (r1 * m22 - m12 * r2) * inv;
+            z2 = (m11 * r2 - m21 * r1) * inv;
+        }
+        *p1 = z1;
+        *p2 = z2;
+        // deposit functional (FP64): stopping + removal of every state, bottom-face outflow
+        const double A = P.dA[g], B = P.dB[g];
+        if (CL) ph0 += A * (double)x1 + B * (double)x2;
+        ph1 += A * (double)y1 + B * (double)y2;
+        if (OP) ph2 += A * (double)z1 + B * (double)z2;
+        if (g == 0) {
+            if (CL) ph0 += P.dBot * ((double)x1 - (double)x2);
+            ph1 += P.dBot * ((double)y1 - (double)y2);
+            if (OP) ph2 += P.dBot * ((double)z1 - (double)z2);
+        }
+        if (hasQ) {
+            const double wi = P.dInj[g];
+            if (CL) injc += wi * ((double)q0 + (double)q1);
+            if (OP) injo += wi * ((double)q1 + (double)q2);
+        }
+        if (hasW) {
+            const T w = P.wc[g], dec = P.wdec[g], idE = P.invdE[g];
+            const long o = (long)g * S + line;
+            if (CL) {
+                U0 = w * x1 + dec * U0;
+                P.W[o] = U0 * idE;
+            }
+            U1 = w * y1 + dec * U1;
+            P.W[QS + o] = U1 * idE;
+            if (OP) {
+                U2 = w * z1 + dec * U2;
+                P.W[2 * QS + o] = U2 * idE;
+            }
+        }
+        fin = x1 - x2;
+        fcl = y1 - y2;
+        fop = z1 - z2;
+    }
+    if (CL) P.dep_c[line] = dac * (ph0 + ph1 - injc) * P.scale;
+    if (OP) P.dep_o[line] = dao * (ph1 + ph2 - injo) * P.scale;
+}
+
+template <typename T>
+hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st)
+{
+    const unsigned nb = (unsigned)((P.NLINE + 255) / 256);
+    if (mode == MODE_PAIR)
+        hipLaunchKernelGGL((epass_kernel<T, MODE_PAIR>), dim3(nb), dim3(256), 0, st, P);
+    else if (mode == MODE_OPEN)
+        hipLaunchKernelGGL((epass_kernel<T, MODE_OPEN>), dim3(nb), dim3(256), 0, st, P);
+    else
+        hipLaunchKernelGGL((epass_kernel<T, MODE_CLOSE>), dim3(nb), dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- transport pass
+// Superbee-limited face slope without division: delta = Dface * eta(Dup / Dface).
+template <typename T>
+__device__ __forceinline__ T superbee_slope(T dup, T dface)
+{
+    const T au = fabs(dup), af = fabs(dface);
+    const T v = fmax(fmin(T(2) * au, af), fmin(au, T(2) * af));
+    const bool same = (dup > T(0) && dface > T(0)) || (dup < T(0) && dface < T(0));
+    return same ? copysign(v, dface) : T(0);
+}
+
+template <typename T, int NSEG>
+__global__ __launch_bounds__(256) void tpass_kernel(TParams<T> P)
+{
+    const int lane = threadIdx.x & 63;
+    const long plane = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (plane >= P.nplanes) return;   // uniform per wave
+    const int a = (int)(plane % P.NA);
+    const long slab = plane / P.NA;
+    const T cx = P.theta[a / P.m], cy = P.theta[a % P.m];
+    const bool mx = cx < T(0), my = cy < T(0);   // sweep frames mirrored so the velocity is >= 0
+    const T ax = fabs(cx) * P.h_half_over_dx, ay = fabs(cy) * P.h_half_over_dy;
+    const T idiag = T(1) / (T(1) + ax + ay);
+    const T cq = ay * idiag;
+    T *base = P.psi + slab * P.NLINE + (long)a * PBS_PT;
+    const long NAPT = (long)P.NA * PBS_PT;
+    const int nx = P.nx, ny = P.ny;
+
+    int qcol[NSEG];
+    bool valid[NSEG];
+#pragma unroll
+    for (int s = 0; s < NSEG; ++s) {
+        const int qq = s * 64 + lane;
+        valid[s] = qq < ny;
+        qcol[s] = my ? ny - 1 - qq : qq;
+    }
+    // powers of the scan multiplier: cp[i] = cq^(2^i); cl = cq^(lane+1)
+    T cp[7];
+    cp[0] = cq;
+#pragma unroll
+    for (int i = 1; i < 7; ++i) cp[i] = cp[i - 1] * cp[i - 1];
+    T cl = T(1);
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        if (((lane + 1) >> i) & 1) cl *= cp[i];
+
+    auto load_row = [&](int r, T (&v)[NSEG]) {
+        const int p = mx ? nx - 1 - r : r;
+#pragma unroll
+        for (int s = 0; s < NSEG; ++s) {
+            T x = T(0);
+            if (r < nx && valid[s]) {
+                const long pq = (long)p * ny + qcol[s];
+                x = base[(pq / PBS_PT) * NAPT + (pq % PBS_PT)];
+            }
+            v[s] = x;
+        }
+    };
+
+    T pm1[NSEG], p0[NSEG], p1[NSEG], p2[NSEG], dxm[NSEG], ym1[NSEG];
+#pragma unroll
+    for (int s = 0; s < NSEG; ++s) pm1[s] = dxm[s] = ym1[s] = T(0);
+    load_row(0, p0);
+    load_row(1, p1);
+    for (int r = 0; r < nx; ++r) {
+        load_row(r + 2, p2);
+        T left[NSEG], dyp[NSEG];
+#pragma unroll
+        for (int s = 0; s < NSEG; ++s) {
+            const T up = __shfl_up(p0[s], 1);
+            const T dn = __shfl_down(p0[s], 1);
+            const T prev_last = s > 0 ? __shfl(p0[s > 0 ? s - 1 : 0], 63) : T(0);
+            const T next_first = s + 1 < NSEG ? __shfl(p0[s + 1 < NSEG ? s + 1 : 0], 0) : T(0);
+            left[s] = lane == 0 ? prev_last : up;
+            const T right = lane == 63 ? next_first : dn;
+            dyp[s] = superbee_slope(p0[s] - left[s], right - p0[s]);
+        }
+        T b[NSEG];
+#pragma unroll
+        for (int s = 0; s < NSEG; ++s) {
+            const T up = __shfl_up(dyp[s], 1);
+            const T prev_last = s > 0 ? __shfl(dyp[s > 0 ? s - 1 : 0], 63) : T(0);
+            const T dym = lane == 0 ? prev_last : up;
+            const T dxp = superbee_slope(p0[s] - pm1[s], p1[s] - p0[s]);
+            const T R = p0[s] - ax * ((p0[s] - pm1[s]) + (dxp - dxm[s])) - ay * ((p0[s] - left[s]) + (dyp[s] - dym));
+            b[s] = (R + ax * ym1[s]) * idiag;
+            dxm[s] = dxp;
+        }
+        // implicit recurrence along the row: y_q = b_q + cq * y_{q-1}
+        T carry = T(0);
+        const int p = mx ? nx - 1 - r : r;
+#pragma unroll
+        for (int s = 0; s < NSEG; ++s) {
+            T y = b[s];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const int d = 1 << i;
+                const T t = __shfl_up(y, d);
+                if (lane >= d) y += cp[i] * t;
+            }
+            y += cl * carry;
+            carry = __shfl(y, 63);
+            ym1[s] = y;
+            if (valid[s]) {
+                const long pq = (long)p * ny + qcol[s];
+                base[(pq / PBS_PT) * NAPT + (pq % PBS_PT)] = y;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NSEG; ++s) {
+            pm1[s] = p0[s];
+            p0[s] = p1[s];
+            p1[s] = p2[s];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_tpass(const TParams<T> &P, hipStream_t st)
+{
+    const unsigned nb = (unsigned)((P.nplanes + 3) / 4);
+    const int nseg = (P.ny + 63) / 64;
+    switch (nseg) {
+    case 1: hipLaunchKernelGGL((tpass_kernel<T, 1>), dim3(nb), dim3(256), 0, st, P); break;
+    case 2: hipLaunchKernelGGL((tpass_kernel<T, 2>), dim3(nb), dim3(256), 0, st, P); break;
+    case 3: hipLaunchKernelGGL((tpass_kernel<T, 3>), dim3(nb), dim3(256), 0, st, P); break;
+    case 4: hipLaunchKernelGGL((tpass_kernel<T, 4>), dim3(nb), dim3(256), 0, st, P); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------- angular pass
+// y_M = sum_n sin(pi M n / N) x_n over the interior nodes n, M = 1..N-1, with the even/odd split
+// sin(pi M (N-n)/N) = (-1)^(M+1) sin(pi M n/N).  S[(M-1)*(N-1) + (n-1)] holds the sines.
+template <typename T, int N>
+__device__ __forceinline__ void dst1(const T (&x)[N - 1], T (&y)[N - 1], const T *__restrict__ S)
+{
+    constexpr int H = N / 2;
+    T sp[H], dm[H];
+#pragma unroll
+    for (int n = 1; n < H; ++n) {
+        sp[n - 1] = x[n - 1] + x[N - n - 1];
+        dm[n - 1] = x[n - 1] - x[N - n - 1];
+    }
+    sp[H - 1] = x[H - 1];
+#pragma unroll
+    for (int M = 1; M < N; M += 2) {   // odd modes: symmetric part + centre node
+        T acc = T(0);
+#pragma unroll
+        for (int n = 1; n <= H; ++n) acc += S[(M - 1) * (N - 1) + (n - 1)] * sp[n - 1];
+        y[M - 1] = acc;
+    }
+#pragma unroll
+    for (int M = 2; M < N; M += 2) {   // even modes: antisymmetric part
+        T acc = T(0);
+#pragma unroll
+        for (int n = 1; n < H; ++n) acc += S[(M - 1) * (N - 1) + (n - 1)] * dm[n - 1];
+        y[M - 1] = acc;
+    }
+}
+
+template <typename T, int N, int PC>
+__global__ __launch_bounds__(256) void apass_kernel(AParams<T> P)
+{
+    constexpr int m = N - 1;
+    constexpr int NA = m * m;
+    extern __shared__ char smem_raw[];
+    T *L = reinterpret_cast<T *>(smem_raw);   // [NA][PC]
+    const int tid = threadIdx.x;
+    const long stack = blockIdx.y;           // (k*G + g)*2 + l
+    const int g = (int)((stack / 2) % P.G);
+    const int pb = blockIdx.x / (PBS_PT / PC);
+    const int c0 = (blockIdx.x % (PBS_PT / PC)) * PC;
+    T *blk = P.psi + stack * P.NLINE + (long)pb * NA * PBS_PT + c0;
+    for (int idx = tid; idx < NA * PC; idx += 256) {
+        const int a = idx / PC, c = idx % PC;
+        L[idx] = blk[(long)a * PBS_PT + c];
+    }
+    __syncthreads();
+    constexpr T inv2N = T(2) / T(N);
+    // forward transform over the first angular index for every (j, column)
+    for (int it = tid; it < m * PC; it += 256) {
+        const int j = it / PC, c = it % PC;
+        T x[m], y[m];
+#pragma unroll
+        for (int i = 0; i < m; ++i) x[i] = L[(i * m + j) * PC + c];
+        dst1<T, N>(x, y, P.S);
+#pragma unroll
+        for (int k = 0; k < m; ++k) L[(k * m + j) * PC + c] = y[k];
+    }
+    __syncthreads();
+    // over the second index: forward, CN factor (1 + a lam)/(1 - a lam), inverse
+    const T coef = T(0.25) * P.h * P.sig[g];   // (h/2) * sigma_tr/2, times rho
+    for (int it = tid; it < m * PC; it += 256) {
+        const int k = it / PC, c = it % PC;
+        const T al = coef * P.rho[(long)pb * PBS_PT + c0 + c];
+        const T lk = P.lam[k];
+        T x[m], y[m];
+#pragma unroll
+        for (int j = 0; j < m; ++j) x[j] = L[(k * m + j) * PC + c];
+        dst1<T, N>(x, y, P.S);
+#pragma unroll
+        for (int n = 0; n < m; ++n) {
+            const T lm = al * (lk + P.lam[n]);
+            y[n] = y[n] * (T(1) + lm) * fast_rcp(T(1) - lm);
+        }
+        dst1<T, N>(y, x, P.S);
+#pragma unroll
+        for (int j = 0; j < m; ++j) L[(k * m + j) * PC + c] = x[j] * inv2N;
+    }
+    __syncthreads();
+    // inverse over the first index
+    for (int it = tid; it < m * PC; it += 256) {
+        const int j = it / PC, c = it % PC;
+        T x[m], y[m];
+#pragma unroll
+        for (int k = 0; k < m; ++k) x[k] = L[(k * m + j) * PC + c];
+        dst1<T, N>(x, y, P.S);
+#pragma unroll
+        for (int i = 0; i < m; ++i) L[(i * m + j) * PC + c] = y[i] * inv2N;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NA * PC; idx += 256) {
+        const int a = idx / PC, c = idx % PC;
+        blk[(long)a * PBS_PT + c] = L[idx];
+    }
+}
+
+template <typename T, int N>
+static hipError_t launch_apass_n(const AParams<T> &P, long nstack, hipStream_t st)
+{
+    constexpr int NA = (N - 1) * (N - 1);
+    const size_t lim = 64 * 1024;
+    int pc = 32;
+    while (pc > 1 && (size_t)NA * pc * sizeof(T) > lim) pc /= 2;
+    dim3 grid((unsigned)(P.NPB * (PBS_PT / pc)), (unsigned)nstack);
+    const size_t sh = (size_t)NA * pc * sizeof(T);
+    switch (pc) {
+    case 32: hipLaunchKernelGGL((apass_kernel<T, N, 32>), grid, dim3(256), sh, st, P); break;
+    case 16: hipLaunchKernelGGL((apass_kernel<T, N, 16>), grid, dim3(256), sh, st, P); break;
+    case 8: hipLaunchKernelGGL((apass_kernel<T, N, 8>), grid, dim3(256), sh, st, P); break;
+    case 4: hipLaunchKernelGGL((apass_kernel<T, N, 4>), grid, dim3(256), sh, st, P); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+bool apass_supported(int nth)
+{
+    switch (nth) {
+    case 4: case 6: case 8: case 10: case 12: case 16: case 20: case 24: case 32: return true;
+    default: return false;
+    }
+}
+
+template <typename T>
+hipError_t launch_apass(const AParams<T> &P, int nth, long nstack, hipStream_t st)
+{
+    switch (nth) {
+    case 4: return launch_apass_n<T, 4>(P, nstack, st);
+    case 6: return launch_apass_n<T, 6>(P, nstack, st);
+    case 8: return launch_apass_n<T, 8>(P, nstack, st);
+    case 10: return launch_apass_n<T, 10>(P, nstack, st);
+    case 12: return launch_apass_n<T, 12>(P, nstack, st);
+    case 16: return launch_apass_n<T, 16>(P, nstack, st);
+    case 20: return launch_apass_n<T, 20>(P, nstack, st);
+    case 24: return launch_apass_n<T, 24>(P, nstack, st);
+    case 32: return launch_apass_n<T, 32>(P, nstack, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------- source angular product
+// Q[s][g][pb][a][pt] = sum_a' P2T[a][a'] W[s][g][pb][a'][pt]; block = 64 rows x 32 columns.
+template <typename T>
+__global__ __launch_bounds__(256) void qgemm_kernel(QParams<T> P)
+{
+    const long bt = blockIdx.x;   // ((si*G + g)*NPB + pb)
+    const int mt = blockIdx.y;
+    const int pb = (int)(bt % P.NPB);
+    const long sg = bt / P.NPB;
+    const int g = (int)(sg % P.G);
+    const int s = P.s0 + (int)(sg / P.G);
+    const long off = ((long)s * P.G + g) * P.NLINE + (long)pb * P.NA * PBS_PT;
+    const T *B = P.W + off;
+    T *C = P.Q + off;
+    __shared__ T As[64][33];
+    __shared__ T Bs[32][32];
+    const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+    const int NA = P.NA;
+    T acc[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[r] = T(0);
+    for (int k0 = 0; k0 < NA; k0 += 32) {
+        for (int idx = tid; idx < 64 * 32; idx += 256) {
+            const int row = idx >> 5, kk = idx & 31;
+            const int ga = mt * 64 + row, gk = k0 + kk;
+            As[row][kk] = (ga < NA && gk < NA) ? P.P2T[(long)ga * NA + gk] : T(0);
+        }
+        for (int idx = tid; idx < 32 * 32; idx += 256) {
+            const int kk = idx >> 5, col = idx & 31;
+            const int gk = k0 + kk;
+            Bs[kk][col] = gk < NA ? B[(long)gk * PBS_PT + col] : T(0);
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < 32; ++kk) {
+            const T bv = Bs[kk][tx];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) acc[r] += As[ty + 8 * r][kk] * bv;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int ga = mt * 64 + ty + 8 * r;
+        if (ga < NA) C[(long)ga * PBS_PT + tx] = acc[r];
+    }
+}
+
+template <typename T>
+hipError_t launch_qgemm(const QParams<T> &P, hipStream_t st)
+{
+    dim3 grid((unsigned)((long)P.ns * P.G * P.NPB), (unsigned)((P.NA + 63) / 64));
+    hipLaunchKernelGGL((qgemm_kernel<T>), grid, dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------------- misc
+template <typename T>
+__global__ void fill_kernel(T *p, T v, long n)
+{
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) p[i] = v;
+}
+
+template <typename T>
+hipError_t launch_fill(T *p, T v, long n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    long nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL((fill_kernel<T>), dim3((unsigned)nb), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+// edep[pq] += sum over generations and angles of dep[k][line(pq, a)], fixed order.
+__global__ void dose_reduce_kernel(double *edep, const double *dep, int ngen, int NA, long NLINE, int NP)
+{
+    const int pq = blockIdx.x * 256 + threadIdx.x;
+    if (pq >= NP) return;
+    const long base = (long)(pq / PBS_PT) * NA * PBS_PT + (pq % PBS_PT);
+    double s = 0.0;
+    for (int k = 0; k < ngen; ++k)
+        for (int a = 0; a < NA; ++a) s += dep[(long)k * NLINE + base + (long)a * PBS_PT];
+    edep[pq] += s;
+}
+
+hipError_t launch_dose_reduce(double *edep_layer, const double *dep, int ngen, int NA, long NLINE, int NP,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(dose_reduce_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, edep_layer, dep, ngen, NA,
+                       NLINE, NP);
+    return hipGetLastError();
+}
+
+__global__ void dose_finalize_kernel(double *out, const double *edep, const double *rho, double vol, long n)
+{
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = edep[i] / (rho[i] * vol);
+}
+
+hipError_t launch_dose_finalize(double *out, const double *edep, const double *rho, double vol, long n,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(dose_finalize_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, edep, rho,
+                       vol, n);
+    return hipGetLastError();
+}
+
+// initial fluence on the theta = 0 node: psi[g][l][pb][center][pt] = E_l[g] * lat[pq]
+template <typename T>
+__global__ void initial_kernel(T *psi0, const double *E1, const double *E2, const double *lat, long center_a,
+                               int G, int NA, int NPB, int NP)
+{
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (long)G * NP) return;
+    const int g = (int)(i / NP), pq = (int)(i % NP);
+    const long NLINE = (long)NPB * NA * PBS_PT;
+    const long line = ((long)(pq / PBS_PT) * NA + center_a) * PBS_PT + (pq % PBS_PT);
+    psi0[(2L * g) * NLINE + line] = (T)(E1[g] * lat[pq]);
+    psi0[(2L * g + 1) * NLINE + line] = (T)(E2[g] * lat[pq]);
+}
+
+template <typename T>
+hipError_t launch_initial(T *psi0, const double *E1, const double *E2, const double *lat, long center_a, int G,
+                          int NA, int NPB, int NP, hipStream_t st)
+{
+    const long n = (long)G * NP;
+    hipLaunchKernelGGL((initial_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, psi0, E1, E2, lat,
+                       center_a, G, NA, NPB, NP);
+    return hipGetLastError();
+}
+
+#define PBS_INSTANTIATE(T)                                                                                    \
+    template hipError_t launch_epass<T>(const EParams<T> &, int, hipStream_t);                                \
+    template hipError_t launch_tpass<T>(const TParams<T> &, hipStream_t);                                     \
+    template hipError_t launch_apass<T>(const AParams<T> &, int, long, hipStream_t);                          \
+    template hipError_t launch_qgemm<T>(const QParams<T> &, hipStream_t);                                     \
+    template hipError_t launch_fill<T>(T *, T, long, hipStream_t);                                            \
+    template hipError_t launch_initial<T>(T *, const double *, const double *, const double *, long, int, int, \
+                                          int, int, hipStream_t);
+PBS_INSTANTIATE(float)
+PBS_INSTANTIATE(double)
+
+}  // namespace pbs

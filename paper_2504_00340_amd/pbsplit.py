@@ -1,0 +1,171 @@
+"""Thin ctypes binding of libpbsplit (include/pbsplit.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  PyTorch supplies the device workspace and the HIP stream.  If the
+shared library is missing the import fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpbsplit.so")
+
+PBS_OK, PBS_EINVAL, PBS_ESTATE, PBS_ENOMEM, PBS_EDEVICE, PBS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+PBS_FP32, PBS_FP64 = 0, 1
+PBS_OP_E, PBS_OP_T, PBS_OP_A = 1, 2, 3
+_NAMES = {0: "PBS_OK", -1: "PBS_EINVAL", -2: "PBS_ESTATE", -3: "PBS_ENOMEM", -4: "PBS_EDEVICE",
+          -5: "PBS_EUNSUPPORTED"}
+
+EXPORTS = ["pbs_create", "pbs_workspace_bytes", "pbs_bind", "pbs_set_phantom", "pbs_set_beam", "pbs_step_depth",
+           "pbs_run_beam", "pbs_get_dose", "pbs_get_state", "pbs_set_state", "pbs_apply", "pbs_last_error",
+           "pbs_destroy"]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nth", C.c_int), ("ng", C.c_int), ("nz", C.c_int),
+                ("ngen", C.c_int), ("x_half", C.c_double), ("y_half", C.c_double), ("th_half", C.c_double),
+                ("e_lo", C.c_double), ("e_hi", C.c_double), ("dz", C.c_double)]
+
+
+class Beam(C.Structure):
+    _fields_ = [("e0", C.c_double), ("sigma_e", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
+                ("sigma_x", C.c_double), ("sigma_y", C.c_double)]
+
+
+class Physics(C.Structure):
+    _fields_ = [("bk_alpha", C.c_double), ("bk_p", C.c_double), ("e_floor", C.c_double),
+                ("highland_es", C.c_double), ("x0_water", C.c_double), ("mp", C.c_double),
+                ("kappa0", C.c_double), ("e_c", C.c_double), ("lambda_nuc", C.c_double),
+                ("gamma_a", C.c_double), ("gamma_b", C.c_double)]
+
+
+class PbsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libpbsplit.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, sz, D = C.c_void_p, C.c_size_t, C.POINTER(C.c_double)
+        L.pbs_create.argtypes = [C.POINTER(Grid), C.POINTER(Physics), C.c_int, C.POINTER(vp)]
+        L.pbs_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
+        L.pbs_bind.argtypes = [vp, vp, sz, vp]
+        L.pbs_set_phantom.argtypes = [vp, D, sz]
+        L.pbs_set_beam.argtypes = [vp, C.POINTER(Beam)]
+        L.pbs_step_depth.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
+        L.pbs_run_beam.argtypes = [vp]
+        L.pbs_get_dose.argtypes = [vp, vp, sz, C.c_int]
+        L.pbs_get_state.argtypes = [vp, D, sz]
+        L.pbs_set_state.argtypes = [vp, D, sz]
+        L.pbs_apply.argtypes = [vp, C.c_int, C.c_int, C.c_double]
+        L.pbs_last_error.argtypes = [vp]
+        L.pbs_last_error.restype = C.c_char_p
+        L.pbs_destroy.argtypes = [vp]
+        L.pbs_destroy.restype = None
+        for n in EXPORTS:
+            if n not in ("pbs_last_error", "pbs_destroy"):
+                getattr(L, n).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _mk(cls, d):
+    return cls(**{k: d[k] for k, _ in cls._fields_})
+
+
+class Solver:
+    """One libpbsplit context bound to a torch-allocated workspace on `device`."""
+
+    def __init__(self, grid: dict, phys: dict, precision: str = "fp32", device="cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.L = lib()
+        self.grid = dict(grid)
+        self.g = _mk(Grid, grid)
+        self.prec = PBS_FP64 if precision == "fp64" else PBS_FP32
+        self.ctx = C.c_void_p()
+        rc = self.L.pbs_create(C.byref(self.g), C.byref(_mk(Physics, phys)), self.prec, C.byref(self.ctx))
+        if rc != PBS_OK:
+            raise PbsError(rc, "pbs_create rejected the grid / physics")
+        nb = C.c_size_t()
+        self._check(self.L.pbs_workspace_bytes(self.ctx, C.byref(nb)))
+        self.ws_bytes = nb.value
+        self.device = torch.device(device)
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self.ws_ptr = base + ((256 - base % 256) % 256)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._check(self.L.pbs_bind(self.ctx, C.c_void_p(self.ws_ptr), self.ws_bytes,
+                                    C.c_void_p(self.stream.cuda_stream)))
+        m = grid["nth"] - 1
+        self.NA = m * m
+        self.NP = grid["nx"] * grid["ny"]
+        self.state_shape = (grid["ngen"], grid["ng"], 2, self.NA, self.NP)
+
+    def _check(self, rc):
+        if rc != PBS_OK:
+            raise PbsError(rc, self.L.pbs_last_error(self.ctx).decode())
+
+    def set_phantom(self, rho):
+        r = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+        self._check(self.L.pbs_set_phantom(self.ctx, r.ctypes.data_as(C.POINTER(C.c_double)), r.size))
+
+    def set_beam(self, beam: dict):
+        self._check(self.L.pbs_set_beam(self.ctx, C.byref(_mk(Beam, beam))))
+
+    def step(self, n: int) -> int:
+        s = C.c_int()
+        self._check(self.L.pbs_step_depth(self.ctx, int(n), C.byref(s)))
+        return s.value
+
+    def run(self):
+        self._check(self.L.pbs_run_beam(self.ctx))
+
+    def dose(self) -> np.ndarray:
+        g = self.grid
+        out = np.zeros((g["nz"], g["nx"], g["ny"]))
+        self._check(self.L.pbs_get_dose(self.ctx, out.ctypes.data_as(C.c_void_p), out.size, 0))
+        return out
+
+    def dose_device(self, out):
+        """Enqueue the dose into a float64 torch tensor on the device."""
+        assert out.dtype == self.torch.float64 and out.is_cuda and out.is_contiguous()
+        self._check(self.L.pbs_get_dose(self.ctx, C.c_void_p(out.data_ptr()), out.numel(), 1))
+
+    def state(self) -> np.ndarray:
+        out = np.zeros(self.state_shape)
+        self._check(self.L.pbs_get_state(self.ctx, out.ctypes.data_as(C.POINTER(C.c_double)), out.size))
+        return out
+
+    def set_state(self, st):
+        s = np.ascontiguousarray(st, dtype=np.float64).reshape(-1)
+        self._check(self.L.pbs_set_state(self.ctx, s.ctypes.data_as(C.POINTER(C.c_double)), s.size))
+
+    def apply(self, op: int, layer: int, h: float):
+        self._check(self.L.pbs_apply(self.ctx, int(op), int(layer), float(h)))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.pbs_destroy(self.ctx)
+            self.ctx = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

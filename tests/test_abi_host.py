@@ -1,0 +1,74 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol of include/pbsplit.h,
+and rejects bad arguments / out-of-order calls before touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2504_00340_amd import inputs as I
+from paper_2504_00340_amd import pbsplit as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pbsplit.h")).read()
+    return sorted(set(re.findall(r"\b(pbs_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = _declared()
+    assert set(names) == set(B.EXPORTS), names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _create(grid, phys=None, prec=B.PBS_FP32):
+    L = B.lib()
+    ctx = C.c_void_p()
+    rc = L.pbs_create(C.byref(B._mk(B.Grid, grid)), C.byref(B._mk(B.Physics, phys or I.PHYS)), prec, C.byref(ctx))
+    return rc, ctx
+
+
+def test_create_validates_grid_and_physics():
+    g = I.config1()["grid"]
+    rc, ctx = _create(g)
+    assert rc == B.PBS_OK and ctx.value
+    nb = C.c_size_t()
+    assert B.lib().pbs_workspace_bytes(ctx, C.byref(nb)) == B.PBS_OK and nb.value > 0
+    # state machine: everything before bind is ESTATE, bad bind is EINVAL
+    L = B.lib()
+    assert L.pbs_set_beam(ctx, C.byref(B._mk(B.Beam, I.beam(100.0)))) == B.PBS_ESTATE
+    assert L.pbs_step_depth(ctx, 1, None) == B.PBS_ESTATE
+    assert L.pbs_run_beam(ctx) == B.PBS_ESTATE
+    assert L.pbs_bind(ctx, None, nb.value, None) == B.PBS_EINVAL
+    assert L.pbs_bind(ctx, C.c_void_p(256 * 1024), nb.value - 1, None) == B.PBS_EINVAL
+    assert L.pbs_bind(ctx, C.c_void_p(256 * 1024 + 8), nb.value, None) == B.PBS_EINVAL
+    assert b"workspace" in L.pbs_last_error(ctx)
+    L.pbs_destroy(ctx)
+    for bad in [dict(g, nth=7), dict(g, nth=2), dict(g, ng=1), dict(g, nz=0), dict(g, ngen=0), dict(g, ngen=9),
+                dict(g, dz=-0.1), dict(g, x_half=float("nan")), dict(g, e_hi=g["e_lo"]), dict(g, ny=300)]:
+        rc, ctx = _create(bad)
+        assert rc == B.PBS_EINVAL and not ctx.value, bad
+    rc, _ = _create(dict(g, nth=14))
+    assert rc == B.PBS_EUNSUPPORTED
+    rc, _ = _create(g, dict(I.PHYS, bk_alpha=0.0))
+    assert rc == B.PBS_EINVAL
+    rc, _ = _create(g, prec=7)
+    assert rc == B.PBS_EINVAL
+
+
+def test_workspace_scales_with_precision_and_generations():
+    g = I.config1()["grid"]
+    sizes = {}
+    for prec in (B.PBS_FP32, B.PBS_FP64):
+        for ngen in (1, 2):
+            rc, ctx = _create(dict(g, ngen=ngen), prec=prec)
+            nb = C.c_size_t()
+            B.lib().pbs_workspace_bytes(ctx, C.byref(nb))
+            sizes[prec, ngen] = nb.value
+            B.lib().pbs_destroy(ctx)
+    assert sizes[B.PBS_FP64, 1] > sizes[B.PBS_FP32, 1]
+    assert sizes[B.PBS_FP32, 2] > 2 * sizes[B.PBS_FP32, 1] - 1

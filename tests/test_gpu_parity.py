@@ -1,0 +1,154 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Sub-steps on ragged grids (lateral tiles partly filled, ny > 64 so the row sweep spans two
+segments, several generations), the full march on configuration 1, chunked stepping, and
+error behaviour.  FP64 instantiation: <= 1e-12 relative; FP32: <= 1e-5 (sub-steps) and
+dose rel-L2 <= 1e-4 (march), the tolerance stated for the FP32 path.
+"""
+import numpy as np
+import pytest
+
+from paper_2504_00340_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(c, prec):
+    from paper_2504_00340_amd.pbsplit import Solver
+
+    s = Solver(c["grid"], c["phys"], precision=prec)
+    s.set_phantom(c["rho"])
+    s.set_beam(c["beam"])
+    return s
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+RAGGED = [dict(nx=6, ny=5, nth=6, ng=7, ngen=3, seed=1),
+          dict(nx=9, ny=70, nth=8, ng=5, ngen=2, seed=2),
+          dict(nx=33, ny=31, nth=4, ng=9, ngen=1, seed=3)]
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+
+    return oracle
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", RAGGED, ids=lambda d: "x".join(str(d[k]) for k in ("nx", "ny", "nth", "ng", "ngen")))
+def test_substeps_match_oracle(O, prec, shape):
+    c = I.small(nz=3, **shape)
+    print("case", prec, shape, flush=True)
+    o = O.Oracle(c["grid"], c["phys"])
+    s = _solver(c, prec)
+    st = I.random_state(s.state_shape, 100 + shape["seed"])
+    # make the psi^2 coefficients O(0.3) of psi^1 as in the physical states
+    st[:, :, 1] *= 0.3
+    vol = o.dx * o.dy * c["grid"]["dz"]
+    for op, h in (("T", 0.037), ("A", 0.061), ("E", 0.045)):
+        s.set_state(st)
+        ref = st.copy()
+        rho = np.ascontiguousarray(c["rho"][1].reshape(-1))
+        if op == "T":
+            s.apply(2, 1, h)
+            for k in range(ref.shape[0]):
+                o.transport_cn(ref[k], h)
+        elif op == "A":
+            s.apply(3, 1, h)
+            for k in range(ref.shape[0]):
+                o.angular_cn(ref[k], rho, h)
+        else:
+            s.set_beam(c["beam"])   # zero the dose
+            s.set_state(st)
+            s.apply(1, 1, h)
+            dep = o.energy_all(ref, rho, h)
+            dose = s.dose()
+            assert _rel(dose[1].reshape(-1), dep / (rho * vol)) < TOL[prec], op
+            assert np.all(dose[0] == 0) and np.all(dose[2] == 0)
+        got = s.state()
+        assert _rel(got, ref) < TOL[prec], (op, _rel(got, ref))
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def c1_ref(O):
+    c = I.config1()
+    o = O.Oracle(c["grid"], c["phys"])
+    dose, fin = o.run(c["beam"], c["rho"])
+    return c, dose, fin
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-4)])
+def test_config1_march_matches_oracle(c1_ref, prec, tol):
+    c, dose_ref, fin_ref = c1_ref
+    s = _solver(c, prec)
+    s.run()
+    dose = s.dose()
+    print(prec, "dose rel-L2", _rel(dose, dose_ref), "state", _rel(s.state(), fin_ref), flush=True)
+    assert _rel(dose, dose_ref) < tol
+    assert _rel(s.state(), fin_ref) < (tol if prec == "fp64" else 1e-3)
+    s.close()
+
+
+def test_ragged_march_fp64(O):
+    c = I.small(nx=9, ny=70, nth=6, ng=10, nz=6, ngen=3, e0=32.0, e_hi=40.0, depth=1.5, seed=4)
+    o = O.Oracle(c["grid"], c["phys"])
+    dref, fref = o.run(c["beam"], c["rho"])
+    s = _solver(c, "fp64")
+    s.run()
+    assert _rel(s.dose(), dref) < 1e-12
+    assert _rel(s.state(), fref) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_chunked_stepping_is_bitwise_equal(prec):
+    c = I.config1()
+    a = _solver(c, prec)
+    a.run()
+    b = _solver(c, prec)
+    for n in (1, 7, 30, 0, 22):
+        b.step(n)
+    b.run()
+    assert np.array_equal(a.dose(), b.dose())
+    assert np.array_equal(a.state(), b.state())
+    # deterministic run to run
+    a.set_beam(c["beam"])
+    a.run()
+    assert np.array_equal(a.dose(), b.dose())
+    a.close()
+    b.close()
+
+
+def test_error_paths():
+    from paper_2504_00340_amd.pbsplit import PbsError, PBS_EINVAL, PBS_ESTATE
+
+    c = I.config1()
+    s = _solver(c, "fp32")
+    with pytest.raises(PbsError) as e:
+        s.step(-1)
+    assert e.value.code == PBS_EINVAL
+    with pytest.raises(PbsError) as e:
+        s.step(c["grid"]["nz"] + 1)
+    assert e.value.code == PBS_EINVAL
+    bad = c["rho"].copy()
+    bad[3, 2, 1] = np.nan
+    with pytest.raises(PbsError):
+        s.set_phantom(bad)
+    bad[3, 2, 1] = -1.0
+    with pytest.raises(PbsError):
+        s.set_phantom(bad)
+    with pytest.raises(PbsError):
+        s.set_phantom(c["rho"][:-1])
+    s.run()
+    with pytest.raises(PbsError) as e:
+        s.step(1)
+    assert e.value.code == PBS_ESTATE
+    with pytest.raises(PbsError):
+        s.apply(9, 0, 0.1)
+    s.close()
