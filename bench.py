@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark of the depth-splitting proton solver on one MI355X.
+
+Workload (default): 150 MeV pencil beam in water, lateral 64x64 cells over +-4 cm, 32x32 angular
+nodes over +-0.15 rad, 128 energy groups on [0,160] MeV, 300 depth steps over 18 cm, primary + 3
+scattered generations, FP32 fluence with FP64 dose.  A step is one full depth step of every
+generation: fused energy half-steps with the catastrophic source, transport, angular diffusion,
+transport, dose reduction.  W untimed warm-up steps, then K timed steps between stream
+synchronisations.
+
+value = nx*ny*nth^2*G*(K+1) cell-updates per second (configured angular grid; the interior
+unknowns are (nth-1)^2 -- also reported).  The roofline entry is the dominant kernel of the timed
+region, its duration measured with HIP events on the library's stream; cpu_baseline is the FP64
+oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_TFLOPS = 78.6     # 256 CU x 2.4 GHz x 64 lanes x 2 flop (packed FP32 not used)
+FP32_MFMA_TFLOPS = 157.3
+
+
+def algorithmic(grid, tsz=4):
+    """Algorithmic bytes / flops per launch of every kernel kind for one depth step."""
+    nx, ny, nth, G, K1 = grid["nx"], grid["ny"], grid["nth"], grid["ng"], grid["ngen"]
+    NA, NP = (nth - 1) ** 2, nx * ny
+    lines = NA * NP
+    # energy pass (fused pair): psi1, psi2 read + write (4 values per group and line), per line
+    # two densities and two FP64 deposits; generation k>0 also reads 3 source values, k<K writes 3
+    ep = []
+    for k in range(K1):
+        per = 4 * tsz + (3 * tsz if k > 0 else 0) + (3 * tsz if k + 1 < K1 else 0)
+        ep.append(G * lines * per + lines * (2 * 8 + 2 * tsz))
+    ep_bytes = sum(ep) / K1
+    tp_bytes = K1 * G * 2 * lines * 2 * tsz          # every plane read and written once
+    ap_bytes = K1 * G * 2 * lines * 2 * tsz + NP * tsz
+    qg_flops = 2.0 * NA * NA * 3 * G * NP            # one source product (3 states) per generation
+    qg_bytes = 3 * G * lines * 2 * tsz + NA * NA * tsz
+    return dict(epass=("bytes", ep_bytes), tpass=("bytes", tp_bytes), apass=("bytes", ap_bytes),
+                qgemm=("flops", qg_flops, qg_bytes))
+
+
+def cpu_baseline(cfg):
+    """FP64 oracle on a bounded sample: the same physics and angular/energy grid on a 6x6 lateral
+    window (same cell size), 1 depth step, all generations."""
+    import numpy as np
+
+    from oracle import oracle as O
+
+    g = dict(cfg["grid"], nx=6, ny=6, x_half=0.375, y_half=0.375, nz=1)
+    o = O.Oracle(g, cfg["phys"])
+    st = o.initial(cfg["beam"])
+    t0 = time.perf_counter()
+    o.run(cfg["beam"], np.ones((1, 6, 6)), state=st)
+    dt = time.perf_counter() - t0
+    cells = g["nx"] * g["ny"] * g["nth"] ** 2 * g["ng"] * g["ngen"]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": cells / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 depth step of the workload on a 6x6 lateral window (same cells, angles, groups, "
+                      f"{g['ngen']} generations): {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--case", default="water", choices=["water", "bone", "lung"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU sharding is a design note, "
+              "not implemented); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2504_00340_amd import inputs as I
+    from paper_2504_00340_amd.pbsplit import Solver
+
+    cfg = I.config2(args.case)
+    g = cfg["grid"]
+    if args.warmup + args.steps > g["nz"]:
+        sys.exit(f"warmup + steps must be <= {g['nz']} depth steps")
+    print(f"bench: {cfg['name']} {args.precision}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
+          flush=True)
+    s = Solver(g, cfg["phys"], precision=args.precision, device="cuda:0")
+    s.set_phantom(cfg["rho"])
+    s.set_beam(cfg["beam"])
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_read()
+    s.profile(False)
+    dt = (t1 - t0) / args.steps
+    cells = g["nx"] * g["ny"] * g["nth"] ** 2 * g["ng"] * g["ngen"]
+    interior = g["nx"] * g["ny"] * (g["nth"] - 1) ** 2 * g["ng"] * g["ngen"]
+    print("bench: kernel totals over the timed region (ms, launches): "
+          + ", ".join(f"{k} {v[0]:.1f}/{v[1]}" for k, v in prof.items()), file=sys.stderr, flush=True)
+
+    tsz = 8 if args.precision == "fp64" else 4
+    alg = algorithmic(g, tsz)
+    dom = max((k for k in prof if k in alg), key=lambda k: prof[k][0])
+    ms, n = prof[dom]
+    avg_s = ms / max(n, 1) / 1e3
+    if alg[dom][0] == "bytes":
+        achieved = alg[dom][1] / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "algorithmic_bytes_per_launch": alg[dom][1], "avg_launch_ms": avg_s * 1e3}
+    else:
+        achieved = alg[dom][1] / avg_s / 1e12
+        peak = FP32_VALU_TFLOPS
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "kernel": dom, "algorithmic_flops_per_launch": alg[dom][1],
+                "avg_launch_ms": avg_s * 1e3}
+    out = {
+        "metric": "phase-space cell-updates/s per z-step",
+        "value": cells / dt,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg['name']}: 64x64 lateral x 32x32 angles x 128 groups x 4 generations, "
+                               f"300 depth steps", "steps_per_beam": g["nz"], "precision": args.precision},
+        "interior_cell_updates_per_s": interior / dt,
+        "beams_per_s": 1.0 / (dt * g["nz"]),
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "roofline": roof,
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -150,6 +150,14 @@ pbs_status pbs_set_state(pbs_ctx *ctx, const double *in, size_t n);
 enum { PBS_OP_E = 1, PBS_OP_T = 2, PBS_OP_A = 3 };
 pbs_status pbs_apply(pbs_ctx *ctx, int op, int layer, double h);
 
+/* Diagnostics: kernel timing.  pbs_profile(ctx, 1) starts recording a HIP event pair on the
+ * bound stream around every kernel launch, grouped by kind; pbs_profile(ctx, 0) stops and
+ * clears.  pbs_profile_read synchronises the stream and returns, for kind = 0..n-1 (at most
+ * PBS_NKIND), the summed duration in ms and the number of launches since recording began. */
+enum { PBS_K_EPASS = 0, PBS_K_TPASS = 1, PBS_K_APASS = 2, PBS_K_QGEMM = 3, PBS_K_DOSE = 4, PBS_NKIND = 5 };
+pbs_status pbs_profile(pbs_ctx *ctx, int enable);
+pbs_status pbs_profile_read(pbs_ctx *ctx, double *ms, long *launches, int n);
+
 /* Text of the last error of this context (never NULL). */
 const char *pbs_last_error(const pbs_ctx *ctx);
 

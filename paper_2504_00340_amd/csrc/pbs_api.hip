@@ -43,13 +43,19 @@ struct pbs_ctx {
     size_t o_psi = 0, o_W = 0, o_Q = 0, o_dep = 0, o_edep = 0, o_dout = 0, o_rhoT = 0, o_rhoD = 0, o_tabT = 0,
            o_tabD = 0, total = 0;
     // table offsets (elements) inside the T and double table blocks
-    size_t t_Sm, t_Sp, t_kap, t_wc, t_wdec, t_invdE, t_sig, t_theta, t_S, t_lam, t_P2T, t_count;
+    size_t t_Sm, t_Sp, t_kap, t_wc, t_wdec, t_invdE, t_sig, t_theta, t_S, t_lam, t_P2T, t_P2p, t_count;
+    int Kp = 0, Mp = 0;           // padded source product (MFMA path, FP32 with NA >= 128)
     size_t d_A, d_B, d_Inj, d_E1, d_E2, d_lat, d_count;
     int state = ST_CREATED;
     int step = 0;
     bool closed = false;
     std::vector<double> rho_host;
     std::string err;
+    // kernel timing (diagnostics)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_pairs;   // (kind, index of the start event)
 
     template <typename T> T *psi(int k) { return reinterpret_cast<T *>(ws + o_psi) + (size_t)k * G() * 2 * NLINE; }
     template <typename T> T *W() { return reinterpret_cast<T *>(ws + o_W); }
@@ -199,9 +205,9 @@ void layout(pbs_ctx *c)
     c->o_W = c->o_Q = o;
     if (K1 > 1) {
         c->o_W = o;
-        o = align256(o + (size_t)3 * G * c->NLINE * T);
+        o = align256(o + (size_t)2 * G * c->NLINE * T);
         c->o_Q = o;
-        o = align256(o + (size_t)3 * G * c->NLINE * T);
+        o = align256(o + (size_t)2 * G * c->NLINE * T);
     }
     c->o_dep = o;
     o = align256(o + (size_t)2 * K1 * c->NLINE * sizeof(double));
@@ -226,6 +232,7 @@ void layout(pbs_ctx *c)
     c->t_S = e; e += (size_t)c->m * c->m;
     c->t_lam = e; e += c->m;
     c->t_P2T = e; e += (size_t)c->NA * c->NA;
+    c->t_P2p = e; e += (size_t)c->Kp * c->Mp;
     c->t_count = e;
     c->o_tabT = o;
     o = align256(o + e * T);
@@ -260,6 +267,10 @@ pbs_status upload_tables(pbs_ctx *c)
     put(c->t_S, c->sinS);
     put(c->t_lam, c->lam);
     put(c->t_P2T, c->P2T);
+    // zero-padded, source-major copy for the MFMA product: P2p[k][a] = P2T[a][k]
+    for (int k = 0; k < c->Kp; ++k)
+        for (int a = 0; a < c->Mp; ++a)
+            t[c->t_P2p + (size_t)k * c->Mp + a] = (k < c->NA && a < c->NA) ? (T)c->P2T[(size_t)a * c->NA + k] : T(0);
     std::vector<double> d(c->d_count, 0.0);
     std::memcpy(&d[c->d_A], c->dA.data(), c->G() * sizeof(double));
     std::memcpy(&d[c->d_B], c->dB.data(), c->G() * sizeof(double));
@@ -269,6 +280,31 @@ pbs_status upload_tables(pbs_ctx *c)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PBS_OK;
 }
+
+// event pair around one launch of kind `kind` while profiling is on
+struct ProfScope {
+    pbs_ctx *c;
+    int kind;
+    size_t i0 = 0;
+    bool on = false;
+    ProfScope(pbs_ctx *c_, int k) : c(c_), kind(k)
+    {
+        if (!c->prof) return;
+        while (c->ev_pool.size() < c->ev_used + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            c->ev_pool.push_back(e);
+        }
+        i0 = c->ev_used;
+        c->ev_used += 2;
+        on = hipEventRecord(c->ev_pool[i0], c->stream) == hipSuccess;
+    }
+    ~ProfScope()
+    {
+        if (!on) return;
+        if (hipEventRecord(c->ev_pool[i0 + 1], c->stream) == hipSuccess) c->ev_pairs.push_back({kind, i0});
+    }
+};
 
 // ---------------------------------------------------------------------------- march schedule
 template <typename T>
@@ -310,7 +346,10 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
     const int K1 = c->g.ngen;
     for (int k = 0; k < K1; ++k) {
         EParams<T> P = eparams<T>(c, k, (mode & MODE_CLOSE) ? lay_c : -1, (mode & MODE_OPEN) ? lay_o : -1, h);
-        HIPCHK(c, launch_epass<T>(P, mode, c->stream));
+        {
+            ProfScope ps(c, PBS_K_EPASS);
+            HIPCHK(c, launch_epass<T>(P, mode, c->stream));
+        }
         if (k + 1 < K1) {
             QParams<T> Q;
             Q.P2T = c->tabT<T>() + c->t_P2T;
@@ -320,11 +359,16 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
             Q.NPB = c->NPB;
             Q.G = c->G();
             Q.NLINE = c->NLINE;
+            Q.P2p = c->Kp > 0 ? c->tabT<T>() + c->t_P2p : nullptr;
+            Q.Kp = c->Kp;
+            Q.Mp = c->Mp;
             Q.s0 = (mode == MODE_OPEN) ? 1 : 0;
-            Q.ns = (mode == MODE_PAIR) ? 3 : 2;
+            Q.ns = (mode == MODE_PAIR) ? 2 : 1;
+            ProfScope ps(c, PBS_K_QGEMM);
             HIPCHK(c, launch_qgemm<T>(Q, c->stream));
         }
     }
+    ProfScope ps(c, PBS_K_DOSE);
     if (mode & MODE_CLOSE)
         HIPCHK(c, launch_dose_reduce(c->edep(lay_c), c->dep(0, 0), K1, c->NA, c->NLINE, c->NP, c->stream));
     if (mode & MODE_OPEN)
@@ -346,6 +390,7 @@ pbs_status transport(pbs_ctx *c, double h)
     P.NA = c->NA;
     P.NLINE = c->NLINE;
     P.nplanes = (long)c->g.ngen * c->G() * 2 * c->NA;
+    ProfScope ps(c, PBS_K_TPASS);
     HIPCHK(c, launch_tpass<T>(P, c->stream));
     return PBS_OK;
 }
@@ -365,6 +410,7 @@ pbs_status angular(pbs_ctx *c, int layer, double h)
     P.NA = c->NA;
     P.NPB = c->NPB;
     P.NLINE = c->NLINE;
+    ProfScope ps(c, PBS_K_APASS);
     HIPCHK(c, launch_apass<T>(P, c->g.nth, (long)c->g.ngen * c->G() * 2, c->stream));
     return PBS_OK;
 }
@@ -542,6 +588,10 @@ pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precisi
     c->dx = 2.0 * g.x_half / g.nx;
     c->dy = 2.0 * g.y_half / g.ny;
     c->dth = 2.0 * g.th_half / g.nth;
+    if (precision == PBS_FP32 && c->NA >= 128) {
+        c->Kp = (c->NA + 15) / 16 * 16;
+        c->Mp = (c->NA + 127) / 128 * 128;
+    }
     try {
         build_tables(c);
     } catch (...) {
@@ -676,12 +726,47 @@ pbs_status pbs_apply(pbs_ctx *c, int op, int layer, double h)
     }
 }
 
+pbs_status pbs_profile(pbs_ctx *c, int enable)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->state < ST_BOUND) return fail(c, PBS_ESTATE, "profile before bind");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->ev_pairs.clear();
+    c->ev_used = 0;
+    c->prof = enable != 0;
+    return PBS_OK;
+}
+
+pbs_status pbs_profile_read(pbs_ctx *c, double *ms, long *launches, int n)
+{
+    if (!c) return PBS_EINVAL;
+    if (!ms || !launches || n < 0) return fail(c, PBS_EINVAL, "bad profile buffers");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < n; ++k) {
+        ms[k] = 0;
+        launches[k] = 0;
+    }
+    for (auto &pr : c->ev_pairs) {
+        if (pr.first >= n) continue;
+        float t = 0;
+        HIPCHK(c, hipEventElapsedTime(&t, c->ev_pool[pr.second], c->ev_pool[pr.second + 1]));
+        ms[pr.first] += t;
+        launches[pr.first] += 1;
+    }
+    return PBS_OK;
+}
+
 const char *pbs_last_error(const pbs_ctx *c)
 {
     if (!c) return "null context";
     return c->err.c_str();
 }
 
-void pbs_destroy(pbs_ctx *c) { delete c; }
+void pbs_destroy(pbs_ctx *c)
+{
+    if (!c) return;
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
 
 }  // extern "C"

@@ -21,8 +21,10 @@ enum { MODE_CLOSE = 1, MODE_OPEN = 2, MODE_PAIR = 3 };
 template <typename T>
 struct EParams {
     T *psi;                 // one generation
-    const T *Q;             // [3][G][NLINE] catastrophic source without the density factor, or null
-    T *W;                   // [3][G][NLINE] energy-scanned psi^1 for the next generation, or null
+    const T *Q;             // [2][G][NLINE] source without the density factor, Q^n + Q* of the closing (0)
+                            // and opening (1) half-step, or null
+    T *W;                   // [2][G][NLINE] energy-scanned psi^1 of this generation, summed over the two
+                            // states of each half-step (0: close, 1: open), or null
     const T *rho_c;         // densities of the closing half-step layer [NPpad] (MODE_CLOSE bit)
     const T *rho_o;         // densities of the opening half-step layer [NPpad] (MODE_OPEN bit)
     double *dep_c;          // [NLINE] deposited energy of the closing half-step (MeV)
@@ -62,10 +64,12 @@ struct AParams {
 template <typename T>
 struct QParams {
     const T *P2T;           // [NA][NA]: P2T[a][a'] = probability a' -> a
-    const T *W;             // [3][G][NLINE]
-    T *Q;                   // [3][G][NLINE]
+    const T *W;             // [2][G][NLINE]
+    T *Q;                   // [2][G][NLINE]
+    const T *P2p;           // [Kp][Mp] zero-padded P2 (k = source node, row = destination), MFMA path
+    int Kp, Mp;
     int NA, NPB, G;
-    int s0, ns;             // states s0 .. s0+ns-1
+    int s0, ns;             // half-step sums s0 .. s0+ns-1
     long NLINE;
 };
 

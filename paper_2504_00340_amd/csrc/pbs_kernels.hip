@@ -48,17 +48,17 @@ __global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
         // rho-free operator: psi1 row [-(S-+k), S-], psi2 row [-3S+, -(S+ + 2S- + k)], coupling S+[1,3]
         const T d11 = -(sm + kp), d12 = sm, d21 = T(-3) * sp, d22 = -(sp + T(2) * sm + kp);
         const T c1 = sp, c2 = T(3) * sp;
-        T q0 = 0, q1 = 0, q2 = 0;
+        // trapezoidal sources of the two half-steps: Q^n + Q* (close), Q^n + Q* (open)
+        T qc = 0, qo = 0;
         if (hasQ) {
             const long o = (long)g * S + line;
-            if (CL) q0 = P.Q[o];
-            q1 = P.Q[QS + o];
-            if (OP) q2 = P.Q[2 * QS + o];
+            if (CL) qc = P.Q[o];
+            if (OP) qo = P.Q[QS + o];
         }
         T y1 = x1, y2 = x2;
         if (CL) {
             const T f = fin + fcl;
-            const T r1 = x1 + ac * (d11 * x1 + d12 * x2 + c1 * f + q0 + q1);
+            const T r1 = x1 + ac * (d11 * x1 + d12 * x2 + c1 * f + qc);
             const T r2 = x2 + ac * (d21 * x1 + d22 * x2 + c2 * f);
             const T m11 = T(1) - ac * d11, m12 = -ac * d12, m21 = -ac * d21, m22 = T(1) - ac * d22;
             const T inv = fast_rcp(m11 * m22 - m12 * m21);
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
         T z1 = y1, z2 = y2;
         if (OP) {
             const T f = (CL ? fcl : fin) + fop;
-            const T r1 = y1 + ao * (d11 * y1 + d12 * y2 + c1 * f + q1 + q2);
+            const T r1 = y1 + ao * (d11 * y1 + d12 * y2 + c1 * f + qo);
             const T r2 = y2 + ao * (d21 * y1 + d22 * y2 + c2 * f);
             const T m11 = T(1) - ao * d11, m12 = -ao * d12, m21 = -ao * d21, m22 = T(1) - ao * d22;
             const T inv = fast_rcp(m11 * m22 - m12 * m21);
@@ -89,22 +89,18 @@ __global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
         }
         if (hasQ) {
             const double wi = P.dInj[g];
-            if (CL) injc += wi * ((double)q0 + (double)q1);
-            if (OP) injo += wi * ((double)q1 + (double)q2);
+            if (CL) injc += wi * (double)qc;
+            if (OP) injo += wi * (double)qo;
         }
         if (hasW) {
+            // energy scans of the three states; the next generation needs the sums 0+1 and 1+2
             const T w = P.wc[g], dec = P.wdec[g], idE = P.invdE[g];
             const long o = (long)g * S + line;
-            if (CL) {
-                U0 = w * x1 + dec * U0;
-                P.W[o] = U0 * idE;
-            }
+            if (CL) U0 = w * x1 + dec * U0;
             U1 = w * y1 + dec * U1;
-            P.W[QS + o] = U1 * idE;
-            if (OP) {
-                U2 = w * z1 + dec * U2;
-                P.W[2 * QS + o] = U2 * idE;
-            }
+            if (OP) U2 = w * z1 + dec * U2;
+            if (CL) P.W[o] = (U0 + U1) * idE;
+            if (OP) P.W[QS + o] = (U1 + U2) * idE;
         }
         fin = x1 - x2;
         fcl = y1 - y2;
@@ -448,9 +444,115 @@ __global__ __launch_bounds__(256) void qgemm_kernel(QParams<T> P)
     }
 }
 
+// FP32 MFMA version (v_mfma_f32_32x32x2_f32).  Block tile 128 destination nodes x 128 columns
+// (4 lateral tiles of one (half-step, group) panel); 4 waves in 2 x 2, each 64 x 64 = 2 x 2
+// MFMA tiles.  A is the zero-padded P2 [Kp][Mp] (source-major), staged k-major in LDS like B.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(256) void qgemm_mfma_f32_kernel(QParams<float> P, int nmt, int nnt, long nlogical,
+                                                             long per_xcd)
+{
+    // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a contiguous range of
+    // logical tiles so the M tiles that share one B panel run back to back on the same L2.
+    const long bid = blockIdx.x;
+    const long logical = (bid & 7) * per_xcd + (bid >> 3);
+    if (logical >= nlogical) return;
+    const int mt = (int)(logical % nmt);
+    const long rest = logical / nmt;
+    const int nt = (int)(rest % nnt);
+    const long batch = rest / nnt;
+    const int s = P.s0 + (int)(batch / P.G), g = (int)(batch % P.G);
+    const long off = ((long)s * P.G + g) * P.NLINE;
+    const float *__restrict__ B = P.W + off;
+    float *__restrict__ C = P.Q + off;
+    const long NAPT = (long)P.NA * PBS_PT;
+    __shared__ float As[16][132];
+    __shared__ float Bs[16][132];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid >> 1, wn = wid & 1;
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    const int nk = P.Kp / 16;
+    float4 ra[2], rb[2];
+    auto gload = [&](int kt) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int idx = tid + 256 * i;
+            const int k = idx >> 5, q4 = idx & 31;
+            ra[i] = *reinterpret_cast<const float4 *>(P.P2p + (long)(kt * 16 + k) * P.Mp + mt * 128 + q4 * 4);
+            const int pb = nt * 4 + (q4 >> 3), pt = (q4 & 7) * 4;
+            const int gk = kt * 16 + k;
+            if (gk < P.NA && pb < P.NPB)
+                rb[i] = *reinterpret_cast<const float4 *>(B + pb * NAPT + (long)gk * PBS_PT + pt);
+            else
+                rb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int idx = tid + 256 * i;
+            const int k = idx >> 5, q4 = idx & 31;
+            *reinterpret_cast<float4 *>(&As[k][q4 * 4]) = ra[i];
+            *reinterpret_cast<float4 *>(&Bs[k][q4 * 4]) = rb[i];
+        }
+    };
+    gload(0);
+    sstore();
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) gload(kt + 1);
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            const int kr = 2 * kk + (lane >> 5);
+            float a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = As[kr][wm * 64 + i * 32 + (lane & 31)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn * 64 + j * 32 + (lane & 31)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            sstore();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int pb = nt * 4 + wn * 2 + j;
+            if (pb >= P.NPB) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = mt * 128 + wm * 64 + i * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+                if (row < P.NA) C[pb * NAPT + (long)row * PBS_PT + (lane & 31)] = acc[i][j][r];
+            }
+        }
+}
+
 template <typename T>
 hipError_t launch_qgemm(const QParams<T> &P, hipStream_t st)
 {
+    if constexpr (sizeof(T) == 4) {
+        if (P.P2p != nullptr) {
+            const int nmt = P.Mp / 128, nnt = (P.NPB + 3) / 4;
+            const long nlog = (long)P.ns * P.G * nnt * nmt;
+            const long per = (nlog + 7) / 8;
+            hipLaunchKernelGGL(qgemm_mfma_f32_kernel, dim3((unsigned)(per * 8)), dim3(256), 0, st, P, nmt, nnt, nlog,
+                               per);
+            return hipGetLastError();
+        }
+    }
     dim3 grid((unsigned)((long)P.ns * P.G * P.NPB), (unsigned)((P.NA + 63) / 64));
     hipLaunchKernelGGL((qgemm_kernel<T>), grid, dim3(256), 0, st, P);
     return hipGetLastError();

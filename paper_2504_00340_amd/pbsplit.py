@@ -21,8 +21,9 @@ _NAMES = {0: "PBS_OK", -1: "PBS_EINVAL", -2: "PBS_ESTATE", -3: "PBS_ENOMEM", -4:
           -5: "PBS_EUNSUPPORTED"}
 
 EXPORTS = ["pbs_create", "pbs_workspace_bytes", "pbs_bind", "pbs_set_phantom", "pbs_set_beam", "pbs_step_depth",
-           "pbs_run_beam", "pbs_get_dose", "pbs_get_state", "pbs_set_state", "pbs_apply", "pbs_last_error",
-           "pbs_destroy"]
+           "pbs_run_beam", "pbs_get_dose", "pbs_get_state", "pbs_set_state", "pbs_apply", "pbs_profile",
+           "pbs_profile_read", "pbs_last_error", "pbs_destroy"]
+KINDS = ["epass", "tpass", "apass", "qgemm", "dose"]
 
 
 class Grid(C.Structure):
@@ -71,6 +72,8 @@ def lib():
         L.pbs_get_state.argtypes = [vp, D, sz]
         L.pbs_set_state.argtypes = [vp, D, sz]
         L.pbs_apply.argtypes = [vp, C.c_int, C.c_int, C.c_double]
+        L.pbs_profile.argtypes = [vp, C.c_int]
+        L.pbs_profile_read.argtypes = [vp, D, C.POINTER(C.c_long), C.c_int]
         L.pbs_last_error.argtypes = [vp]
         L.pbs_last_error.restype = C.c_char_p
         L.pbs_destroy.argtypes = [vp]
@@ -157,6 +160,16 @@ class Solver:
 
     def apply(self, op: int, layer: int, h: float):
         self._check(self.L.pbs_apply(self.ctx, int(op), int(layer), float(h)))
+
+    def profile(self, enable: bool):
+        self._check(self.L.pbs_profile(self.ctx, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        n = len(KINDS)
+        ms = (C.c_double * n)()
+        cnt = (C.c_long * n)()
+        self._check(self.L.pbs_profile_read(self.ctx, ms, cnt, n))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KINDS)}
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -29,7 +29,10 @@ def _rel(a, b):
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
 RAGGED = [dict(nx=6, ny=5, nth=6, ng=7, ngen=3, seed=1),
           dict(nx=9, ny=70, nth=8, ng=5, ngen=2, seed=2),
-          dict(nx=33, ny=31, nth=4, ng=9, ngen=1, seed=3)]
+          dict(nx=33, ny=31, nth=4, ng=9, ngen=1, seed=3),
+          # source product on the MFMA path (>= 128 angular unknowns), partial lateral tiles
+          dict(nx=5, ny=7, nth=16, ng=4, ngen=3, seed=4),
+          dict(nx=4, ny=9, nth=32, ng=3, ngen=2, seed=5)]
 
 
 @pytest.fixture(scope="module")
@@ -103,6 +106,19 @@ def test_ragged_march_fp64(O):
     s.run()
     assert _rel(s.dose(), dref) < 1e-12
     assert _rel(s.state(), fref) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_march_with_mfma_source_product(O, prec, tol):
+    c = I.small(nx=6, ny=7, nth=16, ng=10, nz=5, ngen=3, e0=32.0, e_hi=40.0, depth=1.2, seed=6)
+    o = O.Oracle(c["grid"], c["phys"])
+    dref, fref = o.run(c["beam"], c["rho"])
+    s = _solver(c, prec)
+    s.run()
+    print(prec, _rel(s.dose(), dref), _rel(s.state(), fref), flush=True)
+    assert _rel(s.dose(), dref) < tol
+    assert _rel(s.state(), fref) < 10 * tol
     s.close()
 
 
