@@ -33,16 +33,16 @@ def algorithmic(grid, tsz=4):
     NA, NP = (nth - 1) ** 2, nx * ny
     lines = NA * NP
     # energy pass (fused pair): psi1, psi2 read + write (4 values per group and line), per line
-    # two densities and two FP64 deposits; generation k>0 also reads 3 source values, k<K writes 3
+    # two densities and two FP64 deposits; generation k>0 also reads the 2 source sums, k<K writes 2
     ep = []
     for k in range(K1):
-        per = 4 * tsz + (3 * tsz if k > 0 else 0) + (3 * tsz if k + 1 < K1 else 0)
+        per = 4 * tsz + (2 * tsz if k > 0 else 0) + (2 * tsz if k + 1 < K1 else 0)
         ep.append(G * lines * per + lines * (2 * 8 + 2 * tsz))
     ep_bytes = sum(ep) / K1
     tp_bytes = K1 * G * 2 * lines * 2 * tsz          # every plane read and written once
     ap_bytes = K1 * G * 2 * lines * 2 * tsz + NP * tsz
-    qg_flops = 2.0 * NA * NA * 3 * G * NP            # one source product (3 states) per generation
-    qg_bytes = 3 * G * lines * 2 * tsz + NA * NA * tsz
+    qg_flops = 2.0 * NA * NA * 2 * G * NP            # one source product (2 half-step sums) per generation
+    qg_bytes = 2 * G * lines * 2 * tsz + NA * NA * tsz
     return dict(epass=("bytes", ep_bytes), tpass=("bytes", tp_bytes), apass=("bytes", ap_bytes),
                 qgemm=("flops", qg_flops, qg_bytes))
 
@@ -123,8 +123,10 @@ def main():
                 "algorithmic_bytes_per_launch": alg[dom][1], "avg_launch_ms": avg_s * 1e3}
     else:
         achieved = alg[dom][1] / avg_s / 1e12
-        peak = FP32_VALU_TFLOPS
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+        mfma = args.precision == "fp32" and (g["nth"] - 1) ** 2 >= 128
+        peak = FP32_MFMA_TFLOPS if mfma else FP32_VALU_TFLOPS
+        roof = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak,
                 "traffic": None, "kernel": dom, "algorithmic_flops_per_launch": alg[dom][1],
                 "avg_launch_ms": avg_s * 1e3}
     out = {

@@ -43,7 +43,7 @@ struct pbs_ctx {
     size_t o_psi = 0, o_W = 0, o_Q = 0, o_dep = 0, o_edep = 0, o_dout = 0, o_rhoT = 0, o_rhoD = 0, o_tabT = 0,
            o_tabD = 0, total = 0;
     // table offsets (elements) inside the T and double table blocks
-    size_t t_Sm, t_Sp, t_kap, t_wc, t_wdec, t_invdE, t_sig, t_theta, t_S, t_lam, t_P2T, t_P2p, t_count;
+    size_t t_Sm, t_Sp, t_kap, t_wc, t_wdec, t_invdE, t_sig, t_theta, t_S, t_lam, t_P2T, t_P2p, t_K32, t_count;
     int Kp = 0, Mp = 0;           // padded source product (MFMA path, FP32 with NA >= 128)
     size_t d_A, d_B, d_Inj, d_E1, d_E2, d_lat, d_count;
     int state = ST_CREATED;
@@ -233,6 +233,7 @@ void layout(pbs_ctx *c)
     c->t_lam = e; e += c->m;
     c->t_P2T = e; e += (size_t)c->NA * c->NA;
     c->t_P2p = e; e += (size_t)c->Kp * c->Mp;
+    c->t_K32 = e; e += 1024;
     c->t_count = e;
     c->o_tabT = o;
     o = align256(o + e * T);
@@ -271,6 +272,20 @@ pbs_status upload_tables(pbs_ctx *c)
     for (int k = 0; k < c->Kp; ++k)
         for (int a = 0; a < c->Mp; ++a)
             t[c->t_P2p + (size_t)k * c->Mp + a] = (k < c->NA && a < c->NA) ? (T)c->P2T[(size_t)a * c->NA + k] : T(0);
+    // MFMA operand constants of the 31-point sine transform split by mode parity (nth = 32):
+    // [(mat*4 + s)*64 + lane] = A_mat[lane % 16][4 s + lane / 16]
+    if (c->g.nth == 32) {
+        auto sodd = [](int r, int i) { return std::sin(M_PI * (2 * r + 1) * (i + 1) / 32.0); };
+        auto seven = [](int r, int i) { return (r < 15 && i < 15) ? std::sin(M_PI * 2 * (r + 1) * (i + 1) / 32.0) : 0.0; };
+        for (int s = 0; s < 4; ++s)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int row = lane % 16, k = 4 * s + lane / 16;
+                t[c->t_K32 + (0 * 4 + s) * 64 + lane] = (T)sodd(row, k);
+                t[c->t_K32 + (1 * 4 + s) * 64 + lane] = (T)seven(row, k);
+                t[c->t_K32 + (2 * 4 + s) * 64 + lane] = (T)sodd(k, row);
+                t[c->t_K32 + (3 * 4 + s) * 64 + lane] = (T)seven(k, row);
+            }
+    }
     std::vector<double> d(c->d_count, 0.0);
     std::memcpy(&d[c->d_A], c->dA.data(), c->G() * sizeof(double));
     std::memcpy(&d[c->d_B], c->dB.data(), c->G() * sizeof(double));
@@ -411,6 +426,12 @@ pbs_status angular(pbs_ctx *c, int layer, double h)
     P.NPB = c->NPB;
     P.NLINE = c->NLINE;
     ProfScope ps(c, PBS_K_APASS);
+    if constexpr (sizeof(T) == 4) {
+        if (c->g.nth == 32) {
+            HIPCHK(c, launch_apass_mfma32(P, tb + c->t_K32, (long)c->g.ngen * c->G() * 2, c->stream));
+            return PBS_OK;
+        }
+    }
     HIPCHK(c, launch_apass<T>(P, c->g.nth, (long)c->g.ngen * c->G() * 2, c->stream));
     return PBS_OK;
 }

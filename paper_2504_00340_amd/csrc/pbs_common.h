@@ -87,6 +87,8 @@ template <typename T>
 hipError_t launch_initial(T *psi0, const double *E1, const double *E2, const double *lat, long center_a, int G,
                           int NA, int NPB, int NP, hipStream_t st);
 
+hipError_t launch_apass_mfma32(const AParams<float> &P, const float *Ktab, long nstack, hipStream_t st);
+
 bool apass_supported(int nth);
 
 }  // namespace pbs

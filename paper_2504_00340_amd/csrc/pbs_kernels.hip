@@ -371,6 +371,167 @@ static hipError_t launch_apass_n(const AParams<T> &P, long nstack, hipStream_t s
     return hipGetLastError();
 }
 
+// MFMA version for nth = 32 (31 interior nodes), FP32.  Each of the four 31-point sine transforms
+// is split by mode parity into two 16 x 16 blocks (odd modes act on x_n + x_{32-n} plus the centre
+// node, even modes on x_n - x_{32-n}); the inverse uses the transposed blocks with the output
+// butterflies x_n = u + v, x_{32-n} = u - v.  Every block product is a chain of four
+// v_mfma_f32_16x16x4_f32 whose 16 columns are 16 lateral cells of one angular line.  The block's
+// 31 x 31 x 16 values stay in LDS between the transforms; each wave owns whole lines, so the
+// transforms work in place without block-wide barriers.
+//   Ktab[(mat*4 + s)*64 + lane] = A_mat[lane % 16][4 s + lane / 16] for mat = Sodd, Seven, Sodd^T, Seven^T.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(256) void apass_mfma32_kernel(AParams<float> P, const float *__restrict__ Ktab, int npb)
+{
+    constexpr int m = 31, NA = 961, PC = 16;
+    __shared__ float L[NA * PC];   // L[a*16 + c], a = i*31 + j
+    // the two 16-column halves of one lateral tile are 8 workgroups apart -> same XCD, same L2 lines
+    const int bid = blockIdx.x;
+    const int pb = (bid >> 4) * 8 + (bid & 7), half = (bid >> 3) & 1;
+    if (pb >= npb) return;
+    const int c0 = half * PC;
+    const long stack = blockIdx.y;
+    const int g = (int)((stack / 2) % P.G);
+    float *blk = P.psi + stack * P.NLINE + (long)pb * NA * PBS_PT + c0;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int r4 = lane >> 4, cc = lane & 15;
+    for (int idx = tid; idx < NA * 4; idx += 256) {
+        const int a = idx >> 2, q = idx & 3;
+        *reinterpret_cast<float4 *>(&L[a * PC + q * 4]) = *reinterpret_cast<const float4 *>(blk + (long)a * PBS_PT + q * 4);
+    }
+    float Ao[4], Ae[4], Bo[4], Be[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        Ao[s] = Ktab[(0 * 4 + s) * 64 + lane];
+        Ae[s] = Ktab[(1 * 4 + s) * 64 + lane];
+        Bo[s] = Ktab[(2 * 4 + s) * 64 + lane];
+        Be[s] = Ktab[(3 * 4 + s) * 64 + lane];
+    }
+    float lamO[4], lamE[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 4 * r4 + q;
+        lamO[q] = P.lam[2 * r];
+        lamE[q] = r < 15 ? P.lam[2 * r + 1] : 0.f;
+    }
+    const float al = 0.25f * P.h * P.sig[g] * P.rho[(long)pb * PBS_PT + c0 + cc];
+    __syncthreads();
+
+    // forward over the first angular index; line = column j
+    for (int j = wid; j < m; j += 4) {
+        floatx4 yo = {0.f, 0.f, 0.f, 0.f}, ye = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int ip = 4 * s + r4;
+            const float xa = L[(ip * m + j) * PC + cc];
+            const float xb = ip < 15 ? L[((30 - ip) * m + j) * PC + cc] : 0.f;
+            yo = mfma16(Ao[s], ip < 15 ? xa + xb : xa, yo);
+            ye = mfma16(Ae[s], xa - xb, ye);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 4 * r4 + q;
+            L[((2 * r) * m + j) * PC + cc] = yo[q];
+            if (r < 15) L[((2 * r + 1) * m + j) * PC + cc] = ye[q];
+        }
+    }
+    __syncthreads();
+    // over the second index: forward, CN factor, inverse; line = mode k of the first index
+    for (int k = wid; k < m; k += 4) {
+        floatx4 zo = {0.f, 0.f, 0.f, 0.f}, ze = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int jp = 4 * s + r4;
+            const float ya = L[(k * m + jp) * PC + cc];
+            const float yb = jp < 15 ? L[(k * m + 30 - jp) * PC + cc] : 0.f;
+            zo = mfma16(Ao[s], jp < 15 ? ya + yb : ya, zo);
+            ze = mfma16(Ae[s], ya - yb, ze);
+        }
+        const float lk = P.lam[k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 4 * r4 + q;
+            const float to = al * (lk + lamO[q]);
+            zo[q] = zo[q] * (1.f + to) * __builtin_amdgcn_rcpf(1.f - to);
+            const float te = al * (lk + lamE[q]);
+            ze[q] = r < 15 ? ze[q] * (1.f + te) * __builtin_amdgcn_rcpf(1.f - te) : 0.f;
+        }
+        // modes back through LDS into the operand layout (same wave, same line: in-order LDS)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 4 * r4 + q;
+            L[(k * m + 2 * r) * PC + cc] = zo[q];
+            if (r < 15) L[(k * m + 2 * r + 1) * PC + cc] = ze[q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        floatx4 u = {0.f, 0.f, 0.f, 0.f}, v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int r = 4 * s + r4;
+            const float bo = L[(k * m + 2 * r) * PC + cc];
+            const float be = r < 15 ? L[(k * m + 2 * r + 1) * PC + cc] : 0.f;
+            u = mfma16(Bo[s], bo, u);
+            v = mfma16(Be[s], be, v);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int jp = 4 * r4 + q;
+            if (jp < 15) {
+                L[(k * m + jp) * PC + cc] = u[q] + v[q];
+                L[(k * m + 30 - jp) * PC + cc] = u[q] - v[q];
+            } else {
+                L[(k * m + 15) * PC + cc] = u[q];
+            }
+        }
+    }
+    __syncthreads();
+    // inverse over the first index, with the (2/N)^2 normalisation
+    constexpr float sc = (2.f / 32.f) * (2.f / 32.f);
+    for (int j = wid; j < m; j += 4) {
+        floatx4 u = {0.f, 0.f, 0.f, 0.f}, v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int r = 4 * s + r4;
+            const float bo = L[((2 * r) * m + j) * PC + cc];
+            const float be = r < 15 ? L[((2 * r + 1) * m + j) * PC + cc] : 0.f;
+            u = mfma16(Bo[s], bo, u);
+            v = mfma16(Be[s], be, v);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ip = 4 * r4 + q;
+            if (ip < 15) {
+                L[(ip * m + j) * PC + cc] = (u[q] + v[q]) * sc;
+                L[((30 - ip) * m + j) * PC + cc] = (u[q] - v[q]) * sc;
+            } else {
+                L[(15 * m + j) * PC + cc] = u[q] * sc;
+            }
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NA * 4; idx += 256) {
+        const int a = idx >> 2, q = idx & 3;
+        *reinterpret_cast<float4 *>(blk + (long)a * PBS_PT + q * 4) = *reinterpret_cast<const float4 *>(&L[a * PC + q * 4]);
+    }
+}
+
+hipError_t launch_apass_mfma32(const AParams<float> &P, const float *Ktab, long nstack, hipStream_t st)
+{
+    const int nb = (P.NPB + 7) / 8 * 16;
+    hipLaunchKernelGGL(apass_mfma32_kernel, dim3(nb, (unsigned)nstack), dim3(256), 0, st, P, Ktab, P.NPB);
+    return hipGetLastError();
+}
+
 bool apass_supported(int nth)
 {
     switch (nth) {
@@ -575,23 +736,33 @@ hipError_t launch_fill(T *p, T v, long n, hipStream_t st)
     return hipGetLastError();
 }
 
-// edep[pq] += sum over generations and angles of dep[k][line(pq, a)], fixed order.
-__global__ void dose_reduce_kernel(double *edep, const double *dep, int ngen, int NA, long NLINE, int NP)
+// edep[pq] += sum over generations and angles of dep[k][line(pq, a)], fixed order: one block per
+// lateral tile, 32 lanes per cell x 32 angle slices, then a fixed-order tree over the slices.
+__global__ __launch_bounds__(1024) void dose_reduce_kernel(double *edep, const double *dep, int ngen, int NA,
+                                                           long NLINE, int NP)
 {
-    const int pq = blockIdx.x * 256 + threadIdx.x;
-    if (pq >= NP) return;
-    const long base = (long)(pq / PBS_PT) * NA * PBS_PT + (pq % PBS_PT);
+    __shared__ double part[32][33];
+    const int pt = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const int pb = blockIdx.x;
+    const long base = (long)pb * NA * PBS_PT + pt;
     double s = 0.0;
     for (int k = 0; k < ngen; ++k)
-        for (int a = 0; a < NA; ++a) s += dep[(long)k * NLINE + base + (long)a * PBS_PT];
-    edep[pq] += s;
+        for (int a = sl; a < NA; a += 32) s += dep[(long)k * NLINE + base + (long)a * PBS_PT];
+    part[sl][pt] = s;
+    __syncthreads();
+    for (int w = 16; w > 0; w >>= 1) {
+        if (sl < w) part[sl][pt] += part[sl + w][pt];
+        __syncthreads();
+    }
+    const int pq = pb * PBS_PT + pt;
+    if (sl == 0 && pq < NP) edep[pq] += part[0][pt];
 }
 
 hipError_t launch_dose_reduce(double *edep_layer, const double *dep, int ngen, int NA, long NLINE, int NP,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL(dose_reduce_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, edep_layer, dep, ngen, NA,
-                       NLINE, NP);
+    const int npb = (NP + PBS_PT - 1) / PBS_PT;
+    hipLaunchKernelGGL(dose_reduce_kernel, dim3(npb), dim3(1024), 0, st, edep_layer, dep, ngen, NA, NLINE, NP);
     return hipGetLastError();
 }
 
