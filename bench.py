@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_TFLOPS = 78.6     # 256 CU x 2.4 GHz x 64 lanes x 2 flop (packed FP32 not used)
 FP32_MFMA_TFLOPS = 157.3
+BF16_MFMA_TFLOPS = 2500.0   # dense
 
 
 def algorithmic(grid, tsz=4):
@@ -74,6 +75,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--case", default="water", choices=["water", "bone", "lung"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--source", default="bf16x3", choices=["bf16x3", "fp32"],
+                    help="arithmetic of the angular source product (FP32 contexts)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -93,6 +96,11 @@ def main():
     print(f"bench: {cfg['name']} {args.precision}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
           flush=True)
     s = Solver(g, cfg["phys"], precision=args.precision, device="cuda:0")
+    split = args.precision == "fp32" and args.source == "bf16x3"
+    if args.precision == "fp32":
+        from paper_2504_00340_amd.pbsplit import PBS_SRC_BF16X3, PBS_SRC_FP32
+
+        s.set_source_precision(PBS_SRC_BF16X3 if split else PBS_SRC_FP32)
     s.set_phantom(cfg["rho"])
     s.set_beam(cfg["beam"])
     s.step(args.warmup)
@@ -122,11 +130,16 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
                 "algorithmic_bytes_per_launch": alg[dom][1], "avg_launch_ms": avg_s * 1e3}
     else:
-        achieved = alg[dom][1] / avg_s / 1e12
         mfma = args.precision == "fp32" and (g["nth"] - 1) ** 2 >= 128
-        peak = FP32_MFMA_TFLOPS if mfma else FP32_VALU_TFLOPS
+        if split:
+            # executed BF16 MFMA work: three bf16 products per FP32 multiply-add
+            achieved = 3.0 * alg[dom][1] / avg_s / 1e12
+            peak = BF16_MFMA_TFLOPS
+        else:
+            achieved = alg[dom][1] / avg_s / 1e12
+            peak = FP32_MFMA_TFLOPS if mfma else FP32_VALU_TFLOPS
         roof = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak,
+                "frac": achieved / peak, "dtype": "bf16x3" if split else args.precision,
                 "traffic": None, "kernel": dom, "algorithmic_flops_per_launch": alg[dom][1],
                 "avg_launch_ms": avg_s * 1e3}
     out = {
@@ -143,7 +156,8 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{cfg['name']}: 64x64 lateral x 32x32 angles x 128 groups x 4 generations, "
-                               f"300 depth steps", "steps_per_beam": g["nz"], "precision": args.precision},
+                               f"300 depth steps", "steps_per_beam": g["nz"], "precision": args.precision,
+                   "source_product": "bf16x3" if split else args.precision},
         "interior_cell_updates_per_s": interior / dt,
         "beams_per_s": 1.0 / (dt * g["nz"]),
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},

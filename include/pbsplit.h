@@ -150,6 +150,16 @@ pbs_status pbs_set_state(pbs_ctx *ctx, const double *in, size_t n);
 enum { PBS_OP_E = 1, PBS_OP_T = 2, PBS_OP_A = 3 };
 pbs_status pbs_apply(pbs_ctx *ctx, int op, int layer, double h);
 
+/* Arithmetic of the angular part of the catastrophic source (the product of the nuclear angular
+ * transfer matrix with the energy-scanned fluence, App. A.4) in an FP32 context with at least 128
+ * angular unknowns:
+ *   PBS_SRC_FP32    FP32 MFMA
+ *   PBS_SRC_BF16X3  both operands split as hi + lo bfloat16, three BF16 MFMA products accumulated
+ *                   in FP32 (relative error of each term <= ~2^-15); the default
+ * Other contexts always use their own precision; PBS_SRC_BF16X3 there returns PBS_EUNSUPPORTED. */
+enum { PBS_SRC_FP32 = 0, PBS_SRC_BF16X3 = 1 };
+pbs_status pbs_set_source_precision(pbs_ctx *ctx, int mode);
+
 /* Diagnostics: kernel timing.  pbs_profile(ctx, 1) starts recording a HIP event pair on the
  * bound stream around every kernel launch, grouped by kind; pbs_profile(ctx, 0) stops and
  * clears.  pbs_profile_read synchronises the stream and returns, for kind = 0..n-1 (at most

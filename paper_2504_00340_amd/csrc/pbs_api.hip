@@ -1,5 +1,6 @@
 // libpbsplit host side: context, FP64 tables, workspace carving, the depth march schedule and
 // the C ABI declared in include/pbsplit.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -45,6 +46,11 @@ struct pbs_ctx {
     // table offsets (elements) inside the T and double table blocks
     size_t t_Sm, t_Sp, t_kap, t_wc, t_wdec, t_invdE, t_sig, t_theta, t_S, t_lam, t_P2T, t_P2p, t_K32, t_count;
     int Kp = 0, Mp = 0;           // padded source product (MFMA path, FP32 with NA >= 128)
+    int Kpb = 0;                  // k padding of the split-BF16 operand tables
+    int NOCT = 0;                 // source-node octets of the split-BF16 W layout
+    size_t Wb_half = 0;           // elements of one of the hi / lo arrays
+    int src_mode = PBS_SRC_FP32;
+    size_t o_bf = 0;
     size_t d_A, d_B, d_Inj, d_E1, d_E2, d_lat, d_count;
     int state = ST_CREATED;
     int step = 0;
@@ -205,7 +211,10 @@ void layout(pbs_ctx *c)
     c->o_W = c->o_Q = o;
     if (K1 > 1) {
         c->o_W = o;
-        o = align256(o + (size_t)2 * G * c->NLINE * T);
+        const size_t wf = (size_t)2 * G * c->NLINE * T;
+        const size_t wb = (size_t)2 * 2 * G * c->NPB * c->NOCT * PBS_PT * 8 * sizeof(unsigned short);
+        c->Wb_half = (size_t)2 * G * c->NPB * c->NOCT * PBS_PT * 8;
+        o = align256(o + std::max(wf, c->Kpb > 0 ? wb : (size_t)0));
         c->o_Q = o;
         o = align256(o + (size_t)2 * G * c->NLINE * T);
     }
@@ -247,6 +256,8 @@ void layout(pbs_ctx *c)
     c->d_count = d;
     c->o_tabD = o;
     o = align256(o + d * sizeof(double));
+    c->o_bf = o;
+    if (c->Kpb > 0) o = align256(o + (size_t)2 * c->Mp * c->Kpb * sizeof(unsigned short));
     c->total = o;
 }
 
@@ -290,6 +301,33 @@ pbs_status upload_tables(pbs_ctx *c)
     std::memcpy(&d[c->d_A], c->dA.data(), c->G() * sizeof(double));
     std::memcpy(&d[c->d_B], c->dB.data(), c->G() * sizeof(double));
     std::memcpy(&d[c->d_Inj], c->dInj.data(), c->G() * sizeof(double));
+    std::vector<unsigned short> bf;
+    if (c->Kpb > 0) {
+        // P2 as hi + lo bfloat16 (round to nearest even), row-major [Mp][Kpb]: row = destination
+        auto rne = [](float x) {
+            uint32_t u;
+            std::memcpy(&u, &x, 4);
+            u += 0x7FFFu + ((u >> 16) & 1u);
+            return (unsigned short)(u >> 16);
+        };
+        auto tof = [](unsigned short h) {
+            uint32_t u = (uint32_t)h << 16;
+            float f;
+            std::memcpy(&f, &u, 4);
+            return f;
+        };
+        bf.assign((size_t)2 * c->Mp * c->Kpb, 0);
+        for (int a = 0; a < c->NA; ++a)
+            for (int k = 0; k < c->NA; ++k) {
+                const double x = c->P2T[(size_t)a * c->NA + k];
+                const unsigned short hi = rne((float)x);
+                const unsigned short lo = rne((float)(x - (double)tof(hi)));
+                bf[(size_t)a * c->Kpb + k] = hi;
+                bf[(size_t)c->Mp * c->Kpb + (size_t)a * c->Kpb + k] = lo;
+            }
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->o_bf, bf.data(), bf.size() * sizeof(unsigned short), hipMemcpyHostToDevice,
+                                 c->stream));
+    }
     HIPCHK(c, hipMemcpyAsync(c->tabT<T>(), t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->tabD(), d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -331,6 +369,12 @@ EParams<T> eparams(pbs_ctx *c, int k, int lay_c, int lay_o, double h)
     P.psi = c->psi<T>(k);
     P.Q = (k > 0) ? c->Q<T>() : nullptr;
     P.W = (k + 1 < c->g.ngen) ? c->W<T>() : nullptr;
+    P.Wh = P.Wl = nullptr;
+    P.NOCT = c->NOCT;
+    if (P.W && c->Kpb > 0 && c->src_mode == PBS_SRC_BF16X3) {
+        P.Wh = reinterpret_cast<unsigned short *>(c->ws + c->o_W);
+        P.Wl = P.Wh + c->Wb_half;
+    }
     P.rho_c = lay_c >= 0 ? c->rhoT<T>(lay_c) : nullptr;
     P.rho_o = lay_o >= 0 ? c->rhoT<T>(lay_o) : nullptr;
     P.dep_c = c->dep(0, k);
@@ -377,9 +421,19 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
             Q.P2p = c->Kp > 0 ? c->tabT<T>() + c->t_P2p : nullptr;
             Q.Kp = c->Kp;
             Q.Mp = c->Mp;
+            Q.NOCT = c->NOCT;
+            Q.Bh = reinterpret_cast<const unsigned short *>(c->ws + c->o_W);
+            Q.Bl = Q.Bh + c->Wb_half;
             Q.s0 = (mode == MODE_OPEN) ? 1 : 0;
             Q.ns = (mode == MODE_PAIR) ? 2 : 1;
             ProfScope ps(c, PBS_K_QGEMM);
+            if constexpr (sizeof(T) == 4) {
+                if (c->Kpb > 0 && c->src_mode == PBS_SRC_BF16X3) {
+                    const unsigned short *ah = reinterpret_cast<const unsigned short *>(c->ws + c->o_bf);
+                    HIPCHK(c, launch_qgemm_bf16x3(Q, ah, ah + (size_t)c->Mp * c->Kpb, c->Kpb, c->stream));
+                    continue;
+                }
+            }
             HIPCHK(c, launch_qgemm<T>(Q, c->stream));
         }
     }
@@ -474,6 +528,11 @@ pbs_status start_beam(pbs_ctx *c, const pbs_beam &b)
     const pbs_grid &g = c->g;
     HIPCHK(c, launch_fill<T>(c->psi<T>(0), T(0), (long)g.ngen * c->G() * 2 * c->NLINE, c->stream));
     HIPCHK(c, launch_fill<double>(c->edep(0), 0.0, (long)g.nz * c->NP, c->stream));
+    if (g.ngen > 1) {
+        // padding source nodes of the split layout are never written and must stay zero
+        const size_t wbytes = c->o_Q - c->o_W;
+        HIPCHK(c, launch_fill<float>(reinterpret_cast<float *>(c->ws + c->o_W), 0.f, (long)(wbytes / 4), c->stream));
+    }
     // initial condition: eq:(bdy) projected (lateral cell averages, DG-P1 energy moments, theta = 0 node)
     auto ncdf = [](double x) { return 0.5 * std::erfc(-x / std::sqrt(2.0)); };
     auto npdf = [](double x) { return std::exp(-0.5 * x * x) / std::sqrt(2.0 * M_PI); };
@@ -609,9 +668,12 @@ pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precisi
     c->dx = 2.0 * g.x_half / g.nx;
     c->dy = 2.0 * g.y_half / g.ny;
     c->dth = 2.0 * g.th_half / g.nth;
+    c->NOCT = (c->NA + 7) / 8;
     if (precision == PBS_FP32 && c->NA >= 128) {
         c->Kp = (c->NA + 15) / 16 * 16;
         c->Mp = (c->NA + 127) / 128 * 128;
+        c->Kpb = (c->NA + 31) / 32 * 32;
+        c->src_mode = PBS_SRC_BF16X3;
     }
     try {
         build_tables(c);
@@ -745,6 +807,16 @@ pbs_status pbs_apply(pbs_ctx *c, int op, int layer, double h)
     case PBS_OP_A: return DISPATCH(c, angular, c, layer, h);
     default: return fail(c, PBS_EINVAL, "unknown op");
     }
+}
+
+pbs_status pbs_set_source_precision(pbs_ctx *c, int mode)
+{
+    if (!c) return PBS_EINVAL;
+    if (mode != PBS_SRC_FP32 && mode != PBS_SRC_BF16X3) return fail(c, PBS_EINVAL, "unknown source precision");
+    if (mode == PBS_SRC_BF16X3 && c->Kpb == 0)
+        return fail(c, PBS_EUNSUPPORTED, "split-BF16 source product needs an FP32 context with >= 128 angular unknowns");
+    c->src_mode = mode;
+    return PBS_OK;
 }
 
 pbs_status pbs_profile(pbs_ctx *c, int enable)

@@ -25,6 +25,8 @@ struct EParams {
                             // and opening (1) half-step, or null
     T *W;                   // [2][G][NLINE] energy-scanned psi^1 of this generation, summed over the two
                             // states of each half-step (0: close, 1: open), or null
+    unsigned short *Wh, *Wl;   // split-BF16 form of W (hi, lo): [2][G][NPB][NOCT][PT][8], a' = 8*oct + e
+    int NOCT;                  // ceil(NA / 8)
     const T *rho_c;         // densities of the closing half-step layer [NPpad] (MODE_CLOSE bit)
     const T *rho_o;         // densities of the opening half-step layer [NPpad] (MODE_OPEN bit)
     double *dep_c;          // [NLINE] deposited energy of the closing half-step (MeV)
@@ -68,6 +70,8 @@ struct QParams {
     T *Q;                   // [2][G][NLINE]
     const T *P2p;           // [Kp][Mp] zero-padded P2 (k = source node, row = destination), MFMA path
     int Kp, Mp;
+    const unsigned short *Bh, *Bl;   // split-BF16 W (see EParams), split-BF16 path
+    int NOCT;
     int NA, NPB, G;
     int s0, ns;             // half-step sums s0 .. s0+ns-1
     long NLINE;
@@ -87,6 +91,8 @@ template <typename T>
 hipError_t launch_initial(T *psi0, const double *E1, const double *E2, const double *lat, long center_a, int G,
                           int NA, int NPB, int NP, hipStream_t st);
 
+hipError_t launch_qgemm_bf16x3(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
+                               hipStream_t st);
 hipError_t launch_apass_mfma32(const AParams<float> &P, const float *Ktab, long nstack, hipStream_t st);
 
 bool apass_supported(int nth);

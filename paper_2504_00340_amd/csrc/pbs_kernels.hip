@@ -18,17 +18,28 @@
 
 namespace pbs {
 
+typedef unsigned short u16x8v __attribute__((ext_vector_type(8)));
+
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
 // ------------------------------------------------------------------------------- energy pass
-template <typename T, int MODE>
+// Block = one lateral tile pb and one octet of angular lines a = 8*oct + e (e = tid/32), 32 cells
+// pt = tid%32: the split-BF16 scans of the 8 lines of a cell are gathered in LDS and written as one
+// 16-byte chunk (one LDS buffer per group parity, one barrier per group).
+template <typename T, int MODE, bool SPLIT>
 __global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
 {
     constexpr bool CL = (MODE & MODE_CLOSE) != 0;
     constexpr bool OP = (MODE & MODE_OPEN) != 0;
-    const long line = (long)blockIdx.x * 256 + threadIdx.x;
-    if (line >= P.NLINE) return;
+    const int NA = (int)(P.NAPT / PBS_PT);
+    const int pbk = blockIdx.x / P.NOCT, oct = blockIdx.x % P.NOCT;
+    const int e = threadIdx.x >> 5, ptc = threadIdx.x & 31;
+    const int a = oct * 8 + e;
+    const bool valid = a < NA;
+    if (!SPLIT && !valid) return;
+    const long line = ((long)pbk * NA + (valid ? a : 0)) * PBS_PT + ptc;
+    __shared__ unsigned short wsh[2][4][PBS_PT * 8];   // [group parity][hi c, lo c, hi o, lo o][pt*8 + e]
     const long pq = (line / P.NAPT) * PBS_PT + (line % PBS_PT);
     const long S = P.NLINE;
     const long QS = (long)P.G * S;
@@ -39,18 +50,18 @@ __global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
     T fin = 0, fcl = 0, fop = 0;    // psi1 - psi2 of group g+1: input, after close, after open
     T U0 = 0, U1 = 0, U2 = 0;       // re-emission energy scans of states 0, 1, 2
     double ph0 = 0, ph1 = 0, ph2 = 0, injc = 0, injo = 0;
-    const bool hasQ = P.Q != nullptr, hasW = P.W != nullptr;
+    const bool hasQ = P.Q != nullptr, hasW = SPLIT ? P.Wh != nullptr : P.W != nullptr;
     for (int g = P.G - 1; g >= 0; --g) {
         T *p1 = P.psi + (2L * g) * S + line;
         T *p2 = p1 + S;
-        const T x1 = *p1, x2 = *p2;
+        const T x1 = valid ? *p1 : T(0), x2 = valid ? *p2 : T(0);
         const T sm = P.Sm[g], sp = P.Sp[g], kp = P.kap[g];
         // rho-free operator: psi1 row [-(S-+k), S-], psi2 row [-3S+, -(S+ + 2S- + k)], coupling S+[1,3]
         const T d11 = -(sm + kp), d12 = sm, d21 = T(-3) * sp, d22 = -(sp + T(2) * sm + kp);
         const T c1 = sp, c2 = T(3) * sp;
         // trapezoidal sources of the two half-steps: Q^n + Q* (close), Q^n + Q* (open)
         T qc = 0, qo = 0;
-        if (hasQ) {
+        if (hasQ && valid) {
             const long o = (long)g * S + line;
             if (CL) qc = P.Q[o];
             if (OP) qo = P.Q[QS + o];
@@ -75,8 +86,10 @@ __global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
             z1 = (r1 * m22 - m12 * r2) * inv;
             z2 = (m11 * r2 - m21 * r1) * inv;
         }
-        *p1 = z1;
-        *p2 = z2;
+        if (valid) {
+            *p1 = z1;
+            *p2 = z2;
+        }
         // deposit functional (FP64): stopping + removal of every state, bottom-face outflow
         const double A = P.dA[g], B = P.dB[g];
         if (CL) ph0 += A * (double)x1 + B * (double)x2;
@@ -99,13 +112,39 @@ __global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
             if (CL) U0 = w * x1 + dec * U0;
             U1 = w * y1 + dec * U1;
             if (OP) U2 = w * z1 + dec * U2;
-            if (CL) P.W[o] = (U0 + U1) * idE;
-            if (OP) P.W[QS + o] = (U1 + U2) * idE;
+            if constexpr (SPLIT) {
+                // hi + lo bfloat16 pair of each sum; 8 lines of a cell -> one 16-byte chunk
+                unsigned short *buf = &wsh[g & 1][0][0];
+                const int so = ptc * 8 + e;
+                float vc = valid && CL ? (float)((U0 + U1) * idE) : 0.f;
+                float vo = valid && OP ? (float)((U1 + U2) * idE) : 0.f;
+                const __bf16 hc = (__bf16)vc, ho = (__bf16)vo;
+                buf[0 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, hc);
+                buf[1 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, (__bf16)(vc - (float)hc));
+                buf[2 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, ho);
+                buf[3 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, (__bf16)(vo - (float)ho));
+                __syncthreads();
+                const int t = threadIdx.x;
+                const int arr = t >> 5;   // 0 hi c, 1 lo c, 2 hi o, 3 lo o
+                const bool want = t < 128 && ((arr < 2) ? CL : OP);
+                if (want) {
+                    const long SB = (long)P.G * (S / P.NAPT) * P.NOCT * (PBS_PT * 8);
+                    const long ob = (((long)g * (S / P.NAPT) + pbk) * P.NOCT + oct) * (PBS_PT * 8) + (t & 31) * 8 +
+                                    (arr >= 2 ? SB : 0);
+                    unsigned short *dst = (arr & 1) ? P.Wl : P.Wh;
+                    *reinterpret_cast<u16x8v *>(dst + ob) =
+                        *reinterpret_cast<const u16x8v *>(&buf[arr * PBS_PT * 8 + (t & 31) * 8]);
+                }
+            } else {
+                if (CL) P.W[o] = (U0 + U1) * idE;
+                if (OP) P.W[QS + o] = (U1 + U2) * idE;
+            }
         }
         fin = x1 - x2;
         fcl = y1 - y2;
         fop = z1 - z2;
     }
+    if (!valid) return;
     if (CL) P.dep_c[line] = dac * (ph0 + ph1 - injc) * P.scale;
     if (OP) P.dep_o[line] = dao * (ph1 + ph2 - injo) * P.scale;
 }
@@ -113,13 +152,17 @@ __global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
 template <typename T>
 hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st)
 {
-    const unsigned nb = (unsigned)((P.NLINE + 255) / 256);
-    if (mode == MODE_PAIR)
-        hipLaunchKernelGGL((epass_kernel<T, MODE_PAIR>), dim3(nb), dim3(256), 0, st, P);
-    else if (mode == MODE_OPEN)
-        hipLaunchKernelGGL((epass_kernel<T, MODE_OPEN>), dim3(nb), dim3(256), 0, st, P);
-    else
-        hipLaunchKernelGGL((epass_kernel<T, MODE_CLOSE>), dim3(nb), dim3(256), 0, st, P);
+    const unsigned nb = (unsigned)((P.NLINE / P.NAPT) * P.NOCT);
+    const bool split = P.Wh != nullptr;
+#define PBS_EP(M, SP) hipLaunchKernelGGL((epass_kernel<T, M, SP>), dim3(nb), dim3(256), 0, st, P)
+    if (mode == MODE_PAIR) {
+        if (split) PBS_EP(MODE_PAIR, true); else PBS_EP(MODE_PAIR, false);
+    } else if (mode == MODE_OPEN) {
+        if (split) PBS_EP(MODE_OPEN, true); else PBS_EP(MODE_OPEN, false);
+    } else {
+        if (split) PBS_EP(MODE_CLOSE, true); else PBS_EP(MODE_CLOSE, false);
+    }
+#undef PBS_EP
     return hipGetLastError();
 }
 
@@ -699,6 +742,136 @@ __global__ __launch_bounds__(256) void qgemm_mfma_f32_kernel(QParams<float> P, i
                 if (row < P.NA) C[pb * NAPT + (long)row * PBS_PT + (lane & 31)] = acc[i][j][r];
             }
         }
+}
+
+// Split-BF16 version on v_mfma_f32_32x32x16_bf16: each FP32 operand is written as hi + lo
+// (hi = bf16(x), lo = bf16(x - hi), |x - hi - lo| <= 2^-16 |x|) and the product is accumulated in
+// FP32 as A_lo B_hi + A_hi B_lo + A_hi B_hi (the A_lo B_lo term, O(2^-16), is dropped).
+// Block tile 128 destination nodes x 256 columns (8 lateral tiles), BK = 32; 8 waves in 2 x 4,
+// each 64 x 64 = 2 x 2 MFMA tiles.  A = P2 split on the host, row-major [Mp][Kp] (k contiguous);
+// B arrives split from the energy pass, 8 consecutive source nodes contiguous per lateral cell.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__global__ __launch_bounds__(512) void qgemm_bf16x3_kernel(QParams<float> P, const unsigned short *__restrict__ Ahi,
+                                                           const unsigned short *__restrict__ Alo, int Kp, int nmt,
+                                                           int nnt, long nlogical, long per_xcd)
+{
+    constexpr int BK = 32, LD = BK + 8;   // LDS row stride in bf16 elements (80 B)
+    __shared__ unsigned short sAh[128 * LD], sAl[128 * LD], sBh[256 * LD], sBl[256 * LD];
+    const long bid = blockIdx.x;
+    const long logical = (bid & 7) * per_xcd + (bid >> 3);
+    if (logical >= nlogical) return;
+    const int mt = (int)(logical % nmt);
+    const long rest = logical / nmt;
+    const int nt = (int)(rest % nnt);
+    const long batch = rest / nnt;
+    const int s = P.s0 + (int)(batch / P.G), g = (int)(batch % P.G);
+    const long off = ((long)s * P.G + g) * P.NLINE;
+    float *__restrict__ C = P.Q + off;
+    const long NAPT = (long)P.NA * PBS_PT;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid >> 2, wn = wid & 3;
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    const int nk = Kp / BK;
+    // staging assignment: A chunk (row = tid/4, 8 k at 8*(tid%4)); B: column tid%256, k octets tid/256 and +2
+    const int arow = tid >> 2, akq = tid & 3;
+    const int bcol = tid & 255, boct = tid >> 8;
+    const int bpb = nt * 8 + (bcol >> 5), bpt = bcol & 31;
+    const bool bok = bpb < P.NPB;
+    const long bbase = (((long)s * P.G + g) * P.NPB + (bok ? bpb : 0)) * P.NOCT * (PBS_PT * 8) + bpt * 8;
+    u16x8 rah, ral;
+    u16x8 rbh[2], rbl[2];
+    auto gload = [&](int kt) {
+        const long ao = (long)(mt * 128 + arow) * Kp + kt * BK + akq * 8;
+        rah = *reinterpret_cast<const u16x8 *>(Ahi + ao);
+        ral = *reinterpret_cast<const u16x8 *>(Alo + ao);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int oc = kt * (BK / 8) + boct + 2 * h;
+            if (bok && oc < P.NOCT) {
+                rbh[h] = *reinterpret_cast<const u16x8 *>(P.Bh + bbase + (long)oc * (PBS_PT * 8));
+                rbl[h] = *reinterpret_cast<const u16x8 *>(P.Bl + bbase + (long)oc * (PBS_PT * 8));
+            } else {
+                rbh[h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                rbl[h] = rbh[h];
+            }
+        }
+    };
+    auto sstore = [&]() {
+        *reinterpret_cast<u16x8 *>(&sAh[arow * LD + akq * 8]) = rah;
+        *reinterpret_cast<u16x8 *>(&sAl[arow * LD + akq * 8]) = ral;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            *reinterpret_cast<u16x8 *>(&sBh[bcol * LD + (boct + 2 * h) * 8]) = rbh[h];
+            *reinterpret_cast<u16x8 *>(&sBl[bcol * LD + (boct + 2 * h) * 8]) = rbl[h];
+        }
+    };
+    gload(0);
+    sstore();
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) gload(kt + 1);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int ko = ks * 16 + 8 * (lane >> 5);
+            bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int r = wm * 64 + i * 32 + (lane & 31);
+                ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAh[r * LD + ko]));
+                al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAl[r * LD + ko]));
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int cidx = wn * 64 + j * 32 + (lane & 31);
+                bh[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sBh[cidx * LD + ko]));
+                bl[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sBl[cidx * LD + ko]));
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            sstore();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int pb = nt * 8 + wn * 2 + j;
+            if (pb >= P.NPB) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = mt * 128 + wm * 64 + i * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+                if (row < P.NA) C[pb * NAPT + (long)row * PBS_PT + (lane & 31)] = acc[i][j][r];
+            }
+        }
+}
+
+hipError_t launch_qgemm_bf16x3(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
+                               hipStream_t st)
+{
+    const int nmt = P.Mp / 128, nnt = (P.NPB + 7) / 8;
+    const long nlog = (long)P.ns * P.G * nnt * nmt;
+    const long per = (nlog + 7) / 8;
+    hipLaunchKernelGGL(qgemm_bf16x3_kernel, dim3((unsigned)(per * 8)), dim3(512), 0, st, P, Ahi, Alo, Kp, nmt, nnt,
+                       nlog, per);
+    return hipGetLastError();
 }
 
 template <typename T>

@@ -17,11 +17,13 @@ LIB_PATH = os.path.join(_HERE, "libpbsplit.so")
 PBS_OK, PBS_EINVAL, PBS_ESTATE, PBS_ENOMEM, PBS_EDEVICE, PBS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PBS_FP32, PBS_FP64 = 0, 1
 PBS_OP_E, PBS_OP_T, PBS_OP_A = 1, 2, 3
+PBS_SRC_FP32, PBS_SRC_BF16X3 = 0, 1
 _NAMES = {0: "PBS_OK", -1: "PBS_EINVAL", -2: "PBS_ESTATE", -3: "PBS_ENOMEM", -4: "PBS_EDEVICE",
           -5: "PBS_EUNSUPPORTED"}
 
 EXPORTS = ["pbs_create", "pbs_workspace_bytes", "pbs_bind", "pbs_set_phantom", "pbs_set_beam", "pbs_step_depth",
-           "pbs_run_beam", "pbs_get_dose", "pbs_get_state", "pbs_set_state", "pbs_apply", "pbs_profile",
+           "pbs_run_beam", "pbs_get_dose", "pbs_get_state", "pbs_set_state", "pbs_apply", "pbs_set_source_precision",
+           "pbs_profile",
            "pbs_profile_read", "pbs_last_error", "pbs_destroy"]
 KINDS = ["epass", "tpass", "apass", "qgemm", "dose"]
 
@@ -72,6 +74,7 @@ def lib():
         L.pbs_get_state.argtypes = [vp, D, sz]
         L.pbs_set_state.argtypes = [vp, D, sz]
         L.pbs_apply.argtypes = [vp, C.c_int, C.c_int, C.c_double]
+        L.pbs_set_source_precision.argtypes = [vp, C.c_int]
         L.pbs_profile.argtypes = [vp, C.c_int]
         L.pbs_profile_read.argtypes = [vp, D, C.POINTER(C.c_long), C.c_int]
         L.pbs_last_error.argtypes = [vp]
@@ -160,6 +163,9 @@ class Solver:
 
     def apply(self, op: int, layer: int, h: float):
         self._check(self.L.pbs_apply(self.ctx, int(op), int(layer), float(h)))
+
+    def set_source_precision(self, mode: int):
+        self._check(self.L.pbs_set_source_precision(self.ctx, int(mode)))
 
     def profile(self, enable: bool):
         self._check(self.L.pbs_profile(self.ctx, 1 if enable else 0))
