@@ -241,7 +241,9 @@ void layout(pbs_ctx *c)
     c->t_S = e; e += (size_t)c->m * c->m;
     c->t_lam = e; e += c->m;
     c->t_P2T = e; e += (size_t)c->NA * c->NA;
+    e = (e + 63) / 64 * 64;   // vector loads of the padded tables need 256-byte alignment
     c->t_P2p = e; e += (size_t)c->Kp * c->Mp;
+    e = (e + 63) / 64 * 64;
     c->t_K32 = e; e += 1024;
     c->t_count = e;
     c->o_tabT = o;
@@ -669,11 +671,13 @@ pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precisi
     c->dy = 2.0 * g.y_half / g.ny;
     c->dth = 2.0 * g.th_half / g.nth;
     c->NOCT = (c->NA + 7) / 8;
-    if (precision == PBS_FP32 && c->NA >= 128) {
+    if (c->NA >= 128) {   // source product on MFMA
         c->Kp = (c->NA + 15) / 16 * 16;
         c->Mp = (c->NA + 127) / 128 * 128;
-        c->Kpb = (c->NA + 31) / 32 * 32;
-        c->src_mode = PBS_SRC_BF16X3;
+        if (precision == PBS_FP32) {
+            c->Kpb = (c->NA + 31) / 32 * 32;
+            c->src_mode = PBS_SRC_BF16X3;
+        }
     }
     try {
         build_tables(c);

@@ -874,9 +874,111 @@ hipError_t launch_qgemm_bf16x3(const QParams<float> &P, const unsigned short *Ah
     return hipGetLastError();
 }
 
+// FP64 MFMA version (v_mfma_f64_16x16x4_f64, output row = lane/16 + 4 q, column = lane % 16).
+// Block tile 128 x 128 (4 lateral tiles), BK = 16; 4 waves in 2 x 2, each 64 x 64 = 4 x 4 MFMA tiles.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void qgemm_mfma_f64_kernel(QParams<double> P, int nmt, int nnt, long nlogical,
+                                                             long per_xcd)
+{
+    const long bid = blockIdx.x;
+    const long logical = (bid & 7) * per_xcd + (bid >> 3);
+    if (logical >= nlogical) return;
+    const int mt = (int)(logical % nmt);
+    const long rest = logical / nmt;
+    const int nt = (int)(rest % nnt);
+    const long batch = rest / nnt;
+    const int s = P.s0 + (int)(batch / P.G), g = (int)(batch % P.G);
+    const long off = ((long)s * P.G + g) * P.NLINE;
+    const double *__restrict__ B = P.W + off;
+    double *__restrict__ C = P.Q + off;
+    const long NAPT = (long)P.NA * PBS_PT;
+    __shared__ double As[16][130];
+    __shared__ double Bs[16][130];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid >> 1, wn = wid & 1;
+    doublex4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    const int nk = P.Kp / 16;
+    double2 ra[4], rb[4];
+    auto gload = [&](int kt) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = tid + 256 * i;
+            const int k = idx >> 6, q2 = idx & 63;
+            ra[i] = *reinterpret_cast<const double2 *>(P.P2p + (long)(kt * 16 + k) * P.Mp + mt * 128 + q2 * 2);
+            const int col = q2 * 2, pb = nt * 4 + (col >> 5), pt = col & 31;
+            const int gk = kt * 16 + k;
+            if (gk < P.NA && pb < P.NPB)
+                rb[i] = *reinterpret_cast<const double2 *>(B + pb * NAPT + (long)gk * PBS_PT + pt);
+            else
+                rb[i] = make_double2(0.0, 0.0);
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = tid + 256 * i;
+            const int k = idx >> 6, q2 = idx & 63;
+            *reinterpret_cast<double2 *>(&As[k][q2 * 2]) = ra[i];
+            *reinterpret_cast<double2 *>(&Bs[k][q2 * 2]) = rb[i];
+        }
+    };
+    gload(0);
+    sstore();
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) gload(kt + 1);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int kr = 4 * kk + (lane >> 4);
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kr][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kr][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            sstore();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = wn * 64 + j * 16 + (lane & 15);
+            const int pb = nt * 4 + (col >> 5), pt = col & 31;
+            if (pb >= P.NPB) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = mt * 128 + wm * 64 + i * 16 + (lane >> 4) + 4 * q;
+                if (row < P.NA) C[pb * NAPT + (long)row * PBS_PT + pt] = acc[i][j][q];
+            }
+        }
+}
+
 template <typename T>
 hipError_t launch_qgemm(const QParams<T> &P, hipStream_t st)
 {
+    if constexpr (sizeof(T) == 8) {
+        if (P.P2p != nullptr) {
+            const int nmt = P.Mp / 128, nnt = (P.NPB + 3) / 4;
+            const long nlog = (long)P.ns * P.G * nnt * nmt;
+            const long per = (nlog + 7) / 8;
+            hipLaunchKernelGGL(qgemm_mfma_f64_kernel, dim3((unsigned)(per * 8)), dim3(256), 0, st, P, nmt, nnt, nlog,
+                               per);
+            return hipGetLastError();
+        }
+    }
     if constexpr (sizeof(T) == 4) {
         if (P.P2p != nullptr) {
             const int nmt = P.Mp / 128, nnt = (P.NPB + 3) / 4;
