@@ -48,23 +48,47 @@ def algorithmic(grid, tsz=4):
                 qgemm=("flops", qg_flops, qg_bytes))
 
 
+KIND_KERNEL = {"tpass": "tpass_kernel<float, 1>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16x3_kernel",
+               "epass": "epass_kernel<float, 3, true>"}
+
+
+def measured_traffic(kind):
+    """HBM bytes per dispatch of `kind` from the committed counter summary (FETCH_SIZE/WRITE_SIZE runs of
+    this workload, scaled by the copy calibration), or None when the kernels changed since then."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_c2_water_fp32.md")
+    src = os.path.join(ROOT, "paper_2504_00340_amd", "csrc", "pbs_kernels.hip")
+    if not os.path.exists(path) or kind not in KIND_KERNEL:
+        return None
+    text = open(path).read()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if f"kernel_sha256_prefix {sha}" not in text:
+        return None
+    for line in text.split("```")[1].strip().splitlines():
+        if line.startswith(KIND_KERNEL[kind] + " "):
+            return float(line.split()[-1])
+    return None
+
+
 def cpu_baseline(cfg):
-    """FP64 oracle on a bounded sample: the same physics and angular/energy grid on a 6x6 lateral
+    """FP64 oracle on a bounded sample: the same physics and angular/energy grid on a 12x12 lateral
     window (same cell size), 1 depth step, all generations."""
     import numpy as np
 
     from oracle import oracle as O
 
-    g = dict(cfg["grid"], nx=6, ny=6, x_half=0.375, y_half=0.375, nz=1)
+    n = 12
+    g = dict(cfg["grid"], nx=n, ny=n, x_half=n * 0.0625, y_half=n * 0.0625, nz=1)
     o = O.Oracle(g, cfg["phys"])
     st = o.initial(cfg["beam"])
     t0 = time.perf_counter()
-    o.run(cfg["beam"], np.ones((1, 6, 6)), state=st)
+    o.run(cfg["beam"], np.ones((1, n, n)), state=st)
     dt = time.perf_counter() - t0
     cells = g["nx"] * g["ny"] * g["nth"] ** 2 * g["ng"] * g["ngen"]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": cells / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 depth step of the workload on a 6x6 lateral window (same cells, angles, groups, "
+            "sample": f"1 depth step of the workload on a {n}x{n} lateral window (same cells, angles, groups, "
                       f"{g['ngen']} generations): {dt:.2f} s"}
 
 
@@ -78,6 +102,8 @@ def main():
     ap.add_argument("--source", default="bf16x3", choices=["bf16x3", "fp32"],
                     help="arithmetic of the angular source product (FP32 contexts)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU sharding is a design note, "
@@ -126,8 +152,9 @@ def main():
     avg_s = ms / max(n, 1) / 1e3
     if alg[dom][0] == "bytes":
         achieved = alg[dom][1] / avg_s / 1e9
+        split_ok = args.precision == "fp32" and args.case == "water" and (dom != "qgemm" or split)
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom) if split_ok else None, "kernel": dom,
                 "algorithmic_bytes_per_launch": alg[dom][1], "avg_launch_ms": avg_s * 1e3}
     else:
         mfma = args.precision == "fp32" and (g["nth"] - 1) ** 2 >= 128
@@ -140,6 +167,7 @@ def main():
             peak = FP32_MFMA_TFLOPS if mfma else FP32_VALU_TFLOPS
         roof = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "dtype": "bf16x3" if split else args.precision,
+                "hbm_traffic_bytes": measured_traffic(dom) if split and args.case == "water" else None,
                 "traffic": None, "kernel": dom, "algorithmic_flops_per_launch": alg[dom][1],
                 "avg_launch_ms": avg_s * 1e3}
     out = {
@@ -164,6 +192,15 @@ def main():
         "roofline": roof,
     }
     s.close()
+    if args.calibrate_copy:
+        n = 1 << 28
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n}
+        del src, dst
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)
