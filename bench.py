@@ -92,6 +92,47 @@ def cpu_baseline(cfg):
                       f"{g['ngen']} generations): {dt:.2f} s"}
 
 
+def batched(nbeams, phys_override=None):
+    """Config 4 beams (uneven energies, groups and depths; 32x32 windows of a shared phantom):
+    one graph launch per wave vs the same beams run one at a time through the single-beam path."""
+    import torch
+
+    from paper_2504_00340_amd import inputs as I
+    from paper_2504_00340_amd.pbsplit import Batch, Solver
+
+    cfg = I.config4(seed=0, nbeams=nbeams)
+    beams, ph = cfg["beams"], cfg["phys"]
+    cells = sum(b["grid"]["nx"] * b["grid"]["ny"] * b["grid"]["nth"] ** 2 * b["grid"]["ng"] * b["grid"]["ngen"]
+                * b["grid"]["nz"] for b in beams)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in beams:
+        s = Solver(b["grid"], ph, precision="fp32")
+        s.set_phantom(b["rho"])
+        s.set_beam(b["beam"])
+        s.run()
+        s.dose()
+        s.close()
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    bt = Batch(beams, ph, wave=64)
+    t0 = time.perf_counter()
+    bt.run()                    # first run: includes the autotuner
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bt.run()
+    t_batch = time.perf_counter() - t0
+    tuning = bt.tuning()
+    bt.close()
+    return {"workload": f"{cfg['name']}: first {nbeams} beams, E in "
+                        f"[{min(b['beam']['e0'] for b in beams):.0f}, {max(b['beam']['e0'] for b in beams):.0f}] MeV, "
+                        f"G {min(b['grid']['ng'] for b in beams)}-{max(b['grid']['ng'] for b in beams)}, "
+                        f"{min(b['grid']['nz'] for b in beams)}-{max(b['grid']['nz'] for b in beams)} steps",
+            "beams": nbeams, "beams_per_s": nbeams / t_batch, "beams_per_s_single_beam_path": nbeams / t_single,
+            "speedup": t_single / t_batch, "cell_updates_per_s": cells / t_batch,
+            "first_run_s_with_autotune": t_first, "tuning": tuning}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +143,8 @@ def main():
     ap.add_argument("--source", default="bf16x3", choices=["bf16x3", "fp32"],
                     help="arithmetic of the angular source product (FP32 contexts)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-beams", type=int, default=8,
+                    help="config-4 beams for the batched leg (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -201,6 +244,9 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": 4 * n, "write": 4 * n}
         del src, dst
+    if args.batched_beams > 0:
+        print(f"bench: batched leg, {args.batched_beams} config-4 beams", file=sys.stderr, flush=True)
+        out["batched"] = batched(args.batched_beams)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)

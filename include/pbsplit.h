@@ -168,6 +168,32 @@ enum { PBS_K_EPASS = 0, PBS_K_TPASS = 1, PBS_K_APASS = 2, PBS_K_QGEMM = 3, PBS_K
 pbs_status pbs_profile(pbs_ctx *ctx, int enable);
 pbs_status pbs_profile_read(pbs_ctx *ctx, double *ms, long *launches, int n);
 
+/* ------------------------------------------------------------------ batched pencil beams
+ * Many beams of one shape class -- equal nx, ny, nth, ngen, x_half, y_half, th_half; energy groups,
+ * energy range, depth steps and step length per beam -- marched together on one GPU in FP32 with
+ * the split-BF16 source product (nth >= 16).  Each beam follows exactly the single-beam scheme above
+ * (same kernels, bitwise the same dose).  Beams are grouped into waves of at most `wave` beams
+ * (0 = all), longest first; the whole march of a wave is captured into one HIP graph and launched
+ * once.  Launch variants that do not change the arithmetic are chosen by timing on the first wave.
+ * The caller owns the workspace (pbs_batch_workspace_bytes, 256-byte aligned) and the host arrays. */
+typedef struct pbs_batch pbs_batch;
+pbs_status pbs_batch_create(const pbs_grid *grids, const pbs_beam *beams, int nbeams, const pbs_physics *phys,
+                            int wave, pbs_batch **out);
+pbs_status pbs_batch_workspace_bytes(const pbs_batch *batch, size_t *bytes);
+/* hip_stream must not be NULL: the march is captured into a HIP graph, which the null stream cannot do. */
+pbs_status pbs_batch_bind(pbs_batch *batch, void *dev_workspace, size_t bytes, void *hip_stream);
+/* Densities of one beam's grid, [nz][nx][ny] doubles (finite, > 0); copied. */
+pbs_status pbs_batch_set_phantom(pbs_batch *batch, int beam, const double *rho, size_t n);
+/* March every beam to its end (closing energy half-step included); synchronises the stream. */
+pbs_status pbs_batch_run(pbs_batch *batch);
+/* Dose of one beam, [nz][nx][ny] FP64 host array (MeV/g per incident proton). */
+pbs_status pbs_batch_get_dose(pbs_batch *batch, int beam, double *out, size_t n);
+/* Launch variants chosen by the autotuner: {source-product block columns, transport planes per
+ * block, angular-pass cells per block}. */
+pbs_status pbs_batch_tuning(const pbs_batch *batch, int *out3);
+const char *pbs_batch_last_error(const pbs_batch *batch);
+void pbs_batch_destroy(pbs_batch *batch);
+
 /* Text of the last error of this context (never NULL). */
 const char *pbs_last_error(const pbs_ctx *ctx);
 

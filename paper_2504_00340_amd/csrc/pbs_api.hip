@@ -9,13 +9,13 @@
 #include <vector>
 
 #include "pbs_common.h"
+#include "pbs_ctx.h"
 #include "pbsplit.h"
 
 using namespace pbs;
 
 namespace {
 
-enum { ST_CREATED = 0, ST_BOUND = 1, ST_PHANTOM = 2, ST_BEAM = 3 };
 
 // 8-point Gauss-Legendre rule on [-1, 1] (Abramowitz & Stegun, table 25.4).
 const double GL8_X[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
@@ -25,56 +25,6 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-struct pbs_ctx {
-    pbs_grid g;
-    pbs_physics ph;
-    int prec = PBS_FP32;
-    int tsz = 4;                          // sizeof(T)
-    int m = 0, NA = 0, NP = 0, NPB = 0, NPpad = 0;
-    long NLINE = 0;
-    double dx = 0, dy = 0, dth = 0;
-    // host tables (FP64)
-    std::vector<double> E_face, E_mid, dE, S_face, sig_tr, kappa, Sm, Sp, wc, wdec, invdE, dA, dB, dInj, theta, sinS,
-        lam, P2T;
-    double dBot = 0;
-    // workspace
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
-    hipStream_t stream = nullptr;
-    size_t o_psi = 0, o_W = 0, o_Q = 0, o_dep = 0, o_edep = 0, o_dout = 0, o_rhoT = 0, o_rhoD = 0, o_tabT = 0,
-           o_tabD = 0, total = 0;
-    // table offsets (elements) inside the T and double table blocks
-    size_t t_Sm, t_Sp, t_kap, t_wc, t_wdec, t_invdE, t_sig, t_theta, t_S, t_lam, t_P2T, t_P2p, t_K32, t_count;
-    int Kp = 0, Mp = 0;           // padded source product (MFMA path, FP32 with NA >= 128)
-    int Kpb = 0;                  // k padding of the split-BF16 operand tables
-    int NOCT = 0;                 // source-node octets of the split-BF16 W layout
-    size_t Wb_half = 0;           // elements of one of the hi / lo arrays
-    int src_mode = PBS_SRC_FP32;
-    size_t o_bf = 0;
-    size_t d_A, d_B, d_Inj, d_E1, d_E2, d_lat, d_count;
-    int state = ST_CREATED;
-    int step = 0;
-    bool closed = false;
-    std::vector<double> rho_host;
-    std::string err;
-    // kernel timing (diagnostics)
-    bool prof = false;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    std::vector<std::pair<int, size_t>> ev_pairs;   // (kind, index of the start event)
-
-    template <typename T> T *psi(int k) { return reinterpret_cast<T *>(ws + o_psi) + (size_t)k * G() * 2 * NLINE; }
-    template <typename T> T *W() { return reinterpret_cast<T *>(ws + o_W); }
-    template <typename T> T *Q() { return reinterpret_cast<T *>(ws + o_Q); }
-    template <typename T> T *tabT() { return reinterpret_cast<T *>(ws + o_tabT); }
-    template <typename T> T *rhoT(int s) { return reinterpret_cast<T *>(ws + o_rhoT) + (size_t)s * NPpad; }
-    double *tabD() { return reinterpret_cast<double *>(ws + o_tabD); }
-    double *dep(int half, int k) { return reinterpret_cast<double *>(ws + o_dep) + ((size_t)half * g.ngen + k) * NLINE; }
-    double *edep(int s) { return reinterpret_cast<double *>(ws + o_edep) + (size_t)s * NP; }
-    double *dout() { return reinterpret_cast<double *>(ws + o_dout); }
-    double *rhoD() { return reinterpret_cast<double *>(ws + o_rhoD); }
-    int G() const { return g.ng; }
-};
 
 namespace {
 

@@ -77,6 +77,43 @@ struct QParams {
     long NLINE;
 };
 
+// One beam of a batch (device copy of its descriptor).  Beams of one batch share the lateral and
+// angular grid and the number of generations; groups, depth steps and step length differ.
+struct BeamDev {
+    float *psi;               // generation 0 of the fluence; generations follow
+    float *Q;                 // [2][G][NLINE]
+    unsigned short *Wh, *Wl;  // split-BF16 energy scans, [2][G][NPB][NOCT][PT][8]
+    const float *rho;         // [nz][NPB*PT]
+    double *dep;              // [2][ngen][NLINE]
+    double *edep;             // [nz][NP]
+    const float *tabf;        // Sm, Sp, kappa, wc, wdec, 1/dE, sigma_tr: 7 arrays of G
+    const double *tabd;       // deposit weights dA, dB, dInj: 3 arrays of G
+    double dBot;
+    float dz;
+    int G, nz;
+};
+
+struct BatchShape {
+    const float *theta, *lam, *S;          // angular tables
+    const unsigned short *Ahi, *Alo;       // split-BF16 P2, [Mp][Kpb]
+    int Kpb, Mp;
+    int nx, ny, nth, m, NA, NPB, NOCT, ngen;
+    long NLINE;
+    float dx, dy;
+    double scale;                          // dth^2 dx dy
+};
+
+// bitwise-neutral launch variants picked by the batch autotuner
+struct BatchTuning {
+    int gemm_bn = 256;        // split-BF16 product: 128 or 256 columns per block
+    int tpass_wpb = 4;        // transport: planes (waves) per block, 1, 2 or 4
+    int apass_pc = 32;        // angular pass: lateral cells per block, 8, 16 or 32
+    int max_nz = 0;           // longest beam of the wave (set by the driver)
+};
+
+hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &Sh, int s, int maxG,
+                             const BatchTuning &tu, hipStream_t st);
+
 // launchers (explicitly instantiated for float and double); return hipGetLastError()
 template <typename T> hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st);
 template <typename T> hipError_t launch_tpass(const TParams<T> &P, hipStream_t st);
@@ -92,7 +129,7 @@ hipError_t launch_initial(T *psi0, const double *E1, const double *E2, const dou
                           int NA, int NPB, int NP, hipStream_t st);
 
 hipError_t launch_qgemm_bf16x3(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
-                               hipStream_t st);
+                               hipStream_t st, int bn = 256);
 hipError_t launch_apass_mfma32(const AParams<float> &P, const float *Ktab, long nstack, hipStream_t st);
 
 bool apass_supported(int nth);

@@ -28,12 +28,12 @@ __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 // pt = tid%32: the split-BF16 scans of the 8 lines of a cell are gathered in LDS and written as one
 // 16-byte chunk (one LDS buffer per group parity, one barrier per group).
 template <typename T, int MODE, bool SPLIT>
-__global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
+__device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
 {
     constexpr bool CL = (MODE & MODE_CLOSE) != 0;
     constexpr bool OP = (MODE & MODE_OPEN) != 0;
     const int NA = (int)(P.NAPT / PBS_PT);
-    const int pbk = blockIdx.x / P.NOCT, oct = blockIdx.x % P.NOCT;
+    const int pbk = bx / P.NOCT, oct = bx % P.NOCT;
     const int e = threadIdx.x >> 5, ptc = threadIdx.x & 31;
     const int a = oct * 8 + e;
     const bool valid = a < NA;
@@ -149,6 +149,12 @@ __global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
     if (OP) P.dep_o[line] = dao * (ph1 + ph2 - injo) * P.scale;
 }
 
+template <typename T, int MODE, bool SPLIT>
+__global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
+{
+    epass_body<T, MODE, SPLIT>(P, blockIdx.x);
+}
+
 template <typename T>
 hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st)
 {
@@ -178,10 +184,9 @@ __device__ __forceinline__ T superbee_slope(T dup, T dface)
 }
 
 template <typename T, int NSEG>
-__global__ __launch_bounds__(256) void tpass_kernel(TParams<T> P)
+__device__ __forceinline__ void tpass_body(const TParams<T> &P, long plane)
 {
     const int lane = threadIdx.x & 63;
-    const long plane = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (plane >= P.nplanes) return;   // uniform per wave
     const int a = (int)(plane % P.NA);
     const long slab = plane / P.NA;
@@ -283,6 +288,12 @@ __global__ __launch_bounds__(256) void tpass_kernel(TParams<T> P)
     }
 }
 
+template <typename T, int NSEG>
+__global__ __launch_bounds__(256) void tpass_kernel(TParams<T> P)
+{
+    tpass_body<T, NSEG>(P, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
+}
+
 template <typename T>
 hipError_t launch_tpass(const TParams<T> &P, hipStream_t st)
 {
@@ -329,17 +340,17 @@ __device__ __forceinline__ void dst1(const T (&x)[N - 1], T (&y)[N - 1], const T
 }
 
 template <typename T, int N, int PC>
-__global__ __launch_bounds__(256) void apass_kernel(AParams<T> P)
+__device__ __forceinline__ void apass_body(const AParams<T> &P, int bx, long by)
 {
     constexpr int m = N - 1;
     constexpr int NA = m * m;
     extern __shared__ char smem_raw[];
     T *L = reinterpret_cast<T *>(smem_raw);   // [NA][PC]
     const int tid = threadIdx.x;
-    const long stack = blockIdx.y;           // (k*G + g)*2 + l
+    const long stack = by;           // (k*G + g)*2 + l
     const int g = (int)((stack / 2) % P.G);
-    const int pb = blockIdx.x / (PBS_PT / PC);
-    const int c0 = (blockIdx.x % (PBS_PT / PC)) * PC;
+    const int pb = bx / (PBS_PT / PC);
+    const int c0 = (bx % (PBS_PT / PC)) * PC;
     T *blk = P.psi + stack * P.NLINE + (long)pb * NA * PBS_PT + c0;
     for (int idx = tid; idx < NA * PC; idx += 256) {
         const int a = idx / PC, c = idx % PC;
@@ -393,6 +404,12 @@ __global__ __launch_bounds__(256) void apass_kernel(AParams<T> P)
         const int a = idx / PC, c = idx % PC;
         blk[(long)a * PBS_PT + c] = L[idx];
     }
+}
+
+template <typename T, int N, int PC>
+__global__ __launch_bounds__(256) void apass_kernel(AParams<T> P)
+{
+    apass_body<T, N, PC>(P, blockIdx.x, blockIdx.y);
 }
 
 template <typename T, int N>
@@ -753,13 +770,16 @@ __global__ __launch_bounds__(256) void qgemm_mfma_f32_kernel(QParams<float> P, i
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-__global__ __launch_bounds__(512) void qgemm_bf16x3_kernel(QParams<float> P, const unsigned short *__restrict__ Ahi,
-                                                           const unsigned short *__restrict__ Alo, int Kp, int nmt,
-                                                           int nnt, long nlogical, long per_xcd)
+template <int BN>
+__device__ __forceinline__ void qgemm_bf16x3_body(const QParams<float> &P, const unsigned short *__restrict__ Ahi,
+                                                  const unsigned short *__restrict__ Alo, int Kp, int nmt, int nnt,
+                                                  long nlogical, long per_xcd, long bid)
 {
     constexpr int BK = 32, LD = BK + 8;   // LDS row stride in bf16 elements (80 B)
-    __shared__ unsigned short sAh[128 * LD], sAl[128 * LD], sBh[256 * LD], sBl[256 * LD];
-    const long bid = blockIdx.x;
+    constexpr int NPBT = BN / 32;         // lateral tiles per block
+    constexpr int WN = BN / 64;           // waves along N (2 along M)
+    constexpr int NT = 128 * WN;          // threads
+    __shared__ unsigned short sAh[128 * LD], sAl[128 * LD], sBh[BN * LD], sBl[BN * LD];
     const long logical = (bid & 7) * per_xcd + (bid >> 3);
     if (logical >= nlogical) return;
     const int mt = (int)(logical % nmt);
@@ -771,7 +791,7 @@ __global__ __launch_bounds__(512) void qgemm_bf16x3_kernel(QParams<float> P, con
     float *__restrict__ C = P.Q + off;
     const long NAPT = (long)P.NA * PBS_PT;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int wm = wid >> 2, wn = wid & 3;
+    const int wm = wid / WN, wn = wid % WN;
     floatx16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -780,18 +800,22 @@ __global__ __launch_bounds__(512) void qgemm_bf16x3_kernel(QParams<float> P, con
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
     const int nk = Kp / BK;
-    // staging assignment: A chunk (row = tid/4, 8 k at 8*(tid%4)); B: column tid%256, k octets tid/256 and +2
-    const int arow = tid >> 2, akq = tid & 3;
-    const int bcol = tid & 255, boct = tid >> 8;
-    const int bpb = nt * 8 + (bcol >> 5), bpt = bcol & 31;
+    // staging: A chunks (row, 8 k) c = tid + NT*i over 128 x 4; B items column tid % BN, octets tid / BN and +2
+    constexpr int NA_CH = 512 / NT;
+    const int bcol = tid % BN, boct = tid / BN;
+    const int bpb = nt * NPBT + (bcol >> 5), bpt = bcol & 31;
     const bool bok = bpb < P.NPB;
     const long bbase = (((long)s * P.G + g) * P.NPB + (bok ? bpb : 0)) * P.NOCT * (PBS_PT * 8) + bpt * 8;
-    u16x8 rah, ral;
+    u16x8 rah[NA_CH], ral[NA_CH];
     u16x8 rbh[2], rbl[2];
     auto gload = [&](int kt) {
-        const long ao = (long)(mt * 128 + arow) * Kp + kt * BK + akq * 8;
-        rah = *reinterpret_cast<const u16x8 *>(Ahi + ao);
-        ral = *reinterpret_cast<const u16x8 *>(Alo + ao);
+#pragma unroll
+        for (int c = 0; c < NA_CH; ++c) {
+            const int ch = tid + NT * c, arow = ch >> 2, akq = ch & 3;
+            const long ao = (long)(mt * 128 + arow) * Kp + kt * BK + akq * 8;
+            rah[c] = *reinterpret_cast<const u16x8 *>(Ahi + ao);
+            ral[c] = *reinterpret_cast<const u16x8 *>(Alo + ao);
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int oc = kt * (BK / 8) + boct + 2 * h;
@@ -805,8 +829,12 @@ __global__ __launch_bounds__(512) void qgemm_bf16x3_kernel(QParams<float> P, con
         }
     };
     auto sstore = [&]() {
-        *reinterpret_cast<u16x8 *>(&sAh[arow * LD + akq * 8]) = rah;
-        *reinterpret_cast<u16x8 *>(&sAl[arow * LD + akq * 8]) = ral;
+#pragma unroll
+        for (int c = 0; c < NA_CH; ++c) {
+            const int ch = tid + NT * c, arow = ch >> 2, akq = ch & 3;
+            *reinterpret_cast<u16x8 *>(&sAh[arow * LD + akq * 8]) = rah[c];
+            *reinterpret_cast<u16x8 *>(&sAl[arow * LD + akq * 8]) = ral[c];
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             *reinterpret_cast<u16x8 *>(&sBh[bcol * LD + (boct + 2 * h) * 8]) = rbh[h];
@@ -853,7 +881,7 @@ __global__ __launch_bounds__(512) void qgemm_bf16x3_kernel(QParams<float> P, con
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const int pb = nt * 8 + wn * 2 + j;
+            const int pb = nt * NPBT + wn * 2 + j;
             if (pb >= P.NPB) continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -863,14 +891,26 @@ __global__ __launch_bounds__(512) void qgemm_bf16x3_kernel(QParams<float> P, con
         }
 }
 
-hipError_t launch_qgemm_bf16x3(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
-                               hipStream_t st)
+template <int BN>
+__global__ __launch_bounds__(2 * BN) void qgemm_bf16x3_kernel(QParams<float> P, const unsigned short *__restrict__ Ahi,
+                                                              const unsigned short *__restrict__ Alo, int Kp, int nmt,
+                                                              int nnt, long nlogical, long per_xcd)
 {
-    const int nmt = P.Mp / 128, nnt = (P.NPB + 7) / 8;
+    qgemm_bf16x3_body<BN>(P, Ahi, Alo, Kp, nmt, nnt, nlogical, per_xcd, blockIdx.x);
+}
+
+hipError_t launch_qgemm_bf16x3(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
+                               hipStream_t st, int bn)
+{
+    const int nmt = P.Mp / 128, nnt = (P.NPB + bn / 32 - 1) / (bn / 32);
     const long nlog = (long)P.ns * P.G * nnt * nmt;
     const long per = (nlog + 7) / 8;
-    hipLaunchKernelGGL(qgemm_bf16x3_kernel, dim3((unsigned)(per * 8)), dim3(512), 0, st, P, Ahi, Alo, Kp, nmt, nnt,
-                       nlog, per);
+    if (bn == 128)
+        hipLaunchKernelGGL(qgemm_bf16x3_kernel<128>, dim3((unsigned)(per * 8)), dim3(256), 0, st, P, Ahi, Alo, Kp, nmt,
+                           nnt, nlog, per);
+    else
+        hipLaunchKernelGGL(qgemm_bf16x3_kernel<256>, dim3((unsigned)(per * 8)), dim3(512), 0, st, P, Ahi, Alo, Kp, nmt,
+                           nnt, nlog, per);
     return hipGetLastError();
 }
 
@@ -1013,12 +1053,11 @@ hipError_t launch_fill(T *p, T v, long n, hipStream_t st)
 
 // edep[pq] += sum over generations and angles of dep[k][line(pq, a)], fixed order: one block per
 // lateral tile, 32 lanes per cell x 32 angle slices, then a fixed-order tree over the slices.
-__global__ __launch_bounds__(1024) void dose_reduce_kernel(double *edep, const double *dep, int ngen, int NA,
-                                                           long NLINE, int NP)
+__device__ __forceinline__ void dose_reduce_body(double *edep, const double *dep, int ngen, int NA, long NLINE,
+                                                 int NP, int pb)
 {
     __shared__ double part[32][33];
     const int pt = threadIdx.x & 31, sl = threadIdx.x >> 5;
-    const int pb = blockIdx.x;
     const long base = (long)pb * NA * PBS_PT + pt;
     double s = 0.0;
     for (int k = 0; k < ngen; ++k)
@@ -1031,6 +1070,12 @@ __global__ __launch_bounds__(1024) void dose_reduce_kernel(double *edep, const d
     }
     const int pq = pb * PBS_PT + pt;
     if (sl == 0 && pq < NP) edep[pq] += part[0][pt];
+}
+
+__global__ __launch_bounds__(1024) void dose_reduce_kernel(double *edep, const double *dep, int ngen, int NA,
+                                                           long NLINE, int NP)
+{
+    dose_reduce_body(edep, dep, ngen, NA, NLINE, NP, blockIdx.x);
 }
 
 hipError_t launch_dose_reduce(double *edep_layer, const double *dep, int ngen, int NA, long NLINE, int NP,
@@ -1076,6 +1121,199 @@ hipError_t launch_initial(T *psi0, const double *E1, const double *E2, const dou
     const long n = (long)G * NP;
     hipLaunchKernelGGL((initial_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, psi0, E1, E2, lat,
                        center_a, G, NA, NPB, NP);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------- batched wrappers
+// Every launch covers all beams of a resident wave (grid y or z = beam); each block reads its beam's
+// descriptor, derives the sub-step of step s for that beam (open at s = 0, fused pair for
+// 0 < s < nz, close at s = nz) and exits when the beam has nothing to do.
+__device__ __forceinline__ int beam_mode(int s, int nz)
+{
+    if (s > nz) return 0;
+    if (s == 0) return MODE_OPEN;
+    if (s == nz) return MODE_CLOSE;
+    return MODE_PAIR;
+}
+
+__global__ __launch_bounds__(256) void epass_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int k,
+                                                            int s)
+{
+    const BeamDev &B = beams[blockIdx.y];
+    const int mode = beam_mode(s, B.nz);
+    if (mode == 0 || blockIdx.x >= (unsigned)(Sh.NPB * Sh.NOCT)) return;
+    EParams<float> P;
+    const int G = B.G;
+    P.psi = B.psi + (long)k * G * 2 * Sh.NLINE;
+    P.Q = k > 0 ? B.Q : nullptr;
+    P.W = nullptr;
+    const bool w = k + 1 < Sh.ngen;
+    P.Wh = w ? B.Wh : nullptr;
+    P.Wl = w ? B.Wl : nullptr;
+    P.NOCT = Sh.NOCT;
+    P.rho_c = (mode & MODE_CLOSE) ? B.rho + (long)(s - 1) * Sh.NPB * PBS_PT : nullptr;
+    P.rho_o = (mode & MODE_OPEN) ? B.rho + (long)s * Sh.NPB * PBS_PT : nullptr;
+    P.dep_c = B.dep + (long)k * Sh.NLINE;
+    P.dep_o = B.dep + ((long)Sh.ngen + k) * Sh.NLINE;
+    P.Sm = B.tabf;
+    P.Sp = B.tabf + G;
+    P.kap = B.tabf + 2 * G;
+    P.wc = B.tabf + 3 * G;
+    P.wdec = B.tabf + 4 * G;
+    P.invdE = B.tabf + 5 * G;
+    P.dA = B.tabd;
+    P.dB = B.tabd + G;
+    P.dInj = B.tabd + 2 * G;
+    P.dBot = B.dBot;
+    P.scale = Sh.scale;
+    P.h = 0.5f * B.dz;
+    P.G = G;
+    P.NLINE = Sh.NLINE;
+    P.NAPT = (long)Sh.NA * PBS_PT;
+    if (mode == MODE_PAIR)
+        epass_body<float, MODE_PAIR, true>(P, blockIdx.x);
+    else if (mode == MODE_OPEN)
+        epass_body<float, MODE_OPEN, true>(P, blockIdx.x);
+    else
+        epass_body<float, MODE_CLOSE, true>(P, blockIdx.x);
+}
+
+template <int BN>
+__global__ __launch_bounds__(2 * BN) void qgemm_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
+{
+    const BeamDev &B = beams[blockIdx.y];
+    const int mode = beam_mode(s, B.nz);
+    if (mode == 0) return;
+    QParams<float> P;
+    P.P2T = nullptr;
+    P.W = nullptr;
+    P.Q = B.Q;
+    P.P2p = nullptr;
+    P.Kp = Sh.Kpb;
+    P.Mp = Sh.Mp;
+    P.Bh = B.Wh;
+    P.Bl = B.Wl;
+    P.NOCT = Sh.NOCT;
+    P.NA = Sh.NA;
+    P.NPB = Sh.NPB;
+    P.G = B.G;
+    P.s0 = (mode == MODE_OPEN) ? 1 : 0;
+    P.ns = (mode == MODE_PAIR) ? 2 : 1;
+    P.NLINE = Sh.NLINE;
+    const int nmt = Sh.Mp / 128, nnt = (Sh.NPB + BN / 32 - 1) / (BN / 32);
+    const long nlog = (long)P.ns * P.G * nnt * nmt;
+    const long per = (nlog + 7) / 8;
+    if ((long)blockIdx.x >= per * 8) return;
+    qgemm_bf16x3_body<BN>(P, Sh.Ahi, Sh.Alo, Sh.Kpb, nmt, nnt, nlog, per, blockIdx.x);
+}
+
+template <int NSEG, int WPB>
+__global__ __launch_bounds__(64 * WPB) void tpass_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh,
+                                                                 int s)
+{
+    const BeamDev &B = beams[blockIdx.y];
+    if (s >= B.nz) return;
+    TParams<float> P;
+    P.psi = B.psi;
+    P.theta = Sh.theta;
+    P.h_half_over_dx = 0.25f * B.dz / Sh.dx;
+    P.h_half_over_dy = 0.25f * B.dz / Sh.dy;
+    P.nx = Sh.nx;
+    P.ny = Sh.ny;
+    P.m = Sh.m;
+    P.NA = Sh.NA;
+    P.NLINE = Sh.NLINE;
+    P.nplanes = (long)Sh.ngen * B.G * 2 * Sh.NA;
+    tpass_body<float, NSEG>(P, (long)blockIdx.x * WPB + (threadIdx.x >> 6));
+}
+
+template <int N, int PC>
+__global__ __launch_bounds__(256) void apass_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
+{
+    const BeamDev &B = beams[blockIdx.z];
+    if (s >= B.nz || blockIdx.y >= (unsigned)(Sh.ngen * B.G * 2)) return;
+    AParams<float> P;
+    P.psi = B.psi;
+    P.rho = B.rho + (long)s * Sh.NPB * PBS_PT;
+    P.sig = B.tabf + 6 * B.G;
+    P.S = Sh.S;
+    P.lam = Sh.lam;
+    P.h = B.dz;
+    P.G = B.G;
+    P.NA = Sh.NA;
+    P.NPB = Sh.NPB;
+    P.NLINE = Sh.NLINE;
+    apass_body<float, N, PC>(P, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(1024) void dose_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
+{
+    const BeamDev &B = beams[blockIdx.y];
+    const int mode = beam_mode(s, B.nz);
+    const int NP = Sh.nx * Sh.ny;
+    if (mode & MODE_CLOSE)
+        dose_reduce_body(B.edep + (long)(s - 1) * NP, B.dep, Sh.ngen, Sh.NA, Sh.NLINE, NP, blockIdx.x);
+    __syncthreads();
+    if (mode & MODE_OPEN)
+        dose_reduce_body(B.edep + (long)s * NP, B.dep + (long)Sh.ngen * Sh.NLINE, Sh.ngen, Sh.NA, Sh.NLINE, NP,
+                         blockIdx.x);
+}
+
+hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &Sh, int s, int maxG,
+                             const BatchTuning &tu, hipStream_t st)
+{
+    for (int k = 0; k < Sh.ngen; ++k) {
+        hipLaunchKernelGGL(epass_batched_kernel, dim3(Sh.NPB * Sh.NOCT, nbeam), dim3(256), 0, st, beams, Sh, k, s);
+        if (k + 1 < Sh.ngen) {
+            const int bn = tu.gemm_bn;
+            const int nmt = Sh.Mp / 128, nnt = (Sh.NPB + bn / 32 - 1) / (bn / 32);
+            const long per = ((long)2 * maxG * nnt * nmt + 7) / 8;
+            if (bn == 128)
+                hipLaunchKernelGGL(qgemm_batched_kernel<128>, dim3((unsigned)(per * 8), nbeam), dim3(256), 0, st,
+                                   beams, Sh, s);
+            else
+                hipLaunchKernelGGL(qgemm_batched_kernel<256>, dim3((unsigned)(per * 8), nbeam), dim3(512), 0, st,
+                                   beams, Sh, s);
+        }
+    }
+    hipLaunchKernelGGL(dose_batched_kernel, dim3(Sh.NPB, nbeam), dim3(1024), 0, st, beams, Sh, s);
+    const long planes = (long)Sh.ngen * maxG * 2 * Sh.NA;
+    const int nseg = (Sh.ny + 63) / 64;
+    auto tpass = [&]() {
+        const int w = tu.tpass_wpb;
+        const unsigned nb = (unsigned)((planes + w - 1) / w);
+#define PBS_TB(NS, W) hipLaunchKernelGGL((tpass_batched_kernel<NS, W>), dim3(nb, nbeam), dim3(64 * W), 0, st, beams, Sh, s)
+#define PBS_TW(NS) do { if (w == 1) PBS_TB(NS, 1); else if (w == 2) PBS_TB(NS, 2); else PBS_TB(NS, 4); } while (0)
+        switch (nseg) {
+        case 1: PBS_TW(1); break;
+        case 2: PBS_TW(2); break;
+        case 3: PBS_TW(3); break;
+        default: PBS_TW(4); break;
+        }
+#undef PBS_TW
+#undef PBS_TB
+    };
+    if (s < tu.max_nz) tpass();
+    if (s < tu.max_nz) {
+        const int pc = tu.apass_pc;
+        dim3 grid((unsigned)(Sh.NPB * (PBS_PT / pc)), (unsigned)(Sh.ngen * maxG * 2), nbeam);
+#define PBS_AB(N)                                                                                           \
+    do {                                                                                                    \
+        const size_t sh = (size_t)(N - 1) * (N - 1) * pc * sizeof(float);                                   \
+        if (pc == 32) hipLaunchKernelGGL((apass_batched_kernel<N, 32>), grid, dim3(256), sh, st, beams, Sh, s); \
+        else if (pc == 16) hipLaunchKernelGGL((apass_batched_kernel<N, 16>), grid, dim3(256), sh, st, beams, Sh, s); \
+        else hipLaunchKernelGGL((apass_batched_kernel<N, 8>), grid, dim3(256), sh, st, beams, Sh, s);         \
+    } while (0)
+        switch (Sh.nth) {
+        case 16: PBS_AB(16); break;
+        case 20: PBS_AB(20); break;
+        case 24: PBS_AB(24); break;
+        case 32: PBS_AB(32); break;
+        default: return hipErrorInvalidValue;
+        }
+#undef PBS_AB
+    }
+    if (s < tu.max_nz) tpass();
     return hipGetLastError();
 }
 

@@ -24,7 +24,9 @@ _NAMES = {0: "PBS_OK", -1: "PBS_EINVAL", -2: "PBS_ESTATE", -3: "PBS_ENOMEM", -4:
 EXPORTS = ["pbs_create", "pbs_workspace_bytes", "pbs_bind", "pbs_set_phantom", "pbs_set_beam", "pbs_step_depth",
            "pbs_run_beam", "pbs_get_dose", "pbs_get_state", "pbs_set_state", "pbs_apply", "pbs_set_source_precision",
            "pbs_profile",
-           "pbs_profile_read", "pbs_last_error", "pbs_destroy"]
+           "pbs_profile_read", "pbs_last_error", "pbs_destroy", "pbs_batch_create", "pbs_batch_workspace_bytes",
+           "pbs_batch_bind", "pbs_batch_set_phantom", "pbs_batch_run", "pbs_batch_get_dose", "pbs_batch_tuning",
+           "pbs_batch_last_error", "pbs_batch_destroy"]
 KINDS = ["epass", "tpass", "apass", "qgemm", "dose"]
 
 
@@ -81,8 +83,20 @@ def lib():
         L.pbs_last_error.restype = C.c_char_p
         L.pbs_destroy.argtypes = [vp]
         L.pbs_destroy.restype = None
+        L.pbs_batch_create.argtypes = [C.POINTER(Grid), C.POINTER(Beam), C.c_int, C.POINTER(Physics), C.c_int,
+                                       C.POINTER(vp)]
+        L.pbs_batch_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
+        L.pbs_batch_bind.argtypes = [vp, vp, sz, vp]
+        L.pbs_batch_set_phantom.argtypes = [vp, C.c_int, D, sz]
+        L.pbs_batch_run.argtypes = [vp]
+        L.pbs_batch_get_dose.argtypes = [vp, C.c_int, D, sz]
+        L.pbs_batch_tuning.argtypes = [vp, C.POINTER(C.c_int)]
+        L.pbs_batch_last_error.argtypes = [vp]
+        L.pbs_batch_last_error.restype = C.c_char_p
+        L.pbs_batch_destroy.argtypes = [vp]
+        L.pbs_batch_destroy.restype = None
         for n in EXPORTS:
-            if n not in ("pbs_last_error", "pbs_destroy"):
+            if n not in ("pbs_last_error", "pbs_destroy", "pbs_batch_last_error", "pbs_batch_destroy"):
                 getattr(L, n).restype = C.c_int
         _lib = L
     return _lib
@@ -181,6 +195,66 @@ class Solver:
         if getattr(self, "ctx", None):
             self.L.pbs_destroy(self.ctx)
             self.ctx = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many beams of one shape class marched together (pbs_batch_*).  beams: list of dicts with
+    keys grid, beam, rho (as produced by inputs.config4)."""
+
+    def __init__(self, beams: list, phys: dict, wave: int = 0, device="cuda:0", stream=None):
+        import torch
+
+        self.L = lib()
+        self.n = len(beams)
+        grids = (Grid * self.n)(*[_mk(Grid, b["grid"]) for b in beams])
+        bms = (Beam * self.n)(*[_mk(Beam, b["beam"]) for b in beams])
+        self.shapes = [(b["grid"]["nz"], b["grid"]["nx"], b["grid"]["ny"]) for b in beams]
+        self.h = C.c_void_p()
+        rc = self.L.pbs_batch_create(grids, bms, self.n, C.byref(_mk(Physics, phys)), int(wave), C.byref(self.h))
+        if rc != PBS_OK:
+            raise PbsError(rc, "pbs_batch_create rejected the beams")
+        nb = C.c_size_t()
+        self._check(self.L.pbs_batch_workspace_bytes(self.h, C.byref(nb)))
+        self.ws_bytes = nb.value
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=torch.device(device))
+        base = self._ws.data_ptr()
+        ptr = base + ((256 - base % 256) % 256)
+        # a stream of its own (default priority): the march is captured into a graph
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=torch.device(device))
+        torch.cuda.current_stream(torch.device(device)).synchronize()
+        self._check(self.L.pbs_batch_bind(self.h, C.c_void_p(ptr), self.ws_bytes, C.c_void_p(self.stream.cuda_stream)))
+        for i, b in enumerate(beams):
+            r = np.ascontiguousarray(b["rho"], dtype=np.float64).reshape(-1)
+            self._check(self.L.pbs_batch_set_phantom(self.h, i, r.ctypes.data_as(C.POINTER(C.c_double)), r.size))
+
+    def _check(self, rc):
+        if rc != PBS_OK:
+            raise PbsError(rc, self.L.pbs_batch_last_error(self.h).decode())
+
+    def run(self):
+        self._check(self.L.pbs_batch_run(self.h))
+
+    def dose(self, i: int) -> np.ndarray:
+        out = np.zeros(self.shapes[i])
+        self._check(self.L.pbs_batch_get_dose(self.h, int(i), out.ctypes.data_as(C.POINTER(C.c_double)), out.size))
+        return out
+
+    def tuning(self) -> dict:
+        t = (C.c_int * 3)()
+        self._check(self.L.pbs_batch_tuning(self.h, t))
+        return {"gemm_bn": t[0], "tpass_waves_per_block": t[1], "apass_cells_per_block": t[2]}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pbs_batch_destroy(self.h)
+            self.h = None
         self._ws = None
 
     def __del__(self):

@@ -72,3 +72,23 @@ def test_workspace_scales_with_precision_and_generations():
             B.lib().pbs_destroy(ctx)
     assert sizes[B.PBS_FP64, 1] > sizes[B.PBS_FP32, 1]
     assert sizes[B.PBS_FP32, 2] > 2 * sizes[B.PBS_FP32, 1] - 1
+
+
+def test_batch_create_validates_shape_class():
+    L = B.lib()
+    g1 = I.grid(10, 10, 16, 20, 4, 2, 1.0, 1.0, 0.15, 0.0, 40.0, 0.6)
+    g2 = dict(g1, ng=33, nz=7, e_hi=50.0)
+    bm = I.beam(30.0)
+    grids = (B.Grid * 2)(B._mk(B.Grid, g1), B._mk(B.Grid, g2))
+    beams = (B.Beam * 2)(B._mk(B.Beam, bm), B._mk(B.Beam, bm))
+    h = C.c_void_p()
+    assert L.pbs_batch_create(grids, beams, 2, C.byref(B._mk(B.Physics, I.PHYS)), 0, C.byref(h)) == B.PBS_OK
+    nb = C.c_size_t()
+    assert L.pbs_batch_workspace_bytes(h, C.byref(nb)) == B.PBS_OK and nb.value > 0
+    assert L.pbs_batch_run(h) == B.PBS_ESTATE
+    L.pbs_batch_destroy(h)
+    bad = (B.Grid * 2)(B._mk(B.Grid, g1), B._mk(B.Grid, dict(g2, nx=11)))
+    h = C.c_void_p()
+    assert L.pbs_batch_create(bad, beams, 2, C.byref(B._mk(B.Physics, I.PHYS)), 0, C.byref(h)) == B.PBS_EINVAL
+    small = (B.Grid * 1)(B._mk(B.Grid, dict(g1, nth=8)))
+    assert L.pbs_batch_create(small, beams, 1, C.byref(B._mk(B.Physics, I.PHYS)), 0, C.byref(h)) == B.PBS_EUNSUPPORTED
