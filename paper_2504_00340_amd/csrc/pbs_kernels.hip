@@ -294,9 +294,196 @@ __global__ __launch_bounds__(256) void tpass_kernel(TParams<T> P)
     tpass_body<T, NSEG>(P, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
+// FP32 variant for ny <= 64: cross-lane moves by DPP (wave_shr/shl:1 for the y neighbours, a
+// row_shr / row_bcast affine scan for the implicit row solve) and 8 rows in flight per wave.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_f(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROWMASK, 0xF,
+                                                                 false));
+}
+// DPP controls (GFX9): row_shr:n = 0x110 + n, wave_shl:1 = 0x130, wave_shr:1 = 0x138,
+// row_bcast:15 = 0x142, row_bcast:31 = 0x143.  Lanes without a source receive 0 (the ghost value).
+
+__device__ __forceinline__ void tpass_dpp_body(const TParams<float> &P, long plane)
+{
+    if (plane >= P.nplanes) return;   // uniform per wave
+    const int lane = threadIdx.x & 63;
+    const int a = (int)(plane % P.NA);
+    const long slab = plane / P.NA;
+    const float cx = P.theta[a / P.m], cy = P.theta[a % P.m];
+    const bool mx = cx < 0.f, my = cy < 0.f;
+    const float ax = fabsf(cx) * P.h_half_over_dx, ay = fabsf(cy) * P.h_half_over_dy;
+    const float idiag = 1.f / (1.f + ax + ay);
+    const float cq = ay * idiag;
+    float *base = P.psi + slab * P.NLINE + (long)a * PBS_PT;
+    const long NAPT = (long)P.NA * PBS_PT;
+    const int nx = P.nx, ny = P.ny;
+    const bool valid = lane < ny;
+    const int qc = my ? ny - 1 - lane : lane;
+    // scan multipliers: c^1, c^2, c^4, c^8 within rows of 16 lanes; c^((lane&15)+1), c^((lane&31)+1)
+    const float c1 = cq, c2 = c1 * c1, c4 = c2 * c2, c8 = c4 * c4;
+    float m16 = 1.f, m32 = 1.f;
+    {
+        const int e16 = (lane & 15) + 1, e32 = (lane & 31) + 1;
+        float pw = cq;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            if ((e16 >> i) & 1) m16 *= pw;
+            if ((e32 >> i) & 1) m32 *= pw;
+            pw *= pw;
+        }
+    }
+    auto addr = [&](int r) -> float * {
+        const int p = mx ? nx - 1 - r : r;
+        const long pq = (long)p * ny + qc;
+        return base + (pq / PBS_PT) * NAPT + (pq % PBS_PT);
+    };
+    float rb[16];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) rb[i] = (valid && i < nx) ? *addr(i) : 0.f;
+    float pm1 = 0.f, dxm = 0.f, ym1 = 0.f;
+    for (int r0 = 0; r0 < nx; r0 += 8) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) rb[8 + i] = (valid && r0 + 8 + i < nx) ? *addr(r0 + 8 + i) : 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (r0 + i >= nx) break;
+            const float p0 = rb[i], p1 = rb[i + 1];
+            const float left = dpp_f<0x138, 0xF>(p0);
+            const float right = dpp_f<0x130, 0xF>(p0);
+            const float dyp = superbee_slope(p0 - left, right - p0);
+            const float dym = dpp_f<0x138, 0xF>(dyp);
+            const float dxp = superbee_slope(p0 - pm1, p1 - p0);
+            const float R = p0 - ax * ((p0 - pm1) + (dxp - dxm)) - ay * ((p0 - left) + (dyp - dym));
+            float y = (R + ax * ym1) * idiag;
+            // y_q = b_q + c y_{q-1} along the row: Kogge-Stone within rows of 16, then row broadcasts
+            y += c1 * dpp_f<0x111, 0xF>(y);
+            y += c2 * dpp_f<0x112, 0xF>(y);
+            y += c4 * dpp_f<0x114, 0xF>(y);
+            y += c8 * dpp_f<0x118, 0xF>(y);
+            y += m16 * dpp_f<0x142, 0xA>(y);
+            y += m32 * dpp_f<0x143, 0xC>(y);
+            if (valid) *addr(r0 + i) = y;
+            pm1 = p0;
+            dxm = dxp;
+            ym1 = y;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) rb[i] = rb[8 + i];
+    }
+}
+
+__global__ __launch_bounds__(256) void tpass_dpp_kernel(TParams<float> P)
+{
+    tpass_dpp_body(P, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
+}
+
+// Same sweep when ny is 32 or 64 and nx a multiple of 8: a lane's address is affine in the row
+// (row stride = ny/32 lateral tiles), so each row costs one pointer increment and no guards; lanes
+// beyond ny (ny = 32) read a clamped in-range column and are zeroed.
+template <int NY>
+__device__ __forceinline__ void tpass_affine_body(const TParams<float> &P, long plane)
+{
+    if (plane >= P.nplanes) return;   // uniform per wave
+    const int lane = threadIdx.x & 63;
+    const int a = (int)(plane % P.NA);
+    const long slab = plane / P.NA;
+    const float cx = P.theta[a / P.m], cy = P.theta[a % P.m];
+    const bool mx = cx < 0.f, my = cy < 0.f;
+    const float ax = fabsf(cx) * P.h_half_over_dx, ay = fabsf(cy) * P.h_half_over_dy;
+    const float idiag = 1.f / (1.f + ax + ay);
+    const float cq = ay * idiag;
+    const long NAPT = (long)P.NA * PBS_PT;
+    const int nx = P.nx;
+    constexpr bool FULL = NY == 64;
+    const bool valid = FULL || lane < NY;
+    const int ql = FULL ? lane : (lane < NY ? lane : NY - 1);
+    const int qc = my ? NY - 1 - ql : ql;
+    const long RS = (long)(NY / 32) * NAPT;   // elements from row p to row p+1
+    float *row0 = P.psi + slab * P.NLINE + (long)a * PBS_PT + (long)(qc >> 5) * NAPT + (qc & 31);
+    const long step = mx ? -RS : RS;
+    float *ptr = mx ? row0 + (long)(nx - 1) * RS : row0;
+    const float c1 = cq, c2 = c1 * c1, c4 = c2 * c2, c8 = c4 * c4;
+    float m16 = 1.f, m32 = 1.f;
+    {
+        const int e16 = (lane & 15) + 1, e32 = (lane & 31) + 1;
+        float pw = cq;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            if ((e16 >> i) & 1) m16 *= pw;
+            if ((e32 >> i) & 1) m32 *= pw;
+            pw *= pw;
+        }
+    }
+    const float vmask = valid ? 1.f : 0.f;
+    float rb[16];
+    const float *ld = ptr;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        rb[i] = *ld * vmask;
+        ld += step;
+    }
+    float *st = ptr;
+    float pm1 = 0.f, dxm = 0.f, ym1 = 0.f;
+    for (int r0 = 0; r0 < nx; r0 += 8) {
+        const bool more = r0 + 8 < nx;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            rb[8 + i] = more ? *ld * vmask : 0.f;
+            if (more) ld += step;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float p0 = rb[i], p1 = rb[i + 1];
+            const float left = dpp_f<0x138, 0xF>(p0);
+            const float right = dpp_f<0x130, 0xF>(p0);
+            const float dyp = superbee_slope(p0 - left, right - p0);
+            const float dym = dpp_f<0x138, 0xF>(dyp);
+            const float dxp = superbee_slope(p0 - pm1, p1 - p0);
+            const float R = p0 - ax * ((p0 - pm1) + (dxp - dxm)) - ay * ((p0 - left) + (dyp - dym));
+            float y = (R + ax * ym1) * idiag;
+            y += c1 * dpp_f<0x111, 0xF>(y);
+            y += c2 * dpp_f<0x112, 0xF>(y);
+            y += c4 * dpp_f<0x114, 0xF>(y);
+            y += c8 * dpp_f<0x118, 0xF>(y);
+            y += m16 * dpp_f<0x142, 0xA>(y);
+            y += m32 * dpp_f<0x143, 0xC>(y);
+            if (FULL || valid) *st = y;
+            st += step;
+            pm1 = p0;
+            dxm = dxp;
+            ym1 = y;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) rb[i] = rb[8 + i];
+    }
+}
+
+template <int NY>
+__global__ __launch_bounds__(256) void tpass_affine_kernel(TParams<float> P)
+{
+    tpass_affine_body<NY>(P, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
+}
+
 template <typename T>
 hipError_t launch_tpass(const TParams<T> &P, hipStream_t st)
 {
+    if constexpr (sizeof(T) == 4) {
+        const dim3 grid((unsigned)((P.nplanes + 3) / 4));
+        if (P.nx % 8 == 0 && P.ny == 64) {
+            hipLaunchKernelGGL(tpass_affine_kernel<64>, grid, dim3(256), 0, st, P);
+            return hipGetLastError();
+        }
+        if (P.nx % 8 == 0 && P.ny == 32) {
+            hipLaunchKernelGGL(tpass_affine_kernel<32>, grid, dim3(256), 0, st, P);
+            return hipGetLastError();
+        }
+        if (P.ny <= 64) {
+            hipLaunchKernelGGL(tpass_dpp_kernel, grid, dim3(256), 0, st, P);
+            return hipGetLastError();
+        }
+    }
     const unsigned nb = (unsigned)((P.nplanes + 3) / 4);
     const int nseg = (P.ny + 63) / 64;
     switch (nseg) {
@@ -1227,6 +1414,26 @@ __global__ __launch_bounds__(64 * WPB) void tpass_batched_kernel(const BeamDev *
     tpass_body<float, NSEG>(P, (long)blockIdx.x * WPB + (threadIdx.x >> 6));
 }
 
+template <int NY, int WPB>
+__global__ __launch_bounds__(64 * WPB) void tpass_batched_affine_kernel(const BeamDev *__restrict__ beams,
+                                                                        BatchShape Sh, int s)
+{
+    const BeamDev &B = beams[blockIdx.y];
+    if (s >= B.nz) return;
+    TParams<float> P;
+    P.psi = B.psi;
+    P.theta = Sh.theta;
+    P.h_half_over_dx = 0.25f * B.dz / Sh.dx;
+    P.h_half_over_dy = 0.25f * B.dz / Sh.dy;
+    P.nx = Sh.nx;
+    P.ny = Sh.ny;
+    P.m = Sh.m;
+    P.NA = Sh.NA;
+    P.NLINE = Sh.NLINE;
+    P.nplanes = (long)Sh.ngen * B.G * 2 * Sh.NA;
+    tpass_affine_body<NY>(P, (long)blockIdx.x * WPB + (threadIdx.x >> 6));
+}
+
 template <int N, int PC>
 __global__ __launch_bounds__(256) void apass_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
 {
@@ -1284,6 +1491,16 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
         const unsigned nb = (unsigned)((planes + w - 1) / w);
 #define PBS_TB(NS, W) hipLaunchKernelGGL((tpass_batched_kernel<NS, W>), dim3(nb, nbeam), dim3(64 * W), 0, st, beams, Sh, s)
 #define PBS_TW(NS) do { if (w == 1) PBS_TB(NS, 1); else if (w == 2) PBS_TB(NS, 2); else PBS_TB(NS, 4); } while (0)
+#define PBS_TA(NY, W) hipLaunchKernelGGL((tpass_batched_affine_kernel<NY, W>), dim3(nb, nbeam), dim3(64 * W), 0, st, beams, Sh, s)
+#define PBS_TAW(NY) do { if (w == 1) PBS_TA(NY, 1); else if (w == 2) PBS_TA(NY, 2); else PBS_TA(NY, 4); } while (0)
+        if (Sh.nx % 8 == 0 && Sh.ny == 64) {
+            PBS_TAW(64);
+            return;
+        }
+        if (Sh.nx % 8 == 0 && Sh.ny == 32) {
+            PBS_TAW(32);
+            return;
+        }
         switch (nseg) {
         case 1: PBS_TW(1); break;
         case 2: PBS_TW(2); break;
@@ -1292,6 +1509,8 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
         }
 #undef PBS_TW
 #undef PBS_TB
+#undef PBS_TAW
+#undef PBS_TA
     };
     if (s < tu.max_nz) tpass();
     if (s < tu.max_nz) {

@@ -32,7 +32,10 @@ RAGGED = [dict(nx=6, ny=5, nth=6, ng=7, ngen=3, seed=1),
           dict(nx=33, ny=31, nth=4, ng=9, ngen=1, seed=3),
           # source product on the MFMA path (>= 128 angular unknowns), partial lateral tiles
           dict(nx=5, ny=7, nth=16, ng=4, ngen=3, seed=4),
-          dict(nx=4, ny=9, nth=32, ng=3, ngen=2, seed=5)]
+          dict(nx=4, ny=9, nth=32, ng=3, ngen=2, seed=5),
+          # row-affine transport sweeps (ny = 64 / 32, nx a multiple of 8)
+          dict(nx=16, ny=64, nth=6, ng=3, ngen=2, seed=6),
+          dict(nx=8, ny=32, nth=16, ng=3, ngen=2, seed=7)]
 
 
 @pytest.fixture(scope="module")
