@@ -193,6 +193,24 @@ class Oracle:
                      _p(self.kappa), _p(self.P1), _p(self.P2), _p(rho), _p(state), _p(dose))
         return dose.reshape(g.nz, g.nx, g.ny), state
 
+    def run_records(self, beam: dict, rho, state=None):
+        """Full march of a K = 1 grid (ngen = 2) with the per-layer records of the surrogate:
+        returns (dose, final state, rec [4, nz, nx, ny]) with rec = injected energy into
+        generation 1, energy and number content of generation 0 after the opening half-step,
+        deposit of generation 0 alone (MeV)."""
+        g = self.g
+        if g.ngen != 2:
+            raise ValueError("records need ngen = 2")
+        rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(g.nz, g.nx * g.ny)
+        if state is None:
+            state = self.initial(beam)
+        dose = np.zeros((g.nz, g.nx * g.ny))
+        rec = np.zeros((4, g.nz, g.nx * g.ny))
+        lib().og_run_records(C.byref(g), _p(self.E_face), _p(self.E_mid), _p(self.dE), _p(self.S_face),
+                             _p(self.sig_tr), _p(self.kappa), _p(self.P1), _p(self.P2), _p(rho), _p(state),
+                             _p(dose), _p(rec))
+        return dose.reshape(g.nz, g.nx, g.ny), state, rec.reshape(4, g.nz, g.nx, g.ny)
+
 
 def stopping(phys: dict, E: float) -> float:
     return lib().og_stopping(C.byref(_mk(Phys, phys)), C.c_double(E))

@@ -609,8 +609,21 @@ typedef struct {
  * sub-step, source included (the energy-flux difference of eq:(en_d)
  * applied to each species, summed; R14), accumulated into dep[pq] (MeV).
  */
+static void og_energy_all_rec(const og_grid *g, const og_tab *t, const double *rho, double h, double *state,
+                              double *dep, double *dep0, double *inj);
+
 static void og_energy_all(const og_grid *g, const og_tab *t, const double *rho, double h, double *state,
                           double *dep)
+{
+    og_energy_all_rec(g, t, rho, h, state, dep, NULL, NULL);
+}
+
+/* As og_energy_all; when non-NULL, dep0 also receives the deposit of generation 0 alone and inj the
+ * energy the source puts into generation 1 over the sub-step: the source term of the CN step,
+ * (h/2)(Q^n + Q*), enters the psi^1 row only, so its energy is (h/2) sum_g dE_g E_g (Q^n + Q*)_g
+ * times the cell measure (the energy-content functional of og_ecnt_line applied to it).     */
+static void og_energy_all_rec(const og_grid *g, const og_tab *t, const double *rho, double h, double *state,
+                              double *dep, double *dep0, double *inj)
 {
     long E = og_gen_elems(g), NP = og_np(g), NA = og_na(g), G = g->ng;
     double *before = malloc(sizeof(double) * E);
@@ -632,6 +645,20 @@ static void og_energy_all(const og_grid *g, const og_tab *t, const double *rho, 
         og_energy_cn(g, t->S_face, t->dE, t->kappa, rho, h, cur, k >= 1 ? Qn : NULL, k >= 1 ? Qs : NULL);
         og_energy_content(g, t->E_mid, t->dE, cur, e1);
         for (long pq = 0; pq < NP; pq++) dep[pq] += e0[pq] - e1[pq];
+        if (dep0 && k == 0)
+            for (long pq = 0; pq < NP; pq++) dep0[pq] += e0[pq] - e1[pq];
+        if (inj && k == 1) {
+            double w = og_dth(g) * og_dth(g) * og_dx(g) * og_dy(g);
+            for (long pq = 0; pq < NP; pq++) {
+                double s = 0.0;
+                for (long kk = 0; kk < G; kk++)
+                    for (long a = 0; a < NA; a++) {
+                        long o = (kk * NA + a) * NP + pq;
+                        s += t->dE[kk] * t->E_mid[kk] * (Qn[o] + Qs[o]);
+                    }
+                inj[pq] += 0.5 * h * s * w;
+            }
+        }
     }
     free(before); free(Qn); free(Qs); free(e0); free(e1);
 }
@@ -661,6 +688,38 @@ void og_run(const og_grid *g, const double *E_face, const double *E_mid, const d
         for (int k = 0; k < g->ngen; k++) og_angular_cn(g, sig_tr, r, dz, state + k * E);
         for (int k = 0; k < g->ngen; k++) og_transport_cn(g, 0.5 * dz, state + k * E);
         og_energy_all(g, &t, r, 0.5 * dz, state, dep);
+        for (long pq = 0; pq < NP; pq++) dose[(long)s * NP + pq] = dep[pq] / (r[pq] * vol);
+    }
+    free(dep);
+}
+
+/*
+ * og_run with per-layer records for the surrogate of generation 1 (ngen = 2), rec [4][nz][NP]:
+ *   0: energy injected into generation 1 by the source over both E half-steps of layer s,
+ *   1, 2: energy and number content of generation 0 after the first E half-step of layer s,
+ *   3: deposit of generation 0 alone in layer s (MeV).
+ */
+void og_run_records(const og_grid *g, const double *E_face, const double *E_mid, const double *dE,
+                    const double *S_face, const double *sig_tr, const double *kappa, const double *P1,
+                    const double *P2, const double *rho, double *state, double *dose, double *rec)
+{
+    og_tab t = {E_face, E_mid, dE, S_face, sig_tr, kappa, P1, P2};
+    long E = og_gen_elems(g), NP = og_np(g), L = (long)g->nz * NP;
+    double dz = g->dz, vol = og_dx(g) * og_dy(g) * g->dz;
+    double *dep = malloc(sizeof(double) * NP);
+    memset(rec, 0, sizeof(double) * 4 * L);
+    for (int s = 0; s < g->nz; s++) {
+        const double *r = rho + (long)s * NP;
+        double *inj = rec + (long)s * NP, *me = rec + L + (long)s * NP, *mn = rec + 2 * L + (long)s * NP;
+        double *d0 = rec + 3 * L + (long)s * NP;
+        memset(dep, 0, sizeof(double) * NP);
+        og_energy_all_rec(g, &t, r, 0.5 * dz, state, dep, d0, inj);
+        og_energy_content(g, E_mid, dE, state, me);
+        og_number_content(g, dE, state, mn);
+        for (int k = 0; k < g->ngen; k++) og_transport_cn(g, 0.5 * dz, state + k * E);
+        for (int k = 0; k < g->ngen; k++) og_angular_cn(g, sig_tr, r, dz, state + k * E);
+        for (int k = 0; k < g->ngen; k++) og_transport_cn(g, 0.5 * dz, state + k * E);
+        og_energy_all_rec(g, &t, r, 0.5 * dz, state, dep, d0, inj);
         for (long pq = 0; pq < NP; pq++) dose[(long)s * NP + pq] = dep[pq] / (r[pq] * vol);
     }
     free(dep);

@@ -1,0 +1,178 @@
+"""Pins of the CPU reference of the surrogate (oracle/surrogate.py, Oracle.run_records).
+
+The network reference is pinned to a library routine (scipy's 2-D cross-correlation), to brute
+force on tiny inputs and to central differences; the records of the march to the plain K = 0
+march, to the energy balance of generation 1 and to the CSDA energy loss of the first half-step;
+the depth filters to their closed form.
+"""
+import numpy as np
+import pytest
+from scipy.signal import correlate2d
+
+from oracle import surrogate as S
+from oracle.oracle import Oracle, stopping
+from paper_2504_00340_amd import inputs as I
+
+
+def rnd(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def test_conv_single_channel_is_scipy_correlate():
+    r = rnd(1)
+    x = r.normal(size=(7, 9))
+    w = r.normal(size=(3, 3))
+    got = S.conv3x3(x[None, :, :, None], w[None, None], np.zeros(1))[0, :, :, 0]
+    ref = correlate2d(x, w, mode="same", boundary="fill", fillvalue=0.0)
+    assert np.abs(got - ref).max() < 1e-13
+
+
+def test_conv_channels_brute_force():
+    r = rnd(2)
+    n, H, W, ci, co = 2, 4, 5, 3, 4
+    x = r.normal(size=(n, H, W, ci))
+    w = r.normal(size=(co, ci, 3, 3))
+    b = r.normal(size=co)
+    got = S.conv3x3(x, w, b)
+    ref = np.zeros((n, H, W, co))
+    for a in range(n):
+        for yy in range(H):
+            for xx in range(W):
+                for o in range(co):
+                    s = b[o]
+                    for ky in range(3):
+                        for kx in range(3):
+                            y2, x2 = yy + ky - 1, xx + kx - 1
+                            if 0 <= y2 < H and 0 <= x2 < W:
+                                s += sum(x[a, y2, x2, i] * w[o, i, ky, kx] for i in range(ci))
+                    ref[a, yy, xx, o] = s
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_param_layout():
+    assert S.param_count() == 32 * 8 * 9 + 32 + 2 * (32 * 32 * 9 + 32) + 32 * 9 + 1
+    p = np.arange(S.param_count(), dtype=np.float64)
+    assert np.array_equal(S.flatten(S.unflatten(p)), p)
+
+
+def test_gradient_central_differences():
+    r = rnd(3)
+    n, H, W = 2, 4, 5
+    p = r.normal(size=S.param_count()) * 0.2
+    x = r.normal(size=(n, H, W, 8))
+    t = r.normal(size=(n, H, W))
+    loss, g = S.loss_grad(p, x, t)
+    assert np.isclose(loss, ((S.forward(p, x)[0] - t) ** 2).mean())
+    # parameters of every layer, weights and biases
+    idx = []
+    o = 0
+    for ci, co in S.LAYERS:
+        nw = co * ci * 9
+        idx += list(r.choice(nw, 12, replace=False) + o)
+        idx += list(r.choice(co, min(co, 3), replace=False) + o + nw)
+        o += nw + co
+    eps = 1e-6
+    for k in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[k] += eps
+        pm[k] -= eps
+        fd = (S.loss_grad(pp, x, t)[0] - S.loss_grad(pm, x, t)[0]) / (2 * eps)
+        assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(g[k])), (k, fd, g[k])
+
+
+def _small_k1(nz=6, e0=30.0, nth=8, th_half=0.6, x_half=2.0, seed=None):
+    c = I.small(nx=12, ny=12, nth=nth, ng=12, nz=nz, ngen=2, e0=e0, e_hi=e0 + 8.0, x_half=x_half, y_half=x_half,
+                th_half=th_half, depth=0.1 * nz, seed=seed)
+    return c
+
+
+def test_records_gen0_deposit_is_the_k0_march():
+    c = _small_k1(seed=5)
+    g = c["grid"]
+    o1 = Oracle(g, c["phys"])
+    dose1, _, rec = o1.run_records(c["beam"], c["rho"])
+    g0 = dict(g, ngen=1)
+    dose0, _ = Oracle(g0, c["phys"]).run(c["beam"], c["rho"])
+    vol = o1.dx * o1.dy * g["dz"]
+    e0 = dose0 * c["rho"] * vol
+    assert np.abs(rec[3] - e0).max() <= 1e-13 * np.abs(e0).max()
+    # the plain march with records gives the plain dose
+    dose_plain, _ = o1.run(c["beam"], c["rho"])
+    assert np.array_equal(dose1, dose_plain)
+
+
+def test_records_energy_balance_of_generation1():
+    """Every MeV injected into generation 1 is deposited by it, still in it at the end, or has left
+    through the angular / lateral boundaries during T and A:  sum(E_total - E0 + I) + Ecnt_1(end)
+    + leak = sum I.  The leak is measured by stepping the same march with the sub-operators and
+    taking the energy content of generation 1 before and after each T and A sub-step."""
+    c = _small_k1(seed=6)
+    g = c["grid"]
+    o = Oracle(g, c["phys"])
+    dose, st_end, rec = o.run_records(c["beam"], c["rho"])
+    vol = o.dx * o.dy * g["dz"]
+    own1 = (dose * c["rho"] * vol - rec[3] + rec[0]).sum()
+    inj = rec[0].sum()
+    # the same march, sub-step by sub-step, measuring what T and A remove from generation 1
+    st = o.initial(c["beam"])
+    R = c["rho"].reshape(g["nz"], -1)
+    h = 0.5 * g["dz"]
+    leak = 0.0
+    for s in range(g["nz"]):
+        r = np.ascontiguousarray(R[s])
+        o.energy_all(st, r, h)
+        before = o.energy_content(st[1]).sum()
+        for k in range(2):
+            o.transport_cn(st[k], h)
+            o.angular_cn(st[k], r, 2 * h)
+            o.transport_cn(st[k], h)
+        leak += before - o.energy_content(st[1]).sum()
+        o.energy_all(st, r, h)
+    assert np.array_equal(st, st_end)
+    left = o.energy_content(st[1]).sum()
+    assert inj > 0 and 0 <= leak < 0.01 * inj
+    assert abs(own1 + left + leak - inj) <= 1e-12 * inj
+
+
+def test_records_first_layer_moments():
+    """After the opening half-step of layer 0 the primaries number 1 minus the removal and their
+    mean energy is E0 less the CSDA loss over dz/2 (to first order)."""
+    c = _small_k1(nz=2, e0=30.0)
+    g, ph = c["grid"], c["phys"]
+    o = Oracle(g, ph)
+    _, _, rec = o.run_records(c["beam"], c["rho"])
+    n0 = rec[2, 0].sum()
+    kap = ph["kappa0"] * (1 - np.exp(-30.0 / ph["e_c"]))
+    assert 1.0 - 1.5 * kap * 0.5 * g["dz"] < n0 <= 1.0 + 1e-12
+    ebar = rec[1, 0].sum() / n0
+    loss = stopping(ph, 30.0) * 0.5 * g["dz"]
+    assert abs(ebar - (30.0 - loss)) < 0.05 + 0.2 * loss
+
+
+def test_depth_filter_closed_form():
+    nz, nx, ny = 9, 3, 2
+    rec = np.zeros((4, nz, nx, ny))
+    rec[0] = 2.0
+    rec[2] = 1.0
+    rho = np.full((nz, nx, ny), 1.3)
+    dz = 0.25
+    X = S.features(rec, rho, dz, 0.01)
+    s = np.arange(nz)[:, None, None]
+    for j, L in enumerate(S.FILTER_L):
+        a = np.exp(-1.3 * dz / L)
+        assert np.allclose(X[..., 3 + j], (1 - a ** (s + 1)) * np.ones((nz, nx, ny)), rtol=1e-13, atol=1e-15)
+    assert np.allclose(X[..., 2], 1.0)
+
+
+def test_features_are_causal_in_depth():
+    r = rnd(7)
+    nz, nx, ny = 8, 4, 4
+    rec = np.abs(r.normal(size=(4, nz, nx, ny)))
+    rec[0, 0, 0, 0] = 10.0    # fixes the scale c
+    rho = r.uniform(0.5, 1.5, size=(nz, nx, ny))
+    X = S.features(rec, rho, 0.1, 0.012)
+    rec2 = rec.copy()
+    rec2[0, 5] *= 1.7
+    X2 = S.features(rec2, rho, 0.1, 0.012)
+    assert np.array_equal(X[:5], X2[:5])
+    assert not np.array_equal(X[5:, ..., 3:6], X2[5:, ..., 3:6])
