@@ -194,6 +194,91 @@ pbs_status pbs_batch_tuning(const pbs_batch *batch, int *out3);
 const char *pbs_batch_last_error(const pbs_batch *batch);
 void pbs_batch_destroy(pbs_batch *batch);
 
+/* ------------------------------------------------- surrogate of the scattered generation
+ * A K = 1 march (ngen = 2: primaries plus the first catastrophic-scatter generation of the
+ * scattering decomposition eqn:(pri-se), section 3.1) can replace the scattered generation by a
+ * learned estimate of its net deposit.  This is not part of the paper; it is an add-on of this
+ * library, checked against the plain march.
+ *
+ * Per voxel layer s and lateral cell, the primary march records (FP64):
+ *   I      the energy the nuclear re-emission injects into generation 1 during the two energy
+ *          half-steps of layer s (the source functional of App. A.4 summed over destination
+ *          angles, which the angular law conserves),
+ *   M_E, M_N  the energy and number content of the primaries after the opening energy
+ *          half-step of layer s: sum over groups and angles of dE (E_g psi^1 + dE psi^2 / 6) and
+ *          of dE psi^1, times dth^2 dx dy,
+ *   E0     the deposit of the primary generation alone.
+ * Features of slice s (BF16, 8 channels per cell, image [nx][ny], ny <= 64):
+ *   0: M_E kappa0 dz / c,  1: rho,  2: I / c,  3-5: F_j / c with the causal depth filters
+ *   F_j(s) = a F_j(s-1) + (1 - a) I(s), a = exp(-rho dz / L_j), L = 0.5, 2, 6 cm,
+ *   6: (M_E / M_N) / 250 MeV where M_N > 1e-4 max M_N (else 0),  7: zero;
+ *   c = max over the beam of I.
+ * Target (FP32): (E_total - E0 + I) / c, the energy generation 1 deposits itself in the voxel.
+ * Surrogate dose: E0 - I + c * net(features), from a march of the primaries only.
+ * Residual: |sum c * net - (1 - leak) sum I| / sum I (leak from the weights).  Above the
+ * tolerance the beam is marched again with both generations (the plain method), so the result is
+ * then exactly the plain K = 1 dose.
+ *
+ * Network (weights blob = pbs_net_header + nparam FP32 values): 3x3 convolutions, zero padding,
+ * 8 -> 32 -> 32 -> 32 -> 1 channels, ReLU after the first three; parameters in the order
+ * w0 [32][8][3][3], b0 [32], w1 [32][32][3][3], b1, w2 [32][32][3][3], b2, w3 [1][32][3][3], b3 [1].
+ * BF16 operands, FP32 accumulation (v_mfma_f32_16x16x32_bf16). */
+#define PBS_NET_MAGIC 0x4E534250u /* "PBSN" */
+#define PBS_NET_VERSION 1u
+#define PBS_NET_CIN 8
+typedef struct pbs_net_header {
+    unsigned int magic, version, nparam, nfeat; /* nfeat = 7 */
+    double leak;                                /* mean fraction of sum I that generation 1 does not deposit */
+    double reserved[5];
+} pbs_net_header;                               /* 64 bytes */
+
+/* Must be called after pbs_create and before pbs_workspace_bytes / pbs_bind (it enlarges the
+ * workspace).  The context must have ngen = 2 and ny <= 64.
+ *   weights = NULL, bytes = 0: recording mode.  pbs_run_beam marches the plain method and keeps
+ *       the per-slice records; pbs_surrogate_sample then writes features and targets.
+ *   weights = blob: surrogate mode.  pbs_run_beam marches the primaries only, evaluates the
+ *       network and checks the residual against residual_tol (finite, >= 0), falling back to the
+ *       plain march.  pbs_step_depth is refused (PBS_ESTATE): the surrogate acts on whole beams.
+ * The blob is copied. */
+pbs_status pbs_set_surrogate(pbs_ctx *ctx, const void *weights, size_t bytes, double residual_tol);
+
+/* Recording mode, after pbs_run_beam: features [nz][nx*ny][8] BF16 into dev_x and targets
+ * [nz][nx*ny] FP32 into dev_target (device memory, 16-byte aligned, n_slices = nz); asynchronous. */
+pbs_status pbs_surrogate_sample(pbs_ctx *ctx, void *dev_x, float *dev_target, size_t n_slices);
+
+/* Either mode, after pbs_run_beam: the FP64 records [4][nz][nx*ny] = I, M_E, M_N, E0 (MeV) into
+ * a host array (E0 is recorded in recording mode only; zero otherwise).  Synchronises. */
+pbs_status pbs_surrogate_records(pbs_ctx *ctx, double *out, size_t n);
+
+/* After pbs_run_beam (synchronises): out[0] residual, [1] 1 if the plain march was used,
+ * [2] energy budget (1 - leak) sum I, [3] network energy sum c * net, [4] c, [5] sum I,
+ * [6] energy generation 1 deposited itself (recording mode; else NaN), [7] leak.  n <= 8. */
+pbs_status pbs_surrogate_report(pbs_ctx *ctx, double *out, int n);
+
+/* Training of the network on one GPU (the same kernels as the surrogate, plus the data and weight
+ * gradients and an Adam update).  Images are H x W (W <= 64) with 8 BF16 input channels, one FP32
+ * output channel; loss = mean over pixels of (y - t)^2.  The caller owns the workspace. */
+typedef struct pbs_net pbs_net;
+pbs_status pbs_net_param_count(size_t *count);
+pbs_status pbs_net_create(int H, int W, int max_batch, pbs_net **out);
+pbs_status pbs_net_workspace_bytes(const pbs_net *net, size_t *bytes);
+pbs_status pbs_net_bind(pbs_net *net, void *dev_workspace, size_t bytes, void *hip_stream);
+/* FP32 parameters in the order above (host); resets the Adam state. */
+pbs_status pbs_net_set_params(pbs_net *net, const float *params, size_t count);
+pbs_status pbs_net_get_params(pbs_net *net, float *params, size_t count);
+/* y [n][H][W] FP32 = network(x [n][H][W][8] BF16), device pointers (x 16-byte aligned); asynchronous. */
+pbs_status pbs_net_forward(pbs_net *net, const void *dev_x, float *dev_y, int n);
+/* Gradient of the loss with respect to every parameter (host, parameter order) and the loss;
+ * no update.  Synchronises. */
+pbs_status pbs_net_gradient(pbs_net *net, const void *dev_x, const float *dev_t, int n, float *grad, size_t count,
+                            double *loss);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) with learning rate lr on the minibatch; the loss
+ * before the step goes to dev_loss (device double, may be NULL).  Asynchronous. */
+pbs_status pbs_net_train_step(pbs_net *net, const void *dev_x, const float *dev_t, int n, double lr,
+                              double *dev_loss);
+const char *pbs_net_last_error(const pbs_net *net);
+void pbs_net_destroy(pbs_net *net);
+
 /* Text of the last error of this context (never NULL). */
 const char *pbs_last_error(const pbs_ctx *ctx);
 

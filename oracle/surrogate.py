@@ -62,8 +62,19 @@ def conv3x3(x, w, b):
     return out
 
 
-def forward(p, x):
-    """y [n, H, W] and the activations [x, a1, a2, a3] (inputs of the four layers)."""
+def bf16(a):
+    """Round float64 values to bfloat16 (through float32, round to nearest, ties to even), returned
+    as float64: keep the top 16 bits of the float32 pattern after adding 0x7FFF plus the lowest
+    kept bit."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(a))
+
+
+def forward(p, x, act_bf16=False):
+    """y [n, H, W] and the activations [x, a1, a2, a3] (inputs of the four layers).  act_bf16:
+    the hidden activations are stored as bfloat16 (the network a BF16 implementation evaluates)."""
     L = unflatten(p)
     acts = [np.asarray(x, dtype=np.float64)]
     h = acts[0]
@@ -71,16 +82,19 @@ def forward(p, x):
         z = conv3x3(h, w, b)
         if i < 3:
             h = np.maximum(z, 0.0)
+            if act_bf16:
+                h = bf16(h)
             acts.append(h)
         else:
             h = z
     return h[..., 0], acts
 
 
-def loss_grad(p, x, t):
-    """(loss, gradient with respect to the flat parameters)."""
+def loss_grad(p, x, t, act_bf16=False):
+    """(loss, gradient with respect to the flat parameters).  With act_bf16 the forward stores
+    BF16 activations and the backward passes through the rounding as the identity."""
     L = unflatten(p)
-    y, acts = forward(p, x)
+    y, acts = forward(p, x, act_bf16)
     npx = y.size
     d = y - np.asarray(t, dtype=np.float64)
     loss = float((d * d).sum() / npx)

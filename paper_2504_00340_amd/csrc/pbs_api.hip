@@ -10,6 +10,7 @@
 
 #include "pbs_common.h"
 #include "pbs_ctx.h"
+#include "pbs_net_internal.h"
 #include "pbsplit.h"
 
 using namespace pbs;
@@ -178,6 +179,29 @@ void layout(pbs_ctx *c)
     o = align256(o + (size_t)c->g.nz * c->NPpad * T);
     c->o_rhoD = o;
     o = align256(o + (size_t)c->g.nz * c->NP * sizeof(double));
+    if (c->sur) {
+        const size_t slab = (size_t)c->g.nz * c->NP;
+        c->o_fl = o;
+        o = align256(o + (size_t)4 * c->NLINE * sizeof(double));
+        c->o_frec = o;
+        o = align256(o + 4 * slab * sizeof(double));
+        c->o_scal = o;
+        o = align256(o + 16 * sizeof(double));
+        if (c->sur == 2) {
+            c->o_sx = o;
+            o = align256(o + slab * NET_CX * 2);
+            c->o_sy = o;
+            o = align256(o + slab * sizeof(float));
+            c->o_sa = o;
+            o = align256(o + slab * NET_CH * 2);
+            c->o_sb = o;
+            o = align256(o + slab * NET_CH * 2);
+            c->o_spk = o;
+            o = align256(o + net_packed_bytes());
+            c->o_smaster = o;
+            o = align256(o + net_param_count() * sizeof(float));
+        }
+    }
     // T tables
     size_t e = 0;
     c->t_Sm = e; e += G;
@@ -205,6 +229,7 @@ void layout(pbs_ctx *c)
     c->d_E1 = d; d += G;
     c->d_E2 = d; d += G;
     c->d_lat = d; d += c->NP;
+    c->d_wmom = d; d += 3 * G;
     c->d_count = d;
     c->o_tabD = o;
     o = align256(o + d * sizeof(double));
@@ -253,6 +278,11 @@ pbs_status upload_tables(pbs_ctx *c)
     std::memcpy(&d[c->d_A], c->dA.data(), c->G() * sizeof(double));
     std::memcpy(&d[c->d_B], c->dB.data(), c->G() * sizeof(double));
     std::memcpy(&d[c->d_Inj], c->dInj.data(), c->G() * sizeof(double));
+    for (int k = 0; k < c->G(); ++k) {
+        d[c->d_wmom + k] = c->E_mid[k] * c->dE[k];
+        d[c->d_wmom + c->G() + k] = c->dE[k];
+        d[c->d_wmom + 2 * c->G() + k] = c->dE[k] * c->dE[k] / 6.0;
+    }
     std::vector<unsigned short> bf;
     if (c->Kpb > 0) {
         // P2 as hi + lo bfloat16 (round to nearest even), row-major [Mp][Kpb]: row = destination
@@ -320,7 +350,7 @@ EParams<T> eparams(pbs_ctx *c, int k, int lay_c, int lay_o, double h)
     double *db = c->tabD();
     P.psi = c->psi<T>(k);
     P.Q = (k > 0) ? c->Q<T>() : nullptr;
-    P.W = (k + 1 < c->g.ngen) ? c->W<T>() : nullptr;
+    P.W = (k + 1 < c->kact) ? c->W<T>() : nullptr;
     P.Wh = P.Wl = nullptr;
     P.NOCT = c->NOCT;
     if (P.W && c->Kpb > 0 && c->src_mode == PBS_SRC_BF16X3) {
@@ -346,6 +376,13 @@ EParams<T> eparams(pbs_ctx *c, int k, int lay_c, int lay_o, double h)
     P.G = c->G();
     P.NLINE = c->NLINE;
     P.NAPT = (long)c->NA * PBS_PT;
+    if (c->feat_on && k == 0) {
+        P.inj_c = c->fline(0);
+        P.inj_o = c->fline(1);
+        P.mom_e = c->fline(2);
+        P.mom_n = c->fline(3);
+        P.wmom = db + c->d_wmom;
+    }
     return P;
 }
 
@@ -354,7 +391,7 @@ EParams<T> eparams(pbs_ctx *c, int k, int lay_c, int lay_o, double h)
 template <typename T>
 pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
 {
-    const int K1 = c->g.ngen;
+    const int K1 = c->kact;
     for (int k = 0; k < K1; ++k) {
         EParams<T> P = eparams<T>(c, k, (mode & MODE_CLOSE) ? lay_c : -1, (mode & MODE_OPEN) ? lay_o : -1, h);
         {
@@ -394,6 +431,22 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
         HIPCHK(c, launch_dose_reduce(c->edep(lay_c), c->dep(0, 0), K1, c->NA, c->NLINE, c->NP, c->stream));
     if (mode & MODE_OPEN)
         HIPCHK(c, launch_dose_reduce(c->edep(lay_o), c->dep(1, 0), K1, c->NA, c->NLINE, c->NP, c->stream));
+    if (c->feat_on) {
+        // per-layer surrogate records: injected energy of both halves, moments after the opening half,
+        // and the deposit of the primaries alone when further generations are marched
+        const int NA = c->NA, NP = c->NP;
+        const long NL = c->NLINE;
+        if (mode & MODE_CLOSE) {
+            HIPCHK(c, launch_dose_reduce(c->frec(0, lay_c), c->fline(0), 1, NA, NL, NP, c->stream));
+            if (K1 > 1) HIPCHK(c, launch_dose_reduce(c->frec(3, lay_c), c->dep(0, 0), 1, NA, NL, NP, c->stream));
+        }
+        if (mode & MODE_OPEN) {
+            HIPCHK(c, launch_dose_reduce(c->frec(0, lay_o), c->fline(1), 1, NA, NL, NP, c->stream));
+            HIPCHK(c, launch_dose_reduce(c->frec(1, lay_o), c->fline(2), 1, NA, NL, NP, c->stream));
+            HIPCHK(c, launch_dose_reduce(c->frec(2, lay_o), c->fline(3), 1, NA, NL, NP, c->stream));
+            if (K1 > 1) HIPCHK(c, launch_dose_reduce(c->frec(3, lay_o), c->dep(1, 0), 1, NA, NL, NP, c->stream));
+        }
+    }
     return PBS_OK;
 }
 
@@ -410,7 +463,7 @@ pbs_status transport(pbs_ctx *c, double h)
     P.m = c->m;
     P.NA = c->NA;
     P.NLINE = c->NLINE;
-    P.nplanes = (long)c->g.ngen * c->G() * 2 * c->NA;
+    P.nplanes = (long)c->kact * c->G() * 2 * c->NA;
     ProfScope ps(c, PBS_K_TPASS);
     HIPCHK(c, launch_tpass<T>(P, c->stream));
     return PBS_OK;
@@ -434,11 +487,11 @@ pbs_status angular(pbs_ctx *c, int layer, double h)
     ProfScope ps(c, PBS_K_APASS);
     if constexpr (sizeof(T) == 4) {
         if (c->g.nth == 32) {
-            HIPCHK(c, launch_apass_mfma32(P, tb + c->t_K32, (long)c->g.ngen * c->G() * 2, c->stream));
+            HIPCHK(c, launch_apass_mfma32(P, tb + c->t_K32, (long)c->kact * c->G() * 2, c->stream));
             return PBS_OK;
         }
     }
-    HIPCHK(c, launch_apass<T>(P, c->g.nth, (long)c->g.ngen * c->G() * 2, c->stream));
+    HIPCHK(c, launch_apass<T>(P, c->g.nth, (long)c->kact * c->G() * 2, c->stream));
     return PBS_OK;
 }
 
@@ -480,6 +533,7 @@ pbs_status start_beam(pbs_ctx *c, const pbs_beam &b)
     const pbs_grid &g = c->g;
     HIPCHK(c, launch_fill<T>(c->psi<T>(0), T(0), (long)g.ngen * c->G() * 2 * c->NLINE, c->stream));
     HIPCHK(c, launch_fill<double>(c->edep(0), 0.0, (long)g.nz * c->NP, c->stream));
+    if (c->sur) HIPCHK(c, launch_fill<double>(c->frec(0, 0), 0.0, 4L * g.nz * c->NP, c->stream));
     if (g.ngen > 1) {
         // padding source nodes of the split layout are never written and must stay zero
         const size_t wbytes = c->o_Q - c->o_W;
@@ -575,6 +629,74 @@ pbs_status set_phantom(pbs_ctx *c, const double *rho)
     return PBS_OK;
 }
 
+// ------------------------------------------------------------------ surrogate of generation 1
+template <typename T>
+pbs_status march_rest(pbs_ctx *c)
+{
+    pbs_status r = steps<T>(c, c->g.nz - c->step);
+    if (r != PBS_OK) return r;
+    return close_beam<T>(c);
+}
+
+SurFeatIn feat_inputs(pbs_ctx *c, bool with_target)
+{
+    SurFeatIn F;
+    F.finj = c->frec(0, 0);
+    F.fme = c->frec(1, 0);
+    F.fmn = c->frec(2, 0);
+    F.rho = c->rhoD();
+    F.edep = with_target ? c->edep(0) : nullptr;
+    F.edep0 = with_target ? c->frec(3, 0) : nullptr;
+    F.nz = c->g.nz;
+    F.NP = c->NP;
+    F.dz = c->g.dz;
+    F.k0dz = c->ph.kappa0 * c->g.dz;
+    return F;
+}
+
+// Surrogate mode: march the primaries alone while recording, evaluate the network on every slice,
+// check the energy residual; accept (dose = E0 - I + c net) or march again with both generations.
+template <typename T>
+pbs_status run_surrogate(pbs_ctx *c)
+{
+    const long slab = (long)c->g.nz * c->NP;
+    c->kact = 1;
+    c->feat_on = true;
+    pbs_status r = march_rest<T>(c);
+    c->kact = c->g.ngen;
+    c->feat_on = false;
+    if (r != PBS_OK) return r;
+    double *sc = c->scal();
+    HIPCHK(c, sur_scalars(c->frec(0, 0), c->frec(2, 0), nullptr, nullptr, slab, sc, c->stream));
+    __bf16 *X = reinterpret_cast<__bf16 *>(c->ws + c->o_sx);
+    __bf16 *A = reinterpret_cast<__bf16 *>(c->ws + c->o_sa), *B = reinterpret_cast<__bf16 *>(c->ws + c->o_sb);
+    float *Y = reinterpret_cast<float *>(c->ws + c->o_sy);
+    HIPCHK(c, sur_features(feat_inputs(c, false), sc, X, nullptr, c->stream));
+    NetPacked P;
+    net_carve(c->ws + c->o_spk, P);
+    HIPCHK(c, net_forward(P, X, A, B, A, Y, c->g.nz, c->g.nx, c->g.ny, c->stream));
+    HIPCHK(c, sur_sum(Y, slab, sc + 4, c->stream));
+    double h[5];
+    HIPCHK(c, hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double cb = h[0] > 0.0 ? h[0] : 1.0;
+    const double einj = h[2], epred = cb * h[4], budget = (1.0 - c->sur_leak) * einj;
+    double res = budget > 0.0 ? std::fabs(epred - budget) / budget : (epred == 0.0 ? 0.0 : INFINITY);
+    if (!std::isfinite(epred)) res = INFINITY;
+    const double rep[8] = {res, 0.0, budget, epred, cb, einj, NAN, c->sur_leak};
+    std::memcpy(c->sur_rep, rep, sizeof(rep));
+    if (res <= c->sur_tol) {
+        HIPCHK(c, sur_combine(c->edep(0), c->frec(0, 0), Y, sc, slab, c->stream));
+        return PBS_OK;
+    }
+    // fallback: the plain method from the start
+    if ((r = start_beam<T>(c, c->beam)) != PBS_OK) return r;
+    c->step = 0;
+    if ((r = march_rest<T>(c)) != PBS_OK) return r;
+    c->sur_rep[1] = 1.0;
+    return PBS_OK;
+}
+
 #define DISPATCH(c, fn, ...) ((c)->prec == PBS_FP64 ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__))
 
 }  // namespace
@@ -621,6 +743,7 @@ pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precisi
     c->dy = 2.0 * g.y_half / g.ny;
     c->dth = 2.0 * g.th_half / g.nth;
     c->NOCT = (c->NA + 7) / 8;
+    c->kact = g.ngen;
     if (c->NA >= 128) {   // source product on MFMA
         c->Kp = (c->NA + 15) / 16 * 16;
         c->Mp = (c->NA + 127) / 128 * 128;
@@ -658,6 +781,15 @@ pbs_status pbs_bind(pbs_ctx *c, void *ws, size_t bytes, void *stream)
     c->state = ST_CREATED;
     pbs_status r = DISPATCH(c, upload_tables, c);
     if (r != PBS_OK) return r;
+    if (c->sur == 2) {
+        float *m = reinterpret_cast<float *>(c->ws + c->o_smaster);
+        NetPacked P;
+        net_carve(c->ws + c->o_spk, P);
+        HIPCHK(c, hipMemcpyAsync(m, c->sur_params.data(), c->sur_params.size() * sizeof(float), hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, net_pack(m, P, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     c->state = ST_BOUND;
     return PBS_OK;
 }
@@ -684,8 +816,12 @@ pbs_status pbs_set_beam(pbs_ctx *c, const pbs_beam *b)
     if (!std::isfinite(b->e0) || !finite_pos(b->sigma_e) || !std::isfinite(b->x0) || !std::isfinite(b->y0) ||
         !finite_pos(b->sigma_x) || !finite_pos(b->sigma_y))
         return fail(c, PBS_EINVAL, "bad beam parameters");
+    c->kact = c->g.ngen;
+    c->feat_on = false;
     pbs_status r = DISPATCH(c, start_beam, c, *b);
     if (r != PBS_OK) return r;
+    c->beam = *b;
+    for (double &v : c->sur_rep) v = NAN;
     c->step = 0;
     c->closed = false;
     c->state = ST_BEAM;
@@ -697,8 +833,11 @@ pbs_status pbs_step_depth(pbs_ctx *c, int n, int *step_out)
     if (!c) return PBS_EINVAL;
     if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "step_depth before set_beam");
     if (c->closed) return fail(c, PBS_ESTATE, "beam already finished by run_beam");
+    if (c->sur == 2) return fail(c, PBS_ESTATE, "a surrogate context marches whole beams (pbs_run_beam)");
     if (n < 0 || n > c->g.nz - c->step) return fail(c, PBS_EINVAL, "n must be in [0, nz - steps done]");
+    c->feat_on = c->sur == 1;
     pbs_status r = DISPATCH(c, steps, c, n);
+    c->feat_on = false;
     if (step_out) *step_out = c->step;
     return r;
 }
@@ -708,11 +847,97 @@ pbs_status pbs_run_beam(pbs_ctx *c)
     if (!c) return PBS_EINVAL;
     if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "run_beam before set_beam");
     if (c->closed) return fail(c, PBS_ESTATE, "beam already finished by run_beam");
-    pbs_status r = DISPATCH(c, steps, c, c->g.nz - c->step);
-    if (r != PBS_OK) return r;
-    r = DISPATCH(c, close_beam, c);
+    pbs_status r;
+    if (c->sur == 2) {
+        r = DISPATCH(c, run_surrogate, c);
+    } else {
+        c->feat_on = c->sur == 1;
+        r = DISPATCH(c, march_rest, c);
+        c->feat_on = false;
+        if (r == PBS_OK && c->sur == 1)
+            HIPCHK(c, sur_scalars(c->frec(0, 0), c->frec(2, 0), c->edep(0), c->frec(3, 0), (long)c->g.nz * c->NP,
+                                  c->scal(), c->stream));
+    }
     if (r != PBS_OK) return r;
     c->closed = true;
+    return PBS_OK;
+}
+
+pbs_status pbs_set_surrogate(pbs_ctx *c, const void *weights, size_t bytes, double tol)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->ws) return fail(c, PBS_ESTATE, "set_surrogate must precede bind");
+    if (c->g.ngen != 2) return fail(c, PBS_EINVAL, "the surrogate replaces generation 1 of a K = 1 grid (ngen = 2)");
+    if (c->g.ny > 64) return fail(c, PBS_EUNSUPPORTED, "surrogate images are at most 64 cells wide (ny <= 64)");
+    if (!weights) {
+        if (bytes != 0) return fail(c, PBS_EINVAL, "weights NULL with nonzero size");
+        c->sur = 1;
+        c->sur_params.clear();
+        c->sur_leak = 0.0;
+        c->sur_tol = 0.0;
+        layout(c);
+        return PBS_OK;
+    }
+    if (!std::isfinite(tol) || tol < 0) return fail(c, PBS_EINVAL, "residual tolerance must be finite and >= 0");
+    pbs_net_header h;
+    if (bytes < sizeof(h)) return fail(c, PBS_EINVAL, "weights blob too small");
+    std::memcpy(&h, weights, sizeof(h));
+    const size_t np = net_param_count();
+    if (h.magic != PBS_NET_MAGIC || h.version != PBS_NET_VERSION || h.nparam != np || h.nfeat != (unsigned)SUR_NFEAT)
+        return fail(c, PBS_EINVAL, "weights blob header does not match this network");
+    if (bytes != sizeof(h) + np * sizeof(float)) return fail(c, PBS_EINVAL, "weights blob size mismatch");
+    if (!std::isfinite(h.leak) || h.leak < 0 || h.leak >= 1) return fail(c, PBS_EINVAL, "leak must be in [0, 1)");
+    std::vector<float> p(np);
+    std::memcpy(p.data(), (const char *)weights + sizeof(h), np * sizeof(float));
+    for (float v : p)
+        if (!std::isfinite(v)) return fail(c, PBS_EINVAL, "weights must be finite");
+    c->sur = 2;
+    c->sur_params.swap(p);
+    c->sur_leak = h.leak;
+    c->sur_tol = tol;
+    layout(c);
+    return PBS_OK;
+}
+
+pbs_status pbs_surrogate_sample(pbs_ctx *c, void *dev_x, float *dev_t, size_t n_slices)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->sur != 1) return fail(c, PBS_ESTATE, "sample needs a context in recording mode");
+    if (c->state < ST_BEAM || !c->closed) return fail(c, PBS_ESTATE, "sample before run_beam");
+    if (!dev_x || !dev_t || ((uintptr_t)dev_x & 15) || ((uintptr_t)dev_t & 15))
+        return fail(c, PBS_EINVAL, "feature / target buffers must be non-NULL and 16-byte aligned");
+    if (n_slices != (size_t)c->g.nz) return fail(c, PBS_EINVAL, "n_slices must equal nz");
+    HIPCHK(c, sur_features(feat_inputs(c, true), c->scal(), reinterpret_cast<__bf16 *>(dev_x), dev_t, c->stream));
+    return PBS_OK;
+}
+
+pbs_status pbs_surrogate_records(pbs_ctx *c, double *out, size_t n)
+{
+    if (!c) return PBS_EINVAL;
+    if (!c->sur) return fail(c, PBS_ESTATE, "no surrogate records without pbs_set_surrogate");
+    if (c->state < ST_BEAM || !c->closed) return fail(c, PBS_ESTATE, "records before run_beam");
+    if (!out || n != (size_t)4 * c->g.nz * c->NP) return fail(c, PBS_EINVAL, "records buffer must hold 4*nz*nx*ny");
+    HIPCHK(c, hipMemcpyAsync(out, c->frec(0, 0), n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PBS_OK;
+}
+
+pbs_status pbs_surrogate_report(pbs_ctx *c, double *out, int n)
+{
+    if (!c) return PBS_EINVAL;
+    if (!c->sur) return fail(c, PBS_ESTATE, "no surrogate report without pbs_set_surrogate");
+    if (c->state < ST_BEAM || !c->closed) return fail(c, PBS_ESTATE, "report before run_beam");
+    if (!out || n < 0 || n > 8) return fail(c, PBS_EINVAL, "report holds at most 8 values");
+    if (c->sur == 1) {
+        double h[4];
+        HIPCHK(c, hipMemcpyAsync(h, c->scal(), sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const double rep[8] = {NAN, 1.0, h[2], NAN, h[0] > 0.0 ? h[0] : 1.0, h[2], h[3], 0.0};
+        std::memcpy(c->sur_rep, rep, sizeof(rep));
+    } else {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    for (int i = 0; i < n; ++i) out[i] = c->sur_rep[i];
     return PBS_OK;
 }
 

@@ -39,6 +39,11 @@ struct EParams {
     T h;                    // length of each CN half-step
     int G;
     long NLINE, NAPT;       // lines per (g,l) slab; NA*PT
+    // surrogate features of this generation (all null unless recorded): per line, the energy that
+    // the closing / opening half-step injects into the next generation (MeV, FP64) and the energy
+    // and number moments of psi^1 after the opening half-step
+    double *inj_c = nullptr, *inj_o = nullptr, *mom_e = nullptr, *mom_n = nullptr;
+    const double *wmom = nullptr;   // [3G] moment weights: E_g dE_g and dE_g^2/6 (energy), dE_g (number) at G + g
 };
 
 template <typename T>

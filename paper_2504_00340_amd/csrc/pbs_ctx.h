@@ -47,6 +47,22 @@ struct pbs_ctx {
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> ev_pairs;   // (kind, index of the start event)
 
+    // surrogate of the scattered generation
+    int sur = 0;                  // 0 off, 1 recording, 2 surrogate with fallback
+    double sur_tol = 0, sur_leak = 0;
+    std::vector<float> sur_params;
+    int kact = 0;                 // generations marched (g.ngen, or 1 while the surrogate runs)
+    bool feat_on = false;         // record the per-slice surrogate data in the march
+    double sur_rep[8] = {};
+    pbs_beam beam{};
+    size_t o_fl = 0, o_frec = 0, o_scal = 0, o_sx = 0, o_sy = 0, o_sa = 0, o_sb = 0, o_spk = 0, o_smaster = 0;
+    size_t d_wmom = 0;
+
+    double *fline(int i) { return reinterpret_cast<double *>(ws + o_fl) + (size_t)i * NLINE; }
+    // records [4][nz][NP]: 0 injected energy, 1 energy moment, 2 number moment, 3 generation-0 deposit
+    double *frec(int i, int s) { return reinterpret_cast<double *>(ws + o_frec) + ((size_t)i * g.nz + s) * NP; }
+    double *scal() { return reinterpret_cast<double *>(ws + o_scal); }
+
     template <typename T> T *psi(int k) { return reinterpret_cast<T *>(ws + o_psi) + (size_t)k * G() * 2 * NLINE; }
     template <typename T> T *W() { return reinterpret_cast<T *>(ws + o_W); }
     template <typename T> T *Q() { return reinterpret_cast<T *>(ws + o_Q); }

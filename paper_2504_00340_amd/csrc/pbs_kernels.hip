@@ -50,7 +50,9 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
     T fin = 0, fcl = 0, fop = 0;    // psi1 - psi2 of group g+1: input, after close, after open
     T U0 = 0, U1 = 0, U2 = 0;       // re-emission energy scans of states 0, 1, 2
     double ph0 = 0, ph1 = 0, ph2 = 0, injc = 0, injo = 0;
+    double fic = 0, fio = 0, fme = 0, fmn = 0;   // surrogate features (energy sent to the next generation, moments)
     const bool hasQ = P.Q != nullptr, hasW = SPLIT ? P.Wh != nullptr : P.W != nullptr;
+    const bool feat = P.inj_c != nullptr;
     for (int g = P.G - 1; g >= 0; --g) {
         T *p1 = P.psi + (2L * g) * S + line;
         T *p2 = p1 + S;
@@ -105,39 +107,52 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
             if (CL) injc += wi * (double)qc;
             if (OP) injo += wi * (double)qo;
         }
-        if (hasW) {
+        if (hasW || feat) {
             // energy scans of the three states; the next generation needs the sums 0+1 and 1+2
             const T w = P.wc[g], dec = P.wdec[g], idE = P.invdE[g];
             const long o = (long)g * S + line;
             if (CL) U0 = w * x1 + dec * U0;
             U1 = w * y1 + dec * U1;
             if (OP) U2 = w * z1 + dec * U2;
-            if constexpr (SPLIT) {
-                // hi + lo bfloat16 pair of each sum; 8 lines of a cell -> one 16-byte chunk
-                unsigned short *buf = &wsh[g & 1][0][0];
-                const int so = ptc * 8 + e;
-                float vc = valid && CL ? (float)((U0 + U1) * idE) : 0.f;
-                float vo = valid && OP ? (float)((U1 + U2) * idE) : 0.f;
-                const __bf16 hc = (__bf16)vc, ho = (__bf16)vo;
-                buf[0 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, hc);
-                buf[1 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, (__bf16)(vc - (float)hc));
-                buf[2 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, ho);
-                buf[3 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, (__bf16)(vo - (float)ho));
-                __syncthreads();
-                const int t = threadIdx.x;
-                const int arr = t >> 5;   // 0 hi c, 1 lo c, 2 hi o, 3 lo o
-                const bool want = t < 128 && ((arr < 2) ? CL : OP);
-                if (want) {
-                    const long SB = (long)P.G * (S / P.NAPT) * P.NOCT * (PBS_PT * 8);
-                    const long ob = (((long)g * (S / P.NAPT) + pbk) * P.NOCT + oct) * (PBS_PT * 8) + (t & 31) * 8 +
-                                    (arr >= 2 ? SB : 0);
-                    unsigned short *dst = (arr & 1) ? P.Wl : P.Wh;
-                    *reinterpret_cast<u16x8v *>(dst + ob) =
-                        *reinterpret_cast<const u16x8v *>(&buf[arr * PBS_PT * 8 + (t & 31) * 8]);
+            if (feat) {
+                // energy the re-emission puts into the next generation (the dInj functional of its
+                // source summed over destination angles, which the angular law conserves), moments
+                const double wi = P.dInj[g];
+                if (CL) fic += wi * (double)((U0 + U1) * idE);
+                if (OP) {
+                    fio += wi * (double)((U1 + U2) * idE);
+                    fme += P.wmom[g] * (double)z1 + P.wmom[2 * P.G + g] * (double)z2;
+                    fmn += P.wmom[P.G + g] * (double)z1;
                 }
-            } else {
-                if (CL) P.W[o] = (U0 + U1) * idE;
-                if (OP) P.W[QS + o] = (U1 + U2) * idE;
+            }
+            if (hasW) {
+                if constexpr (SPLIT) {
+                    // hi + lo bfloat16 pair of each sum; 8 lines of a cell -> one 16-byte chunk
+                    unsigned short *buf = &wsh[g & 1][0][0];
+                    const int so = ptc * 8 + e;
+                    float vc = valid && CL ? (float)((U0 + U1) * idE) : 0.f;
+                    float vo = valid && OP ? (float)((U1 + U2) * idE) : 0.f;
+                    const __bf16 hc = (__bf16)vc, ho = (__bf16)vo;
+                    buf[0 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, hc);
+                    buf[1 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, (__bf16)(vc - (float)hc));
+                    buf[2 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, ho);
+                    buf[3 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, (__bf16)(vo - (float)ho));
+                    __syncthreads();
+                    const int t = threadIdx.x;
+                    const int arr = t >> 5;   // 0 hi c, 1 lo c, 2 hi o, 3 lo o
+                    const bool want = t < 128 && ((arr < 2) ? CL : OP);
+                    if (want) {
+                        const long SB = (long)P.G * (S / P.NAPT) * P.NOCT * (PBS_PT * 8);
+                        const long ob = (((long)g * (S / P.NAPT) + pbk) * P.NOCT + oct) * (PBS_PT * 8) + (t & 31) * 8 +
+                                        (arr >= 2 ? SB : 0);
+                        unsigned short *dst = (arr & 1) ? P.Wl : P.Wh;
+                        *reinterpret_cast<u16x8v *>(dst + ob) =
+                            *reinterpret_cast<const u16x8v *>(&buf[arr * PBS_PT * 8 + (t & 31) * 8]);
+                    }
+                } else {
+                    if (CL) P.W[o] = (U0 + U1) * idE;
+                    if (OP) P.W[QS + o] = (U1 + U2) * idE;
+                }
             }
         }
         fin = x1 - x2;
@@ -147,6 +162,14 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
     if (!valid) return;
     if (CL) P.dep_c[line] = dac * (ph0 + ph1 - injc) * P.scale;
     if (OP) P.dep_o[line] = dao * (ph1 + ph2 - injo) * P.scale;
+    if (feat) {
+        if (CL) P.inj_c[line] = dac * fic * P.scale;
+        if (OP) {
+            P.inj_o[line] = dao * fio * P.scale;
+            P.mom_e[line] = fme * P.scale;
+            P.mom_n[line] = fmn * P.scale;
+        }
+    }
 }
 
 template <typename T, int MODE, bool SPLIT>

@@ -26,7 +26,14 @@ EXPORTS = ["pbs_create", "pbs_workspace_bytes", "pbs_bind", "pbs_set_phantom", "
            "pbs_profile",
            "pbs_profile_read", "pbs_last_error", "pbs_destroy", "pbs_batch_create", "pbs_batch_workspace_bytes",
            "pbs_batch_bind", "pbs_batch_set_phantom", "pbs_batch_run", "pbs_batch_get_dose", "pbs_batch_tuning",
-           "pbs_batch_last_error", "pbs_batch_destroy"]
+           "pbs_batch_last_error", "pbs_batch_destroy", "pbs_set_surrogate", "pbs_surrogate_sample",
+           "pbs_surrogate_records", "pbs_surrogate_report", "pbs_net_param_count", "pbs_net_create",
+           "pbs_net_workspace_bytes", "pbs_net_bind", "pbs_net_set_params", "pbs_net_get_params", "pbs_net_forward",
+           "pbs_net_gradient", "pbs_net_train_step", "pbs_net_last_error", "pbs_net_destroy"]
+_NORET = ("pbs_last_error", "pbs_destroy", "pbs_batch_last_error", "pbs_batch_destroy", "pbs_net_last_error",
+          "pbs_net_destroy")
+PBS_NET_MAGIC, PBS_NET_VERSION, PBS_NET_CIN, SUR_NFEAT = 0x4E534250, 1, 8, 7
+REPORT_KEYS = ["residual", "fallback", "budget", "predicted", "scale", "injected", "own_deposit", "leak"]
 KINDS = ["epass", "tpass", "apass", "qgemm", "dose"]
 
 
@@ -95,8 +102,26 @@ def lib():
         L.pbs_batch_last_error.restype = C.c_char_p
         L.pbs_batch_destroy.argtypes = [vp]
         L.pbs_batch_destroy.restype = None
+        F = C.POINTER(C.c_float)
+        L.pbs_set_surrogate.argtypes = [vp, vp, sz, C.c_double]
+        L.pbs_surrogate_sample.argtypes = [vp, vp, vp, sz]
+        L.pbs_surrogate_records.argtypes = [vp, D, sz]
+        L.pbs_surrogate_report.argtypes = [vp, D, C.c_int]
+        L.pbs_net_param_count.argtypes = [C.POINTER(sz)]
+        L.pbs_net_create.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(vp)]
+        L.pbs_net_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
+        L.pbs_net_bind.argtypes = [vp, vp, sz, vp]
+        L.pbs_net_set_params.argtypes = [vp, F, sz]
+        L.pbs_net_get_params.argtypes = [vp, F, sz]
+        L.pbs_net_forward.argtypes = [vp, vp, vp, C.c_int]
+        L.pbs_net_gradient.argtypes = [vp, vp, vp, C.c_int, F, sz, D]
+        L.pbs_net_train_step.argtypes = [vp, vp, vp, C.c_int, C.c_double, vp]
+        L.pbs_net_last_error.argtypes = [vp]
+        L.pbs_net_last_error.restype = C.c_char_p
+        L.pbs_net_destroy.argtypes = [vp]
+        L.pbs_net_destroy.restype = None
         for n in EXPORTS:
-            if n not in ("pbs_last_error", "pbs_destroy", "pbs_batch_last_error", "pbs_batch_destroy"):
+            if n not in _NORET:
                 getattr(L, n).restype = C.c_int
         _lib = L
     return _lib
@@ -106,10 +131,40 @@ def _mk(cls, d):
     return cls(**{k: d[k] for k, _ in cls._fields_})
 
 
-class Solver:
-    """One libpbsplit context bound to a torch-allocated workspace on `device`."""
+def param_count() -> int:
+    n = C.c_size_t()
+    rc = lib().pbs_net_param_count(C.byref(n))
+    if rc != PBS_OK:
+        raise PbsError(rc, "pbs_net_param_count")
+    return n.value
 
-    def __init__(self, grid: dict, phys: dict, precision: str = "fp32", device="cuda:0", stream=None):
+
+def pack_weights(params, leak: float) -> bytes:
+    """Weights blob of pbs_set_surrogate: 64-byte header + FP32 parameters."""
+    p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    head = np.zeros(6, dtype=np.float64)   # leak + 5 reserved: 48 bytes after the 16-byte ids
+    head[0] = leak
+    u = np.array([PBS_NET_MAGIC, PBS_NET_VERSION, p.size, SUR_NFEAT], dtype=np.uint32)
+    return u.tobytes() + head.tobytes() + p.tobytes()
+
+
+def unpack_weights(blob: bytes):
+    """(params float32, leak) from a weights blob."""
+    u = np.frombuffer(blob[:16], dtype=np.uint32)
+    if u[0] != PBS_NET_MAGIC or u[1] != PBS_NET_VERSION:
+        raise ValueError("not a pbsplit network blob")
+    leak = float(np.frombuffer(blob[16:24], dtype=np.float64)[0])
+    return np.frombuffer(blob[64:], dtype=np.float32).copy(), leak
+
+
+class Solver:
+    """One libpbsplit context bound to a torch-allocated workspace on `device`.
+
+    surrogate: None, "record" (plain march that keeps the per-slice surrogate records) or a weights
+    blob (bytes) for the surrogate of generation 1 with fallback at residual_tol."""
+
+    def __init__(self, grid: dict, phys: dict, precision: str = "fp32", device="cuda:0", stream=None,
+                 surrogate=None, residual_tol: float = 1e-2):
         import torch
 
         self.torch = torch
@@ -121,6 +176,15 @@ class Solver:
         rc = self.L.pbs_create(C.byref(self.g), C.byref(_mk(Physics, phys)), self.prec, C.byref(self.ctx))
         if rc != PBS_OK:
             raise PbsError(rc, "pbs_create rejected the grid / physics")
+        if surrogate is not None:
+            if isinstance(surrogate, str):
+                if surrogate != "record":
+                    raise ValueError("surrogate must be None, 'record' or a weights blob")
+                self._check(self.L.pbs_set_surrogate(self.ctx, None, 0, 0.0))
+            else:
+                self._blob = C.create_string_buffer(bytes(surrogate), len(surrogate))
+                self._check(self.L.pbs_set_surrogate(self.ctx, C.cast(self._blob, C.c_void_p), len(surrogate),
+                                                     float(residual_tol)))
         nb = C.c_size_t()
         self._check(self.L.pbs_workspace_bytes(self.ctx, C.byref(nb)))
         self.ws_bytes = nb.value
@@ -191,6 +255,24 @@ class Solver:
         self._check(self.L.pbs_profile_read(self.ctx, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KINDS)}
 
+    def surrogate_sample(self, x, t):
+        """Features (uint8-viewed or bfloat16 tensor of nz*nx*ny*8 values) and FP32 targets into
+        device tensors."""
+        g = self.grid
+        self._check(self.L.pbs_surrogate_sample(self.ctx, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                                g["nz"]))
+
+    def surrogate_records(self) -> np.ndarray:
+        g = self.grid
+        out = np.zeros((4, g["nz"], g["nx"], g["ny"]))
+        self._check(self.L.pbs_surrogate_records(self.ctx, out.ctypes.data_as(C.POINTER(C.c_double)), out.size))
+        return out
+
+    def surrogate_report(self) -> dict:
+        out = (C.c_double * 8)()
+        self._check(self.L.pbs_surrogate_report(self.ctx, out, 8))
+        return {k: out[i] for i, k in enumerate(REPORT_KEYS)}
+
     def close(self):
         if getattr(self, "ctx", None):
             self.L.pbs_destroy(self.ctx)
@@ -254,6 +336,73 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             self.L.pbs_batch_destroy(self.h)
+            self.h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Net:
+    """The surrogate network with its training state (pbs_net_*), bound to a torch workspace."""
+
+    def __init__(self, H: int, W: int, max_batch: int, device="cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.L = lib()
+        self.H, self.W, self.max_batch = H, W, max_batch
+        self.h = C.c_void_p()
+        rc = self.L.pbs_net_create(int(H), int(W), int(max_batch), C.byref(self.h))
+        if rc != PBS_OK:
+            raise PbsError(rc, "pbs_net_create rejected the shape")
+        self.npar = param_count()
+        nb = C.c_size_t()
+        self._check(self.L.pbs_net_workspace_bytes(self.h, C.byref(nb)))
+        self._ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=torch.device(device))
+        base = self._ws.data_ptr()
+        ptr = base + ((256 - base % 256) % 256)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        self._check(self.L.pbs_net_bind(self.h, C.c_void_p(ptr), nb.value, C.c_void_p(self.stream.cuda_stream)))
+
+    def _check(self, rc):
+        if rc != PBS_OK:
+            raise PbsError(rc, self.L.pbs_net_last_error(self.h).decode())
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32).reshape(-1)
+        self._check(self.L.pbs_net_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+
+    def params(self) -> np.ndarray:
+        a = np.zeros(self.npar, dtype=np.float32)
+        self._check(self.L.pbs_net_get_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    def forward(self, x, y):
+        """x: bfloat16 tensor [n, H, W, 8] on the device; y: float32 tensor [n, H, W] (written)."""
+        self._check(self.L.pbs_net_forward(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                           int(x.shape[0])))
+
+    def gradient(self, x, t):
+        g = np.zeros(self.npar, dtype=np.float32)
+        loss = C.c_double()
+        self._check(self.L.pbs_net_gradient(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                            int(x.shape[0]), g.ctypes.data_as(C.POINTER(C.c_float)), g.size,
+                                            C.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, x, t, lr: float, loss_out=None):
+        """One Adam step; loss_out: optional float64 device tensor element receiving the loss."""
+        lp = C.c_void_p(loss_out.data_ptr()) if loss_out is not None else None
+        self._check(self.L.pbs_net_train_step(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                              int(x.shape[0]), float(lr), lp))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pbs_net_destroy(self.h)
             self.h = None
         self._ws = None
 

@@ -92,3 +92,57 @@ def test_batch_create_validates_shape_class():
     assert L.pbs_batch_create(bad, beams, 2, C.byref(B._mk(B.Physics, I.PHYS)), 0, C.byref(h)) == B.PBS_EINVAL
     small = (B.Grid * 1)(B._mk(B.Grid, dict(g1, nth=8)))
     assert L.pbs_batch_create(small, beams, 1, C.byref(B._mk(B.Physics, I.PHYS)), 0, C.byref(h)) == B.PBS_EUNSUPPORTED
+
+
+def test_surrogate_and_network_argument_checks():
+    import numpy as np
+
+    L = B.lib()
+    g = dict(I.config1()["grid"])           # ngen = 2
+    rc, ctx = _create(g)
+    nb0 = C.c_size_t()
+    L.pbs_workspace_bytes(ctx, C.byref(nb0))
+    # blobs: wrong magic, wrong size, NaN; then recording mode grows the workspace
+    good = B.pack_weights(np.zeros(B.param_count(), dtype=np.float32), 0.01)
+    bad_magic = b"XXXX" + good[4:]
+    assert L.pbs_set_surrogate(ctx, bad_magic, len(bad_magic), 1e-2) == B.PBS_EINVAL
+    assert L.pbs_set_surrogate(ctx, good, len(good) - 4, 1e-2) == B.PBS_EINVAL
+    nanp = np.zeros(B.param_count(), dtype=np.float32)
+    nanp[5] = np.nan
+    nan_blob = B.pack_weights(nanp, 0.0)
+    assert L.pbs_set_surrogate(ctx, nan_blob, len(nan_blob), 1e-2) == B.PBS_EINVAL
+    assert L.pbs_set_surrogate(ctx, good, len(good), -1.0) == B.PBS_EINVAL
+    assert L.pbs_set_surrogate(ctx, None, 0, 0.0) == B.PBS_OK
+    nb1 = C.c_size_t()
+    L.pbs_workspace_bytes(ctx, C.byref(nb1))
+    assert nb1.value > nb0.value
+    assert L.pbs_set_surrogate(ctx, good, len(good), 1e-2) == B.PBS_OK
+    nb2 = C.c_size_t()
+    L.pbs_workspace_bytes(ctx, C.byref(nb2))
+    assert nb2.value > nb1.value
+    out = (C.c_double * 8)()
+    assert L.pbs_surrogate_report(ctx, out, 8) == B.PBS_ESTATE
+    L.pbs_destroy(ctx)
+    # the surrogate replaces generation 1 of a K = 1 grid only
+    for bad in (dict(g, ngen=1), dict(g, ngen=3)):
+        rc, ctx = _create(bad)
+        assert L.pbs_set_surrogate(ctx, None, 0, 0.0) == B.PBS_EINVAL
+        L.pbs_destroy(ctx)
+    rc, ctx = _create(dict(g, ny=65))
+    assert L.pbs_set_surrogate(ctx, None, 0, 0.0) == B.PBS_EUNSUPPORTED
+    L.pbs_destroy(ctx)
+    # network
+    n = C.c_size_t()
+    assert L.pbs_net_param_count(C.byref(n)) == B.PBS_OK and n.value == 21121
+    h = C.c_void_p()
+    assert L.pbs_net_create(64, 65, 4, C.byref(h)) == B.PBS_EINVAL
+    assert L.pbs_net_create(64, 64, 0, C.byref(h)) == B.PBS_EINVAL
+    assert L.pbs_net_create(64, 64, 4, C.byref(h)) == B.PBS_OK
+    nb = C.c_size_t()
+    assert L.pbs_net_workspace_bytes(h, C.byref(nb)) == B.PBS_OK and nb.value > 4 * 64 * 64 * 32 * 2 * 5
+    p = np.zeros(n.value, dtype=np.float32)
+    assert L.pbs_net_set_params(h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size) == B.PBS_ESTATE
+    assert L.pbs_net_forward(h, C.c_void_p(4096), C.c_void_p(4096), 1) == B.PBS_ESTATE
+    assert L.pbs_net_bind(h, C.c_void_p(256 * 1024 + 8), nb.value, None) == B.PBS_EINVAL
+    assert b"aligned" in L.pbs_net_last_error(h)
+    L.pbs_net_destroy(h)

@@ -1,0 +1,305 @@
+"""The surrogate of generation 1 on the GPU (through the C ABI) against the CPU reference.
+
+Network kernels: the forward and the gradient on BF16-exact operands (integer weights and inputs,
+identity middle layers, power-of-two pixel count) must equal the FP64 reference exactly, which
+checks every index of the data-gradient and weight-gradient kernels with only FP32 accumulation
+left; on random operands the BF16 gradient is within 1e-2 (relative, per layer) of the FP64
+reference evaluated on the same BF16-rounded weights and inputs with BF16-stored activations
+(the network a BF16 implementation evaluates; the distance to FP64 activations is printed).  Training is deterministic and
+lowers the loss.  Records and features of the march match the oracle (FP64 context: 1e-10; the
+features are BF16), recording does not change the dose, and the surrogate mode either accepts the
+network (dose = E0 - I + c * net) or falls back to exactly the plain march.
+"""
+import numpy as np
+import pytest
+
+from paper_2504_00340_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _bf16_round(a):
+    torch = _torch()
+    return torch.tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).float().numpy().astype(np.float64)
+
+
+def _dev_bf16(a):
+    torch = _torch()
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).cuda().contiguous()
+
+
+def _dev_f32(a):
+    torch = _torch()
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32)).cuda().contiguous()
+
+
+@pytest.fixture(scope="module")
+def S():
+    from oracle import surrogate
+
+    return surrogate
+
+
+def _layer_slices(S):
+    out, o = [], 0
+    for ci, co in S.LAYERS:
+        nw = co * ci * 9
+        out.append((slice(o, o + nw), slice(o + nw, o + nw + co)))
+        o += nw + co
+    return out
+
+
+def _integer_net(S, seed):
+    """Integer first and last layers, identity middle layers (centre tap, channel to itself)."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    L = []
+    for i, (ci, co) in enumerate(S.LAYERS):
+        if i in (1, 2):
+            w = np.zeros((co, ci, 3, 3))
+            for k in range(co):
+                w[k, k, 1, 1] = 1.0
+            b = np.zeros(co)
+        else:
+            w = r.integers(-1, 2, size=(co, ci, 3, 3)).astype(np.float64)
+            b = r.integers(-2, 3, size=co).astype(np.float64)
+        L.append((w, b))
+    return S.flatten(L)
+
+
+@pytest.mark.parametrize("shape", [(3, 6, 20), (2, 9, 64), (1, 5, 7)])
+def test_forward_exact_on_integers(S, shape):
+    from paper_2504_00340_amd.pbsplit import Net
+
+    torch = _torch()
+    n, H, W = shape
+    print("case forward", shape, flush=True)
+    r = np.random.Generator(np.random.PCG64(11))
+    p = _integer_net(S, 12)
+    x = r.integers(-2, 3, size=(n, H, W, 8)).astype(np.float64)
+    ref, _ = S.forward(p, x)
+    net = Net(H, W, n)
+    net.set_params(p)
+    y = torch.empty((n, H, W), dtype=torch.float32, device="cuda")
+    net.forward(_dev_bf16(x), y)
+    got = y.cpu().numpy().astype(np.float64)
+    assert np.array_equal(got, ref), np.abs(got - ref).max()
+
+
+def test_gradient_exact_on_integers(S):
+    from paper_2504_00340_amd.pbsplit import Net
+
+    n, H, W = 2, 8, 16     # 256 pixels: 2 (y - t) / npx stays exact in BF16
+    print("case gradient exact", flush=True)
+    r = np.random.Generator(np.random.PCG64(13))
+    p = _integer_net(S, 14)
+    x = r.integers(-2, 3, size=(n, H, W, 8)).astype(np.float64)
+    y, _ = S.forward(p, x)
+    t = y - r.integers(-3, 4, size=y.shape)
+    loss_ref, g_ref = S.loss_grad(p, x, t)
+    net = Net(H, W, n)
+    net.set_params(p)
+    g, loss = net.gradient(_dev_bf16(x), _dev_f32(t))
+    assert abs(loss - loss_ref) <= 1e-12 * loss_ref
+    assert np.array_equal(g.astype(np.float64), g_ref), np.abs(g - g_ref).max()
+
+
+@pytest.mark.parametrize("shape", [(3, 13, 37), (2, 64, 64)])
+def test_gradient_bf16_random(S, shape):
+    from paper_2504_00340_amd.pbsplit import Net
+
+    n, H, W = shape
+    print("case gradient bf16", shape, flush=True)
+    r = np.random.Generator(np.random.PCG64(15))
+    L = []
+    for ci, co in S.LAYERS:
+        L.append((r.normal(size=(co, ci, 3, 3)) * np.sqrt(2.0 / (9 * ci)), r.normal(size=co) * 0.1))
+    p = _bf16_round(S.flatten(L))
+    x = _bf16_round(np.abs(r.normal(size=(n, H, W, 8))))
+    t = r.normal(size=(n, H, W))
+    loss_ref, g_ref = S.loss_grad(p, x, t, act_bf16=True)
+    loss_64, g_64 = S.loss_grad(p, x, t)
+    net = Net(H, W, n)
+    net.set_params(p)
+    g, loss = net.gradient(_dev_bf16(x), _dev_f32(t))
+    assert abs(loss - loss_ref) <= 1e-3 * loss_ref
+    assert abs(loss - loss_64) <= 1e-2 * loss_64
+    for i, (sw, sb) in enumerate(_layer_slices(S)):
+        for sl in (sw, sb):
+            e = np.linalg.norm(g[sl] - g_ref[sl]) / np.linalg.norm(g_ref[sl])
+            e64 = np.linalg.norm(g[sl] - g_64[sl]) / np.linalg.norm(g_64[sl])
+            print(f"layer {i} {'w' if sl is sw else 'b'} rel {e:.2e} (vs FP64 activations {e64:.2e})", flush=True)
+            assert e <= 1e-2
+
+
+def test_training_lowers_loss_and_is_deterministic(S):
+    from paper_2504_00340_amd.pbsplit import Net
+
+    torch = _torch()
+    n, H, W = 8, 16, 24
+    print("case training", flush=True)
+    r = np.random.Generator(np.random.PCG64(17))
+
+    def init(seed):
+        rr = np.random.Generator(np.random.PCG64(seed))
+        return S.flatten([(rr.normal(size=(co, ci, 3, 3)) * np.sqrt(2.0 / (9 * ci)), np.zeros(co))
+                          for ci, co in S.LAYERS])
+
+    x = _dev_bf16(np.abs(r.normal(size=(n, H, W, 8))))
+    teacher = Net(H, W, n)
+    teacher.set_params(init(100))
+    t = torch.empty((n, H, W), dtype=torch.float32, device="cuda")
+    teacher.forward(x, t)
+    runs = []
+    for rep in range(2):
+        net = Net(H, W, n)
+        net.set_params(init(200))
+        loss = torch.zeros(300, dtype=torch.float64, device="cuda")
+        for k in range(300):
+            net.train_step(x, t, 2e-3, loss[k:k + 1])
+        runs.append((loss.cpu().numpy(), net.params()))
+    l0, l1 = runs[0][0][:5].mean(), runs[0][0][-5:].mean()
+    print("loss", l0, "->", l1, flush=True)
+    assert l1 < 0.2 * l0
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[0][0], runs[1][0])
+
+
+# ----------------------------------------------------------------------------- records and features
+def _case(seed=21, nx=9, ny=13):
+    return I.small(nx=nx, ny=ny, nth=6, ng=10, nz=5, ngen=2, e0=30.0, e_hi=38.0, x_half=1.5, y_half=1.5,
+                   th_half=0.2, depth=0.5, seed=seed)
+
+
+def _solver(c, prec, surrogate=None, tol=1e-2):
+    from paper_2504_00340_amd.pbsplit import Solver
+
+    s = Solver(c["grid"], c["phys"], precision=prec, surrogate=surrogate, residual_tol=tol)
+    s.set_phantom(c["rho"])
+    s.set_beam(c["beam"])
+    return s
+
+
+@pytest.fixture(scope="module")
+def rec_case():
+    from oracle.oracle import Oracle
+
+    c = _case()
+    o = Oracle(c["grid"], c["phys"])
+    dose, _, rec = o.run_records(c["beam"], c["rho"])
+    return c, o, dose, rec
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_records_match_oracle(rec_case, prec):
+    c, o, dose_ref, rec_ref = rec_case
+    print("case records", prec, flush=True)
+    s = _solver(c, prec, surrogate="record")
+    s.run()
+    rec = s.surrogate_records()
+    d = s.dose()
+    plain = _solver(c, prec)
+    plain.run()
+    assert np.array_equal(d, plain.dose())       # recording changes nothing
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    for i in range(4):
+        e = np.abs(rec[i] - rec_ref[i]).max() / np.abs(rec_ref[i]).max()
+        print("record", i, e, flush=True)
+        assert e <= tol
+
+
+def test_features_and_targets_match_oracle(rec_case, S):
+    torch = _torch()
+    c, o, dose_ref, rec_ref = rec_case
+    g = c["grid"]
+    print("case features", flush=True)
+    s = _solver(c, "fp64", surrogate="record")
+    s.run()
+    npx = g["nx"] * g["ny"]
+    x = torch.zeros((g["nz"], g["nx"], g["ny"], 8), dtype=torch.bfloat16, device="cuda")
+    t = torch.zeros((g["nz"], g["nx"], g["ny"]), dtype=torch.float32, device="cuda")
+    s.surrogate_sample(x, t)
+    X = x.float().cpu().numpy().astype(np.float64)
+    T = t.cpu().numpy().astype(np.float64)
+    Xr = S.features(rec_ref, c["rho"], g["dz"], c["phys"]["kappa0"])
+    vol = o.dx * o.dy * g["dz"]
+    Tr = S.target(rec_ref, dose_ref * c["rho"] * vol)
+    assert np.all(X[..., 7] == 0)
+    for k in range(7):
+        err = np.abs(X[..., k] - Xr[..., k]) - 2.0 ** -7 * np.abs(Xr[..., k])
+        assert err.max() <= 1e-30, (k, err.max())
+    assert np.abs(T - Tr).max() <= 1e-6 * np.abs(Tr).max()
+    rep = s.surrogate_report()
+    assert rep["fallback"] == 1.0
+    assert abs(rep["injected"] - rec_ref[0].sum()) <= 1e-10 * rec_ref[0].sum()
+    assert rep["scale"] == pytest.approx(S.scale(rec_ref), rel=1e-10)
+
+
+def _random_blob(S, seed, leak=0.0):
+    from paper_2504_00340_amd.pbsplit import pack_weights
+
+    r = np.random.Generator(np.random.PCG64(seed))
+    L = [(r.normal(size=(co, ci, 3, 3)) * np.sqrt(2.0 / (9 * ci)), r.normal(size=co) * 0.01) for ci, co in S.LAYERS]
+    return pack_weights(S.flatten(L), leak), S.flatten(L)
+
+
+def test_surrogate_fallback_is_the_plain_march(S):
+    c = _case(seed=22)
+    print("case fallback", flush=True)
+    blob, _ = _random_blob(S, 5)
+    s = _solver(c, "fp32", surrogate=blob, tol=0.0)
+    s.run()
+    rep = s.surrogate_report()
+    assert rep["fallback"] == 1.0 and rep["residual"] > 0
+    plain = _solver(c, "fp32")
+    plain.run()
+    assert np.array_equal(s.dose(), plain.dose())
+
+
+def test_surrogate_accepted_dose(S):
+    """Accepted surrogate: dose = (E0 - I + c * net(features)) / (rho V), with E0, I, features from
+    a recording run and net evaluated by the same kernels through pbs_net_forward."""
+    from paper_2504_00340_amd.pbsplit import Net
+
+    torch = _torch()
+    c = _case(seed=23, nx=12, ny=16)
+    g = c["grid"]
+    print("case accepted", flush=True)
+    blob, p = _random_blob(S, 6)
+    s = _solver(c, "fp32", surrogate=blob, tol=1e30)
+    s.run()
+    rep = s.surrogate_report()
+    assert rep["fallback"] == 0.0
+    d = s.dose()
+    r = _solver(c, "fp32", surrogate="record")
+    r.run()
+    rec = r.surrogate_records()
+    x = torch.zeros((g["nz"], g["nx"], g["ny"], 8), dtype=torch.bfloat16, device="cuda")
+    t = torch.zeros((g["nz"], g["nx"], g["ny"]), dtype=torch.float32, device="cuda")
+    r.surrogate_sample(x, t)
+    net = Net(g["nx"], g["ny"], g["nz"])
+    net.set_params(p)
+    y = torch.zeros((g["nz"], g["nx"], g["ny"]), dtype=torch.float32, device="cuda")
+    net.forward(x, y)
+    yv = y.cpu().numpy().astype(np.float64)
+    cb = rep["scale"]
+    assert cb == pytest.approx(rec[0].max(), rel=1e-12)
+    vol = (2 * g["x_half"] / g["nx"]) * (2 * g["y_half"] / g["ny"]) * g["dz"]
+    want = (rec[3] + (cb * yv - rec[0])) / (c["rho"] * vol)
+    assert np.abs(d - want).max() <= 1e-12 * np.abs(want).max()
+    assert rep["predicted"] == pytest.approx(cb * yv.sum(), rel=1e-9)
+
+
+def test_surrogate_refuses_stepping(S):
+    from paper_2504_00340_amd.pbsplit import PbsError
+
+    c = _case(seed=24)
+    blob, _ = _random_blob(S, 7)
+    s = _solver(c, "fp32", surrogate=blob)
+    with pytest.raises(PbsError):
+        s.step(1)

@@ -49,6 +49,16 @@ def test_conv_channels_brute_force():
     assert np.abs(got - ref).max() < 1e-12
 
 
+def test_bf16_rounding_matches_torch():
+    import torch
+
+    r = rnd(4)
+    a = np.concatenate([r.normal(size=5000) * 10.0 ** r.integers(-30, 30, size=5000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 65504.0, 3.0e38]])
+    ref = torch.tensor(a.astype(np.float32)).to(torch.bfloat16).float().numpy().astype(np.float64)
+    assert np.array_equal(S.bf16(a), ref)
+
+
 def test_param_layout():
     assert S.param_count() == 32 * 8 * 9 + 32 + 2 * (32 * 32 * 9 + 32) + 32 * 9 + 1
     p = np.arange(S.param_count(), dtype=np.float64)
