@@ -133,6 +133,47 @@ def batched(nbeams, phys_override=None):
             "first_run_s_with_autotune": t_first, "tuning": tuning}
 
 
+def surrogate(nseeds, tol=1e-2):
+    """Config-5 held-out beams: the plain K = 1 march against the surrogate of generation 1 (trained
+    weights shipped with the package; residual test with fallback to the plain march)."""
+    import numpy as np
+    import torch
+
+    from paper_2504_00340_amd import inputs as I
+    from paper_2504_00340_amd.pbsplit import Solver, surrogate_weights
+
+    blob = surrogate_weights()
+    t = {"plain": 0.0, "surrogate": 0.0}
+    rows = []
+    for seed in range(100_000, 100_000 + nseeds):
+        c = I.config5(seed)
+        dose = {}
+        for mode in ("plain", "surrogate"):
+            s = Solver(c["grid"], c["phys"], "fp32", surrogate=blob if mode == "surrogate" else None,
+                       residual_tol=tol)
+            s.set_phantom(c["rho"])
+            s.set_beam(c["beam"])
+            s.run()                          # warm-up beam
+            s.set_beam(c["beam"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.run()
+            rep = s.surrogate_report() if mode == "surrogate" else None
+            torch.cuda.synchronize()
+            t[mode] += time.perf_counter() - t0
+            dose[mode] = s.dose()
+            s.close()
+        err = float(np.linalg.norm(dose["surrogate"] - dose["plain"]) / np.linalg.norm(dose["plain"]))
+        rows.append({"seed": seed, "e0": round(c["beam"]["e0"], 2), "rel_l2_dose_error": err,
+                     "residual": rep["residual"], "fallback": bool(rep["fallback"])})
+    return {"workload": f"config 5 held-out seeds 100000-{100_000 + nseeds - 1}: 64x64 cells, 16x16 angles, "
+                        f"96 groups, 300 steps, K = 1, FP32",
+            "beams_per_s_plain": nseeds / t["plain"], "beams_per_s_surrogate": nseeds / t["surrogate"],
+            "speedup": t["plain"] / t["surrogate"], "tolerance": tol,
+            "max_rel_l2_dose_error": max(r["rel_l2_dose_error"] for r in rows),
+            "fallbacks": sum(r["fallback"] for r in rows), "beams": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +186,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-beams", type=int, default=8,
                     help="config-4 beams for the batched leg (0 = skip)")
+    ap.add_argument("--surrogate-beams", type=int, default=4,
+                    help="config-5 held-out beams for the surrogate leg (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -247,6 +290,9 @@ def main():
     if args.batched_beams > 0:
         print(f"bench: batched leg, {args.batched_beams} config-4 beams", file=sys.stderr, flush=True)
         out["batched"] = batched(args.batched_beams)
+    if args.surrogate_beams > 0:
+        print(f"bench: surrogate leg, {args.surrogate_beams} config-5 beams", file=sys.stderr, flush=True)
+        out["surrogate"] = surrogate(args.surrogate_beams)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -209,15 +209,17 @@ void pbs_batch_destroy(pbs_batch *batch);
  *          of dE psi^1, times dth^2 dx dy,
  *   E0     the deposit of the primary generation alone.
  * Features of slice s (BF16, 8 channels per cell, image [nx][ny], ny <= 64):
- *   0: M_E kappa0 dz / c,  1: rho,  2: I / c,  3-5: F_j / c with the causal depth filters
- *   F_j(s) = a F_j(s-1) + (1 - a) I(s), a = exp(-rho dz / L_j), L = 0.5, 2, 6 cm,
- *   6: (M_E / M_N) / 250 MeV where M_N > 1e-4 max M_N (else 0),  7: zero;
- *   c = max over the beam of I.
+ *   0: M_E kappa0 dz / c,  1: rho,  2: I / c,  3-5 and 7: F_j / c with the causal depth filters
+ *   F_j(s) = a F_j(s-1) + (1 - a) I(s), a = exp(-rho dz / L_j), L = 0.5, 2, 6 (3-5) and 15 cm (7),
+ *   6: (M_E / M_N) / 250 MeV where M_N > 1e-4 max M_N (else 0);  c = max over the beam of I.
  * Target (FP32): (E_total - E0 + I) / c, the energy generation 1 deposits itself in the voxel.
  * Surrogate dose: E0 - I + c * net(features), from a march of the primaries only.
- * Residual: |sum c * net - (1 - leak) sum I| / sum I (leak from the weights).  Above the
- * tolerance the beam is marched again with both generations (the plain method), so the result is
- * then exactly the plain K = 1 dose.
+ * Residual: |sum c * net - (1 - l) sum I| / (sum E0 - sum I + sum c * net), the energy balance of
+ * generation 1 relative to the whole deposit of the beam, where l = l0 + l1 x + l2 x^2 (clamped to
+ * [0, 0.95]) models the fraction of the injected energy that generation 1 carries out of the grid
+ * (through the angular and lateral boundaries, or past the last layer) from the fraction of the
+ * beam energy the primaries do not deposit, x = 1 - sum E0 / e0.  Above the tolerance the beam is marched again with both generations
+ * (the plain method), so the result is then exactly the plain K = 1 dose.
  *
  * Network (weights blob = pbs_net_header + nparam FP32 values): 3x3 convolutions, zero padding,
  * 8 -> 32 -> 32 -> 32 -> 1 channels, ReLU after the first three; parameters in the order
@@ -227,9 +229,9 @@ void pbs_batch_destroy(pbs_batch *batch);
 #define PBS_NET_VERSION 1u
 #define PBS_NET_CIN 8
 typedef struct pbs_net_header {
-    unsigned int magic, version, nparam, nfeat; /* nfeat = 7 */
-    double leak;                                /* mean fraction of sum I that generation 1 does not deposit */
-    double reserved[5];
+    unsigned int magic, version, nparam, nfeat; /* nfeat = 8 */
+    double leak[3];                             /* leak model coefficients l0, l1, l2 */
+    double reserved[3];
 } pbs_net_header;                               /* 64 bytes */
 
 /* Must be called after pbs_create and before pbs_workspace_bytes / pbs_bind (it enlarges the
@@ -251,8 +253,10 @@ pbs_status pbs_surrogate_sample(pbs_ctx *ctx, void *dev_x, float *dev_target, si
 pbs_status pbs_surrogate_records(pbs_ctx *ctx, double *out, size_t n);
 
 /* After pbs_run_beam (synchronises): out[0] residual, [1] 1 if the plain march was used,
- * [2] energy budget (1 - leak) sum I, [3] network energy sum c * net, [4] c, [5] sum I,
- * [6] energy generation 1 deposited itself (recording mode; else NaN), [7] leak.  n <= 8. */
+ * [2] energy budget (1 - l) sum I, [3] network energy sum c * net, [4] c, [5] sum I,
+ * [6] energy generation 1 deposited itself (recording mode; else NaN), [7] leak fraction (model
+ * value in surrogate mode, measured 1 - [6] / [5] in recording mode), [8] sum E0, [9] x (above).
+ * Values that do not apply are NaN.  n <= 10. */
 pbs_status pbs_surrogate_report(pbs_ctx *ctx, double *out, int n);
 
 /* Training of the network on one GPU (the same kernels as the surrogate, plus the data and weight

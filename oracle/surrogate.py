@@ -23,9 +23,9 @@ from __future__ import annotations
 import numpy as np
 
 LAYERS = [(8, 32), (32, 32), (32, 32), (32, 1)]
-FILTER_L = (0.5, 2.0, 6.0)     # cm water-equivalent, depth filters of the injected energy
-E_REF = 250.0                  # MeV, scale of the mean-energy channel
-NFEAT = 7
+FILTER_L = (0.5, 2.0, 6.0, 15.0)   # cm water-equivalent, depth filters of the injected energy
+E_REF = 250.0                      # MeV, scale of the mean-energy channel
+NFEAT = 8
 
 
 def param_count() -> int:
@@ -127,20 +127,22 @@ def scale(rec):
 
 
 def features(rec, rho, dz, kappa0):
-    """Per-slice features [nz, nx, ny, 7] from the records and the densities [nz, nx, ny]."""
+    """Per-slice features [nz, nx, ny, 8] from the records and the densities [nz, nx, ny]:
+    M_E kappa0 dz / c, rho, I / c, F_0.5 / c, F_2 / c, F_6 / c, mean primary energy / 250 MeV,
+    F_15 / c."""
     I, ME, MN = rec[0], rec[1], rec[2]
     c = scale(rec)
     cn = float(MN.max())
     nz = I.shape[0]
-    F = np.zeros((3,) + I.shape)
-    run = np.zeros((3,) + I.shape[1:])
+    F = np.zeros((4,) + I.shape)
+    run = np.zeros((4,) + I.shape[1:])
     for s in range(nz):
         for j, Lj in enumerate(FILTER_L):
             a = np.exp(-rho[s] * dz / Lj)
             run[j] = a * run[j] + (1.0 - a) * I[s]
             F[j, s] = run[j]
     eb = np.where(MN > 1e-4 * cn, ME / np.where(MN > 1e-4 * cn, MN, 1.0), 0.0) if cn > 0 else np.zeros_like(ME)
-    X = np.stack([ME * kappa0 * dz / c, rho, I / c, F[0] / c, F[1] / c, F[2] / c, eb / E_REF], axis=-1)
+    X = np.stack([ME * kappa0 * dz / c, rho, I / c, F[0] / c, F[1] / c, F[2] / c, eb / E_REF, F[3] / c], axis=-1)
     return X
 
 

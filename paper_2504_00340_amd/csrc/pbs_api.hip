@@ -667,7 +667,7 @@ pbs_status run_surrogate(pbs_ctx *c)
     c->feat_on = false;
     if (r != PBS_OK) return r;
     double *sc = c->scal();
-    HIPCHK(c, sur_scalars(c->frec(0, 0), c->frec(2, 0), nullptr, nullptr, slab, sc, c->stream));
+    HIPCHK(c, sur_scalars(c->frec(0, 0), c->frec(2, 0), c->edep(0), nullptr, slab, sc, c->stream));
     __bf16 *X = reinterpret_cast<__bf16 *>(c->ws + c->o_sx);
     __bf16 *A = reinterpret_cast<__bf16 *>(c->ws + c->o_sa), *B = reinterpret_cast<__bf16 *>(c->ws + c->o_sb);
     float *Y = reinterpret_cast<float *>(c->ws + c->o_sy);
@@ -675,15 +675,20 @@ pbs_status run_surrogate(pbs_ctx *c)
     NetPacked P;
     net_carve(c->ws + c->o_spk, P);
     HIPCHK(c, net_forward(P, X, A, B, A, Y, c->g.nz, c->g.nx, c->g.ny, c->stream));
-    HIPCHK(c, sur_sum(Y, slab, sc + 4, c->stream));
-    double h[5];
+    HIPCHK(c, sur_sum(Y, slab, sc + 5, c->stream));
+    double h[6];
     HIPCHK(c, hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const double cb = h[0] > 0.0 ? h[0] : 1.0;
-    const double einj = h[2], epred = cb * h[4], budget = (1.0 - c->sur_leak) * einj;
-    double res = budget > 0.0 ? std::fabs(epred - budget) / budget : (epred == 0.0 ? 0.0 : INFINITY);
-    if (!std::isfinite(epred)) res = INFINITY;
-    const double rep[8] = {res, 0.0, budget, epred, cb, einj, NAN, c->sur_leak};
+    const double einj = h[2], e0 = h[4], epred = cb * h[5];
+    // energy balance of generation 1: what the network deposits against the injected energy less
+    // the modelled leak, relative to the whole deposit of the beam
+    const double x = 1.0 - e0 / c->beam.e0;
+    const double leak = std::min(0.95, std::max(0.0, c->sur_leak[0] + x * (c->sur_leak[1] + x * c->sur_leak[2])));
+    const double budget = (1.0 - leak) * einj, etot = e0 - einj + epred;
+    double res = etot > 0.0 ? std::fabs(epred - budget) / etot : INFINITY;
+    if (!std::isfinite(epred) || !std::isfinite(res)) res = INFINITY;
+    const double rep[10] = {res, 0.0, budget, epred, cb, einj, NAN, leak, e0, x};
     std::memcpy(c->sur_rep, rep, sizeof(rep));
     if (res <= c->sur_tol) {
         HIPCHK(c, sur_combine(c->edep(0), c->frec(0, 0), Y, sc, slab, c->stream));
@@ -873,7 +878,7 @@ pbs_status pbs_set_surrogate(pbs_ctx *c, const void *weights, size_t bytes, doub
         if (bytes != 0) return fail(c, PBS_EINVAL, "weights NULL with nonzero size");
         c->sur = 1;
         c->sur_params.clear();
-        c->sur_leak = 0.0;
+        c->sur_leak[0] = c->sur_leak[1] = c->sur_leak[2] = 0.0;
         c->sur_tol = 0.0;
         layout(c);
         return PBS_OK;
@@ -886,14 +891,15 @@ pbs_status pbs_set_surrogate(pbs_ctx *c, const void *weights, size_t bytes, doub
     if (h.magic != PBS_NET_MAGIC || h.version != PBS_NET_VERSION || h.nparam != np || h.nfeat != (unsigned)SUR_NFEAT)
         return fail(c, PBS_EINVAL, "weights blob header does not match this network");
     if (bytes != sizeof(h) + np * sizeof(float)) return fail(c, PBS_EINVAL, "weights blob size mismatch");
-    if (!std::isfinite(h.leak) || h.leak < 0 || h.leak >= 1) return fail(c, PBS_EINVAL, "leak must be in [0, 1)");
+    for (double v : h.leak)
+        if (!std::isfinite(v)) return fail(c, PBS_EINVAL, "leak model coefficients must be finite");
     std::vector<float> p(np);
     std::memcpy(p.data(), (const char *)weights + sizeof(h), np * sizeof(float));
     for (float v : p)
         if (!std::isfinite(v)) return fail(c, PBS_EINVAL, "weights must be finite");
     c->sur = 2;
     c->sur_params.swap(p);
-    c->sur_leak = h.leak;
+    std::memcpy(c->sur_leak, h.leak, sizeof(h.leak));
     c->sur_tol = tol;
     layout(c);
     return PBS_OK;
@@ -927,12 +933,13 @@ pbs_status pbs_surrogate_report(pbs_ctx *c, double *out, int n)
     if (!c) return PBS_EINVAL;
     if (!c->sur) return fail(c, PBS_ESTATE, "no surrogate report without pbs_set_surrogate");
     if (c->state < ST_BEAM || !c->closed) return fail(c, PBS_ESTATE, "report before run_beam");
-    if (!out || n < 0 || n > 8) return fail(c, PBS_EINVAL, "report holds at most 8 values");
+    if (!out || n < 0 || n > 10) return fail(c, PBS_EINVAL, "report holds at most 10 values");
     if (c->sur == 1) {
-        double h[4];
+        double h[5];
         HIPCHK(c, hipMemcpyAsync(h, c->scal(), sizeof(h), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        const double rep[8] = {NAN, 1.0, h[2], NAN, h[0] > 0.0 ? h[0] : 1.0, h[2], h[3], 0.0};
+        const double lk = h[2] > 0.0 ? 1.0 - h[3] / h[2] : NAN;
+        const double rep[10] = {NAN, 1.0, NAN, NAN, h[0] > 0.0 ? h[0] : 1.0, h[2], h[3], lk, h[4], 1.0 - h[4] / c->beam.e0};
         std::memcpy(c->sur_rep, rep, sizeof(rep));
     } else {
         HIPCHK(c, hipStreamSynchronize(c->stream));

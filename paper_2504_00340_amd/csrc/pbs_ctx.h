@@ -49,11 +49,11 @@ struct pbs_ctx {
 
     // surrogate of the scattered generation
     int sur = 0;                  // 0 off, 1 recording, 2 surrogate with fallback
-    double sur_tol = 0, sur_leak = 0;
+    double sur_tol = 0, sur_leak[3] = {0, 0, 0};
     std::vector<float> sur_params;
     int kact = 0;                 // generations marched (g.ngen, or 1 while the surrogate runs)
     bool feat_on = false;         // record the per-slice surrogate data in the march
-    double sur_rep[8] = {};
+    double sur_rep[10] = {};
     pbs_beam beam{};
     size_t o_fl = 0, o_frec = 0, o_scal = 0, o_sx = 0, o_sy = 0, o_sa = 0, o_sb = 0, o_spk = 0, o_smaster = 0;
     size_t d_wmom = 0;

@@ -50,7 +50,7 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
     T fin = 0, fcl = 0, fop = 0;    // psi1 - psi2 of group g+1: input, after close, after open
     T U0 = 0, U1 = 0, U2 = 0;       // re-emission energy scans of states 0, 1, 2
     double ph0 = 0, ph1 = 0, ph2 = 0, injc = 0, injo = 0;
-    double fic = 0, fio = 0, fme = 0, fmn = 0;   // surrogate features (energy sent to the next generation, moments)
+    T fic = 0, fio = 0, fme = 0, fmn = 0;   // surrogate records (energy sent to the next generation, moments)
     const bool hasQ = P.Q != nullptr, hasW = SPLIT ? P.Wh != nullptr : P.W != nullptr;
     const bool feat = P.inj_c != nullptr;
     for (int g = P.G - 1; g >= 0; --g) {
@@ -117,12 +117,12 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
             if (feat) {
                 // energy the re-emission puts into the next generation (the dInj functional of its
                 // source summed over destination angles, which the angular law conserves), moments
-                const double wi = P.dInj[g];
-                if (CL) fic += wi * (double)((U0 + U1) * idE);
+                const T wi = (T)P.dInj[g];
+                if (CL) fic += wi * ((U0 + U1) * idE);
                 if (OP) {
-                    fio += wi * (double)((U1 + U2) * idE);
-                    fme += P.wmom[g] * (double)z1 + P.wmom[2 * P.G + g] * (double)z2;
-                    fmn += P.wmom[P.G + g] * (double)z1;
+                    fio += wi * ((U1 + U2) * idE);
+                    fme += (T)P.wmom[g] * z1 + (T)P.wmom[2 * P.G + g] * z2;
+                    fmn += (T)P.wmom[P.G + g] * z1;
                 }
             }
             if (hasW) {
@@ -163,11 +163,11 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
     if (CL) P.dep_c[line] = dac * (ph0 + ph1 - injc) * P.scale;
     if (OP) P.dep_o[line] = dao * (ph1 + ph2 - injo) * P.scale;
     if (feat) {
-        if (CL) P.inj_c[line] = dac * fic * P.scale;
+        if (CL) P.inj_c[line] = dac * (double)fic * P.scale;
         if (OP) {
-            P.inj_o[line] = dao * fio * P.scale;
-            P.mom_e[line] = fme * P.scale;
-            P.mom_n[line] = fmn * P.scale;
+            P.inj_o[line] = dao * (double)fio * P.scale;
+            P.mom_e[line] = (double)fme * P.scale;
+            P.mom_n[line] = (double)fmn * P.scale;
         }
     }
 }

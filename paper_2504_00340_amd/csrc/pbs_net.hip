@@ -438,19 +438,25 @@ __global__ __launch_bounds__(1024) void sur_scalars_kernel(const double *__restr
                                                            const double *__restrict__ edep0, long n,
                                                            double *__restrict__ scal)
 {
-    __shared__ double r[4][1024];
-    double mi = 0.0, mn = 0.0, si = 0.0, so = 0.0;
+    __shared__ double r[5][1024];
+    double mi = 0.0, mn = 0.0, si = 0.0, so = 0.0, s0 = 0.0;
     for (long i = threadIdx.x; i < n; i += 1024) {
         const double I = finj[i];
         mi = fmax(mi, I);
         mn = fmax(mn, fmn[i]);
         si += I;
-        if (edep0) so += edep[i] - edep0[i] + I;
+        if (edep0) {
+            so += edep[i] - edep0[i] + I;
+            s0 += edep0[i];
+        } else {
+            s0 += edep[i];
+        }
     }
     r[0][threadIdx.x] = mi;
     r[1][threadIdx.x] = mn;
     r[2][threadIdx.x] = si;
     r[3][threadIdx.x] = so;
+    r[4][threadIdx.x] = s0;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
@@ -459,10 +465,11 @@ __global__ __launch_bounds__(1024) void sur_scalars_kernel(const double *__restr
             r[1][t] = fmax(r[1][t], r[1][t + w]);
             r[2][t] += r[2][t + w];
             r[3][t] += r[3][t + w];
+            r[4][t] += r[4][t + w];
         }
         __syncthreads();
     }
-    if (threadIdx.x < 4) scal[threadIdx.x] = r[threadIdx.x][0];
+    if (threadIdx.x < 5) scal[threadIdx.x] = r[threadIdx.x][0];
 }
 
 hipError_t sur_scalars(const double *finj, const double *fmn, const double *edep, const double *edep0, long n,
@@ -480,12 +487,12 @@ __global__ void sur_features_kernel(SurFeatIn F, const double *__restrict__ scal
     if (pq >= F.NP) return;
     const double cb = scal[0] > 0.0 ? scal[0] : 1.0, cn = scal[1];
     const double icb = 1.0 / cb;
-    double f[3] = {0.0, 0.0, 0.0};
+    double f[4] = {0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < F.nz; ++s) {
         const long i = (long)s * F.NP + pq;
         const double I = F.finj[i], me = F.fme[i], mn = F.fmn[i], r = F.rho[i];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
+        for (int j = 0; j < 4; ++j) {
             const double a = exp(-r * F.dz / SUR_FILTER_L[j]);
             f[j] = a * f[j] + (1.0 - a) * I;
         }
@@ -498,6 +505,7 @@ __global__ void sur_features_kernel(SurFeatIn F, const double *__restrict__ scal
         v[4] = (__bf16)(f[1] * icb);
         v[5] = (__bf16)(f[2] * icb);
         v[6] = (__bf16)(eb / SUR_EREF);
+        v[7] = (__bf16)(f[3] * icb);
         *reinterpret_cast<bf16x8 *>(X + i * NET_CX) = v;
         if (T) T[i] = (float)((F.edep[i] - F.edep0[i] + I) * icb);
     }

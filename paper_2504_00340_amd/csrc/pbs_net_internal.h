@@ -9,7 +9,7 @@ constexpr int NET_LAYERS = 4;
 constexpr int NET_CX = 8;    // stored input channels (BF16) per pixel
 constexpr int NET_CH = 32;   // hidden channels
 constexpr int NET_CG = 8;    // stored channels of the output gradient
-constexpr int SUR_NFEAT = 7; // feature channels the solver writes (the rest are zero)
+constexpr int SUR_NFEAT = 8; // feature channels the solver writes
 
 struct NetLayerDef {
     int cin, cout;    // channels of the layer (parameters [cout][cin][3][3], bias [cout])
@@ -39,7 +39,7 @@ hipError_t net_forward(const NetPacked &P, const __bf16 *x, __bf16 *a1, __bf16 *
 // ------------------------------------------------------------------ per-slice surrogate features
 // Depth filters of the injected energy: F_j(s) = a F_j(s-1) + (1 - a) I(s), a = exp(-rho dz / L_j),
 // with L_j in water-equivalent cm.
-constexpr double SUR_FILTER_L[3] = {0.5, 2.0, 6.0};
+constexpr double SUR_FILTER_L[4] = {0.5, 2.0, 6.0, 15.0};
 constexpr double SUR_EREF = 250.0;   // MeV, scale of the mean-energy channel
 
 struct SurFeatIn {
@@ -54,7 +54,7 @@ struct SurFeatIn {
 };
 
 // scal[0] = max finj, scal[1] = max fmn, scal[2] = sum finj, scal[3] = sum(edep - edep0 + finj)
-// (0 without edep0); fixed-order reductions in one block
+// (0 without edep0), scal[4] = sum edep0 (sum edep without edep0); fixed-order reductions in one block
 hipError_t sur_scalars(const double *finj, const double *fmn, const double *edep, const double *edep0, long n,
                        double *scal, hipStream_t st);
 // X [nz][NP][8] BF16 features; T [nz][NP] FP32 targets (optional)

@@ -32,8 +32,9 @@ EXPORTS = ["pbs_create", "pbs_workspace_bytes", "pbs_bind", "pbs_set_phantom", "
            "pbs_net_gradient", "pbs_net_train_step", "pbs_net_last_error", "pbs_net_destroy"]
 _NORET = ("pbs_last_error", "pbs_destroy", "pbs_batch_last_error", "pbs_batch_destroy", "pbs_net_last_error",
           "pbs_net_destroy")
-PBS_NET_MAGIC, PBS_NET_VERSION, PBS_NET_CIN, SUR_NFEAT = 0x4E534250, 1, 8, 7
-REPORT_KEYS = ["residual", "fallback", "budget", "predicted", "scale", "injected", "own_deposit", "leak"]
+PBS_NET_MAGIC, PBS_NET_VERSION, PBS_NET_CIN, SUR_NFEAT = 0x4E534250, 1, 8, 8
+REPORT_KEYS = ["residual", "fallback", "budget", "predicted", "scale", "injected", "own_deposit", "leak",
+               "primary_deposit", "primary_escape"]
 KINDS = ["epass", "tpass", "apass", "qgemm", "dose"]
 
 
@@ -131,6 +132,16 @@ def _mk(cls, d):
     return cls(**{k: d[k] for k, _ in cls._fields_})
 
 
+SURROGATE_WEIGHTS = os.path.join(_HERE, "data", "surrogate_c5.pbsn")
+
+
+def surrogate_weights() -> bytes:
+    """Weights of the generation-1 surrogate trained on the config-5 workload (written by
+    train_surrogate.py)."""
+    with open(SURROGATE_WEIGHTS, "rb") as f:
+        return f.read()
+
+
 def param_count() -> int:
     n = C.c_size_t()
     rc = lib().pbs_net_param_count(C.byref(n))
@@ -139,21 +150,23 @@ def param_count() -> int:
     return n.value
 
 
-def pack_weights(params, leak: float) -> bytes:
-    """Weights blob of pbs_set_surrogate: 64-byte header + FP32 parameters."""
+def pack_weights(params, leak) -> bytes:
+    """Weights blob of pbs_set_surrogate: 64-byte header + FP32 parameters.  leak: coefficients
+    (l0, l1, l2) of the leak model l(x) = l0 + l1 x + l2 x^2 (a scalar means a constant)."""
     p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
-    head = np.zeros(6, dtype=np.float64)   # leak + 5 reserved: 48 bytes after the 16-byte ids
-    head[0] = leak
+    head = np.zeros(6, dtype=np.float64)   # leak model + 3 reserved: 48 bytes after the 16-byte ids
+    lk = np.atleast_1d(np.asarray(leak, dtype=np.float64))
+    head[:lk.size] = lk
     u = np.array([PBS_NET_MAGIC, PBS_NET_VERSION, p.size, SUR_NFEAT], dtype=np.uint32)
     return u.tobytes() + head.tobytes() + p.tobytes()
 
 
 def unpack_weights(blob: bytes):
-    """(params float32, leak) from a weights blob."""
+    """(params float32, leak model coefficients) from a weights blob."""
     u = np.frombuffer(blob[:16], dtype=np.uint32)
     if u[0] != PBS_NET_MAGIC or u[1] != PBS_NET_VERSION:
         raise ValueError("not a pbsplit network blob")
-    leak = float(np.frombuffer(blob[16:24], dtype=np.float64)[0])
+    leak = np.frombuffer(blob[16:40], dtype=np.float64).copy()
     return np.frombuffer(blob[64:], dtype=np.float32).copy(), leak
 
 
@@ -269,8 +282,8 @@ class Solver:
         return out
 
     def surrogate_report(self) -> dict:
-        out = (C.c_double * 8)()
-        self._check(self.L.pbs_surrogate_report(self.ctx, out, 8))
+        out = (C.c_double * 10)()
+        self._check(self.L.pbs_surrogate_report(self.ctx, out, 10))
         return {k: out[i] for i, k in enumerate(REPORT_KEYS)}
 
     def close(self):

@@ -229,8 +229,7 @@ def test_features_and_targets_match_oracle(rec_case, S):
     Xr = S.features(rec_ref, c["rho"], g["dz"], c["phys"]["kappa0"])
     vol = o.dx * o.dy * g["dz"]
     Tr = S.target(rec_ref, dose_ref * c["rho"] * vol)
-    assert np.all(X[..., 7] == 0)
-    for k in range(7):
+    for k in range(8):
         err = np.abs(X[..., k] - Xr[..., k]) - 2.0 ** -7 * np.abs(Xr[..., k])
         assert err.max() <= 1e-30, (k, err.max())
     assert np.abs(T - Tr).max() <= 1e-6 * np.abs(Tr).max()
@@ -303,3 +302,53 @@ def test_surrogate_refuses_stepping(S):
     s = _solver(c, "fp32", surrogate=blob)
     with pytest.raises(PbsError):
         s.step(1)
+
+
+# ------------------------------------------------------------------------------ the trained network
+def test_trained_surrogate_gain():
+    """Held-out config-5 beams with the shipped weights: accepted beams are within 1e-2 (dose
+    relative L2) of the plain K = 1 march, several times closer than the primaries alone (the method
+    without generation 1), and faster than the plain march; a beam the residual test rejects gets
+    exactly the plain dose.  One accepted beam is also checked against the plain march in FP64."""
+    import time
+
+    import torch
+
+    from paper_2504_00340_amd.pbsplit import Solver, surrogate_weights
+
+    blob = surrogate_weights()
+
+    def run(c, mode, prec="fp32"):
+        g = dict(c["grid"], ngen=1) if mode == "primaries" else c["grid"]
+        s = Solver(g, c["phys"], prec, surrogate=blob if mode == "surrogate" else None, residual_tol=1e-2)
+        s.set_phantom(c["rho"])
+        s.set_beam(c["beam"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run()
+        rep = s.surrogate_report() if mode == "surrogate" else None
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        d = s.dose()
+        s.close()
+        return d, dt, rep
+
+    for seed in (100001, 100002, 100000):
+        c = I.config5(seed)
+        print("case trained surrogate seed", seed, "E0", c["beam"]["e0"], flush=True)
+        plain, tp, _ = run(c, "plain")
+        prim, _, _ = run(c, "primaries")
+        sur, ts, rep = run(c, "surrogate")
+        nrm = np.linalg.norm(plain)
+        e_sur = np.linalg.norm(sur - plain) / nrm
+        e_prim = np.linalg.norm(prim - plain) / nrm
+        print(f"  err surrogate {e_sur:.3e} primaries {e_prim:.3e} residual {rep['residual']:.3e} "
+              f"fallback {rep['fallback']} ms plain {tp * 1e3:.0f} surrogate {ts * 1e3:.0f}", flush=True)
+        if rep["fallback"]:
+            assert seed == 100000 and np.array_equal(sur, plain)
+            continue
+        assert e_sur <= 1e-2 and e_sur < 0.2 * e_prim
+        assert ts < 0.6 * tp
+        if seed == 100002:
+            p64, _, _ = run(c, "plain", "fp64")
+            assert np.linalg.norm(sur - p64) / np.linalg.norm(p64) <= 1e-2

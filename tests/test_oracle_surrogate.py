@@ -170,7 +170,8 @@ def test_depth_filter_closed_form():
     s = np.arange(nz)[:, None, None]
     for j, L in enumerate(S.FILTER_L):
         a = np.exp(-1.3 * dz / L)
-        assert np.allclose(X[..., 3 + j], (1 - a ** (s + 1)) * np.ones((nz, nx, ny)), rtol=1e-13, atol=1e-15)
+        ch = 3 + j if j < 3 else 7
+        assert np.allclose(X[..., ch], (1 - a ** (s + 1)) * np.ones((nz, nx, ny)), rtol=1e-13, atol=1e-15)
     assert np.allclose(X[..., 2], 1.0)
 
 
