@@ -48,7 +48,7 @@ def algorithmic(grid, tsz=4):
                 qgemm=("flops", qg_flops, qg_bytes))
 
 
-KIND_KERNEL = {"tpass": "tpass_kernel<float, 1>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16x3_kernel",
+KIND_KERNEL = {"tpass": "tpass_affine_kernel<64>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16x3_kernel<256>",
                "epass": "epass_kernel<float, 3, true>"}
 
 

@@ -1,6 +1,6 @@
 """Train the surrogate of generation 1 on the solver's own output, on one GPU.
 
-  python -m paper_2504_00340_amd.train_surrogate --train-seeds 160 --eval-seeds 8 --out <blob>
+  python -m paper_2504_00340_amd.train_surrogate --out <blob>      (240 beams, 30000 Adam steps)
 
 1. Data: for every training seed, a K = 1 beam of the surrogate workload (64 x 64 cells on
    +-4 cm, 16 x 16 angular nodes on +-0.15 rad, 96 groups on [0, E0 + 10] MeV, 300 depth steps over
@@ -153,10 +153,10 @@ def evaluate(blob: bytes, seeds, nz: int = 300, tol: float = 1e-2, log=print):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--train-seeds", type=int, default=160)
+    ap.add_argument("--train-seeds", type=int, default=240)
     ap.add_argument("--eval-seeds", type=int, default=8)
     ap.add_argument("--nz", type=int, default=300)
-    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--steps", type=int, default=30000)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=1)
