@@ -48,7 +48,7 @@ def algorithmic(grid, tsz=4):
                 qgemm=("flops", qg_flops, qg_bytes))
 
 
-KIND_KERNEL = {"tpass": "tpass_affine_kernel<64>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16x3_kernel<256>",
+KIND_KERNEL = {"tpass": "tpass_affine_kernel<64>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16s_kernel<256, 2>",
                "epass": "epass_kernel<float, 3, true>"}
 
 
@@ -181,7 +181,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--case", default="water", choices=["water", "bone", "lung"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--source", default="bf16x3", choices=["bf16x3", "fp32"],
+    ap.add_argument("--source", default="bf16x2", choices=["bf16x2", "bf16x3", "fp32"],
                     help="arithmetic of the angular source product (FP32 contexts)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-beams", type=int, default=8,
@@ -208,11 +208,12 @@ def main():
     print(f"bench: {cfg['name']} {args.precision}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
           flush=True)
     s = Solver(g, cfg["phys"], precision=args.precision, device="cuda:0")
-    split = args.precision == "fp32" and args.source == "bf16x3"
+    split = args.precision == "fp32" and args.source != "fp32"
+    nprod = 3 if args.source == "bf16x3" else 2
     if args.precision == "fp32":
-        from paper_2504_00340_amd.pbsplit import PBS_SRC_BF16X3, PBS_SRC_FP32
+        from paper_2504_00340_amd.pbsplit import PBS_SRC_BF16X2, PBS_SRC_BF16X3, PBS_SRC_FP32
 
-        s.set_source_precision(PBS_SRC_BF16X3 if split else PBS_SRC_FP32)
+        s.set_source_precision({"bf16x2": PBS_SRC_BF16X2, "bf16x3": PBS_SRC_BF16X3}.get(args.source, PBS_SRC_FP32))
     s.set_phantom(cfg["rho"])
     s.set_beam(cfg["beam"])
     s.step(args.warmup)
@@ -238,23 +239,23 @@ def main():
     avg_s = ms / max(n, 1) / 1e3
     if alg[dom][0] == "bytes":
         achieved = alg[dom][1] / avg_s / 1e9
-        split_ok = args.precision == "fp32" and args.case == "water" and (dom != "qgemm" or split)
+        split_ok = args.precision == "fp32" and args.case == "water" and args.source == "bf16x2"
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom) if split_ok else None, "kernel": dom,
                 "algorithmic_bytes_per_launch": alg[dom][1], "avg_launch_ms": avg_s * 1e3}
     else:
         mfma = args.precision == "fp32" and (g["nth"] - 1) ** 2 >= 128
         if split:
-            # executed BF16 MFMA work: three bf16 products per FP32 multiply-add
-            achieved = 3.0 * alg[dom][1] / avg_s / 1e12
+            # executed BF16 MFMA work: two or three bf16 products per FP32 multiply-add
+            achieved = nprod * alg[dom][1] / avg_s / 1e12
             peak = BF16_MFMA_TFLOPS
         else:
             achieved = alg[dom][1] / avg_s / 1e12
             peak = FP32_MFMA_TFLOPS if mfma else FP32_VALU_TFLOPS
         roof = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "dtype": "bf16x3" if split else args.precision,
-                "hbm_traffic_bytes": measured_traffic(dom) if split and args.case == "water" else None,
-                "traffic": None, "kernel": dom, "algorithmic_flops_per_launch": alg[dom][1],
+                "frac": achieved / peak, "dtype": args.source if split else args.precision,
+                "traffic": measured_traffic(dom) if args.source == "bf16x2" and args.case == "water" else None,
+                "kernel": dom, "algorithmic_flops_per_launch": alg[dom][1],
                 "avg_launch_ms": avg_s * 1e3}
     out = {
         "metric": "phase-space cell-updates/s per z-step",
@@ -271,7 +272,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{cfg['name']}: 64x64 lateral x 32x32 angles x 128 groups x 4 generations, "
                                f"300 depth steps", "steps_per_beam": g["nz"], "precision": args.precision,
-                   "source_product": "bf16x3" if split else args.precision},
+                   "source_product": args.source if split else args.precision},
         "interior_cell_updates_per_s": interior / dt,
         "beams_per_s": 1.0 / (dt * g["nz"]),
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},

@@ -353,9 +353,9 @@ EParams<T> eparams(pbs_ctx *c, int k, int lay_c, int lay_o, double h)
     P.W = (k + 1 < c->kact) ? c->W<T>() : nullptr;
     P.Wh = P.Wl = nullptr;
     P.NOCT = c->NOCT;
-    if (P.W && c->Kpb > 0 && c->src_mode == PBS_SRC_BF16X3) {
+    if (P.W && c->Kpb > 0 && (c->src_mode == PBS_SRC_BF16X3 || c->src_mode == PBS_SRC_BF16X2)) {
         P.Wh = reinterpret_cast<unsigned short *>(c->ws + c->o_W);
-        P.Wl = P.Wh + c->Wb_half;
+        P.Wl = c->src_mode == PBS_SRC_BF16X3 ? P.Wh + c->Wb_half : nullptr;
     }
     P.rho_c = lay_c >= 0 ? c->rhoT<T>(lay_c) : nullptr;
     P.rho_o = lay_o >= 0 ? c->rhoT<T>(lay_o) : nullptr;
@@ -417,9 +417,10 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
             Q.ns = (mode == MODE_PAIR) ? 2 : 1;
             ProfScope ps(c, PBS_K_QGEMM);
             if constexpr (sizeof(T) == 4) {
-                if (c->Kpb > 0 && c->src_mode == PBS_SRC_BF16X3) {
+                if (c->Kpb > 0 && (c->src_mode == PBS_SRC_BF16X3 || c->src_mode == PBS_SRC_BF16X2)) {
                     const unsigned short *ah = reinterpret_cast<const unsigned short *>(c->ws + c->o_bf);
-                    HIPCHK(c, launch_qgemm_bf16x3(Q, ah, ah + (size_t)c->Mp * c->Kpb, c->Kpb, c->stream));
+                    HIPCHK(c, launch_qgemm_bf16s(Q, ah, ah + (size_t)c->Mp * c->Kpb, c->Kpb,
+                                                 c->src_mode == PBS_SRC_BF16X3 ? 3 : 2, c->stream));
                     continue;
                 }
             }
@@ -754,7 +755,7 @@ pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precisi
         c->Mp = (c->NA + 127) / 128 * 128;
         if (precision == PBS_FP32) {
             c->Kpb = (c->NA + 31) / 32 * 32;
-            c->src_mode = PBS_SRC_BF16X3;
+            c->src_mode = PBS_DEFAULT_SRC;
         }
     }
     try {
@@ -998,8 +999,9 @@ pbs_status pbs_apply(pbs_ctx *c, int op, int layer, double h)
 pbs_status pbs_set_source_precision(pbs_ctx *c, int mode)
 {
     if (!c) return PBS_EINVAL;
-    if (mode != PBS_SRC_FP32 && mode != PBS_SRC_BF16X3) return fail(c, PBS_EINVAL, "unknown source precision");
-    if (mode == PBS_SRC_BF16X3 && c->Kpb == 0)
+    if (mode != PBS_SRC_FP32 && mode != PBS_SRC_BF16X3 && mode != PBS_SRC_BF16X2)
+        return fail(c, PBS_EINVAL, "unknown source precision");
+    if (mode != PBS_SRC_FP32 && c->Kpb == 0)
         return fail(c, PBS_EUNSUPPORTED, "split-BF16 source product needs an FP32 context with >= 128 angular unknowns");
     c->src_mode = mode;
     return PBS_OK;

@@ -124,7 +124,7 @@ pbs_status setup_wave(pbs_batch *b, const std::vector<int> &w, std::vector<BeamD
         d.psi = reinterpret_cast<float *>(W + s.psi);
         d.Q = reinterpret_cast<float *>(W + s.Q);
         d.Wh = reinterpret_cast<unsigned short *>(W + s.Wh);
-        d.Wl = reinterpret_cast<unsigned short *>(W + s.Wl);
+        d.Wl = src_nprod(PBS_DEFAULT_SRC) == 3 ? reinterpret_cast<unsigned short *>(W + s.Wl) : nullptr;
         d.rho = reinterpret_cast<const float *>(W + s.rho);
         d.dep = reinterpret_cast<double *>(W + s.dep);
         d.edep = reinterpret_cast<double *>(W + s.edep);
@@ -218,6 +218,7 @@ BatchShape shape(const pbs_batch *b)
     Sh.Alo = Sh.Ahi + (size_t)b->Mp * b->Kpb;
     Sh.Kpb = b->Kpb;
     Sh.Mp = b->Mp;
+    Sh.nprod = src_nprod(PBS_DEFAULT_SRC);
     Sh.nx = b->nx;
     Sh.ny = b->ny;
     Sh.nth = b->nth;

@@ -25,7 +25,8 @@ struct EParams {
                             // and opening (1) half-step, or null
     T *W;                   // [2][G][NLINE] energy-scanned psi^1 of this generation, summed over the two
                             // states of each half-step (0: close, 1: open), or null
-    unsigned short *Wh, *Wl;   // split-BF16 form of W (hi, lo): [2][G][NPB][NOCT][PT][8], a' = 8*oct + e
+    unsigned short *Wh, *Wl;   // split-BF16 form of W (hi, lo): [2][G][NPB][NOCT][PT][8], a' = 8*oct + e;
+                               // Wl null: hi only
     int NOCT;                  // ceil(NA / 8)
     const T *rho_c;         // densities of the closing half-step layer [NPpad] (MODE_CLOSE bit)
     const T *rho_o;         // densities of the opening half-step layer [NPpad] (MODE_OPEN bit)
@@ -102,6 +103,7 @@ struct BatchShape {
     const float *theta, *lam, *S;          // angular tables
     const unsigned short *Ahi, *Alo;       // split-BF16 P2, [Mp][Kpb]
     int Kpb, Mp;
+    int nprod;                             // 3: scanned fluence as hi + lo; 2: hi only (no lo array)
     int nx, ny, nth, m, NA, NPB, NOCT, ngen;
     long NLINE;
     float dx, dy;
@@ -133,8 +135,10 @@ template <typename T>
 hipError_t launch_initial(T *psi0, const double *E1, const double *E2, const double *lat, long center_a, int G,
                           int NA, int NPB, int NP, hipStream_t st);
 
-hipError_t launch_qgemm_bf16x3(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
-                               hipStream_t st, int bn = 256);
+// split-BF16 source product: P2 as hi + lo; the scanned fluence as hi + lo (nprod = 3: three BF16
+// products) or rounded once to BF16 (nprod = 2: two products)
+hipError_t launch_qgemm_bf16s(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
+                              int nprod, hipStream_t st, int bn = 256);
 hipError_t launch_apass_mfma32(const AParams<float> &P, const float *Ktab, long nstack, hipStream_t st);
 
 bool apass_supported(int nth);

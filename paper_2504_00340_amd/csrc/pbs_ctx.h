@@ -9,6 +9,10 @@
 
 enum { ST_CREATED = 0, ST_BOUND = 1, ST_PHANTOM = 2, ST_BEAM = 3 };
 
+// source-product arithmetic of FP32 contexts with >= 128 angular unknowns (and of every batch)
+constexpr int PBS_DEFAULT_SRC = PBS_SRC_BF16X2;
+inline int src_nprod(int mode) { return mode == PBS_SRC_BF16X2 ? 2 : 3; }
+
 struct pbs_ctx {
     pbs_grid g;
     pbs_physics ph;

@@ -139,8 +139,8 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
                     buf[3 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, (__bf16)(vo - (float)ho));
                     __syncthreads();
                     const int t = threadIdx.x;
-                    const int arr = t >> 5;   // 0 hi c, 1 lo c, 2 hi o, 3 lo o
-                    const bool want = t < 128 && ((arr < 2) ? CL : OP);
+                    const int arr = t >> 5;   // 0 hi c, 1 lo c, 2 hi o, 3 lo o (lo parts only with Wl)
+                    const bool want = t < 128 && ((arr < 2) ? CL : OP) && (!(arr & 1) || P.Wl != nullptr);
                     if (want) {
                         const long SB = (long)P.G * (S / P.NAPT) * P.NOCT * (PBS_PT * 8);
                         const long ob = (((long)g * (S / P.NAPT) + pbk) * P.NOCT + oct) * (PBS_PT * 8) + (t & 31) * 8 +
@@ -980,8 +980,8 @@ __global__ __launch_bounds__(256) void qgemm_mfma_f32_kernel(QParams<float> P, i
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-template <int BN>
-__device__ __forceinline__ void qgemm_bf16x3_body(const QParams<float> &P, const unsigned short *__restrict__ Ahi,
+template <int BN, int NPROD>
+__device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const unsigned short *__restrict__ Ahi,
                                                   const unsigned short *__restrict__ Alo, int Kp, int nmt, int nnt,
                                                   long nlogical, long per_xcd, long bid)
 {
@@ -989,7 +989,8 @@ __device__ __forceinline__ void qgemm_bf16x3_body(const QParams<float> &P, const
     constexpr int NPBT = BN / 32;         // lateral tiles per block
     constexpr int WN = BN / 64;           // waves along N (2 along M)
     constexpr int NT = 128 * WN;          // threads
-    __shared__ unsigned short sAh[128 * LD], sAl[128 * LD], sBh[BN * LD], sBl[BN * LD];
+    constexpr bool BLO = NPROD == 3;      // the lo part of the scanned fluence takes part
+    __shared__ unsigned short sAh[128 * LD], sAl[128 * LD], sBh[BN * LD], sBl[BLO ? BN * LD : 8];
     const long logical = (bid & 7) * per_xcd + (bid >> 3);
     if (logical >= nlogical) return;
     const int mt = (int)(logical % nmt);
@@ -1031,7 +1032,7 @@ __device__ __forceinline__ void qgemm_bf16x3_body(const QParams<float> &P, const
             const int oc = kt * (BK / 8) + boct + 2 * h;
             if (bok && oc < P.NOCT) {
                 rbh[h] = *reinterpret_cast<const u16x8 *>(P.Bh + bbase + (long)oc * (PBS_PT * 8));
-                rbl[h] = *reinterpret_cast<const u16x8 *>(P.Bl + bbase + (long)oc * (PBS_PT * 8));
+                if constexpr (BLO) rbl[h] = *reinterpret_cast<const u16x8 *>(P.Bl + bbase + (long)oc * (PBS_PT * 8));
             } else {
                 rbh[h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
                 rbl[h] = rbh[h];
@@ -1048,7 +1049,7 @@ __device__ __forceinline__ void qgemm_bf16x3_body(const QParams<float> &P, const
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             *reinterpret_cast<u16x8 *>(&sBh[bcol * LD + (boct + 2 * h) * 8]) = rbh[h];
-            *reinterpret_cast<u16x8 *>(&sBl[bcol * LD + (boct + 2 * h) * 8]) = rbl[h];
+            if constexpr (BLO) *reinterpret_cast<u16x8 *>(&sBl[bcol * LD + (boct + 2 * h) * 8]) = rbl[h];
         }
     };
     gload(0);
@@ -1070,14 +1071,16 @@ __device__ __forceinline__ void qgemm_bf16x3_body(const QParams<float> &P, const
             for (int j = 0; j < 2; ++j) {
                 const int cidx = wn * 64 + j * 32 + (lane & 31);
                 bh[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sBh[cidx * LD + ko]));
-                bl[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sBl[cidx * LD + ko]));
+                if constexpr (BLO)
+                    bl[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sBl[cidx * LD + ko]));
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    if constexpr (BLO)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
                 }
         }
@@ -1101,26 +1104,29 @@ __device__ __forceinline__ void qgemm_bf16x3_body(const QParams<float> &P, const
         }
 }
 
-template <int BN>
-__global__ __launch_bounds__(2 * BN) void qgemm_bf16x3_kernel(QParams<float> P, const unsigned short *__restrict__ Ahi,
-                                                              const unsigned short *__restrict__ Alo, int Kp, int nmt,
-                                                              int nnt, long nlogical, long per_xcd)
+template <int BN, int NPROD>
+__global__ __launch_bounds__(2 * BN) void qgemm_bf16s_kernel(QParams<float> P, const unsigned short *__restrict__ Ahi,
+                                                             const unsigned short *__restrict__ Alo, int Kp, int nmt,
+                                                             int nnt, long nlogical, long per_xcd)
 {
-    qgemm_bf16x3_body<BN>(P, Ahi, Alo, Kp, nmt, nnt, nlogical, per_xcd, blockIdx.x);
+    qgemm_bf16s_body<BN, NPROD>(P, Ahi, Alo, Kp, nmt, nnt, nlogical, per_xcd, blockIdx.x);
 }
 
-hipError_t launch_qgemm_bf16x3(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
-                               hipStream_t st, int bn)
+hipError_t launch_qgemm_bf16s(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
+                              int nprod, hipStream_t st, int bn)
 {
     const int nmt = P.Mp / 128, nnt = (P.NPB + bn / 32 - 1) / (bn / 32);
     const long nlog = (long)P.ns * P.G * nnt * nmt;
     const long per = (nlog + 7) / 8;
-    if (bn == 128)
-        hipLaunchKernelGGL(qgemm_bf16x3_kernel<128>, dim3((unsigned)(per * 8)), dim3(256), 0, st, P, Ahi, Alo, Kp, nmt,
-                           nnt, nlog, per);
-    else
-        hipLaunchKernelGGL(qgemm_bf16x3_kernel<256>, dim3((unsigned)(per * 8)), dim3(512), 0, st, P, Ahi, Alo, Kp, nmt,
-                           nnt, nlog, per);
+    const dim3 grid((unsigned)(per * 8));
+#define PBS_QG(BN_, NP_) \
+    hipLaunchKernelGGL((qgemm_bf16s_kernel<BN_, NP_>), grid, dim3(2 * BN_), 0, st, P, Ahi, Alo, Kp, nmt, nnt, nlog, per)
+    if (bn == 128) {
+        if (nprod == 3) PBS_QG(128, 3); else PBS_QG(128, 2);
+    } else {
+        if (nprod == 3) PBS_QG(256, 3); else PBS_QG(256, 2);
+    }
+#undef PBS_QG
     return hipGetLastError();
 }
 
@@ -1388,7 +1394,7 @@ __global__ __launch_bounds__(256) void epass_batched_kernel(const BeamDev *__res
         epass_body<float, MODE_CLOSE, true>(P, blockIdx.x);
 }
 
-template <int BN>
+template <int BN, int NPROD>
 __global__ __launch_bounds__(2 * BN) void qgemm_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
 {
     const BeamDev &B = beams[blockIdx.y];
@@ -1414,7 +1420,7 @@ __global__ __launch_bounds__(2 * BN) void qgemm_batched_kernel(const BeamDev *__
     const long nlog = (long)P.ns * P.G * nnt * nmt;
     const long per = (nlog + 7) / 8;
     if ((long)blockIdx.x >= per * 8) return;
-    qgemm_bf16x3_body<BN>(P, Sh.Ahi, Sh.Alo, Sh.Kpb, nmt, nnt, nlog, per, blockIdx.x);
+    qgemm_bf16s_body<BN, NPROD>(P, Sh.Ahi, Sh.Alo, Sh.Kpb, nmt, nnt, nlog, per, blockIdx.x);
 }
 
 template <int NSEG, int WPB>
@@ -1498,12 +1504,14 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
             const int bn = tu.gemm_bn;
             const int nmt = Sh.Mp / 128, nnt = (Sh.NPB + bn / 32 - 1) / (bn / 32);
             const long per = ((long)2 * maxG * nnt * nmt + 7) / 8;
-            if (bn == 128)
-                hipLaunchKernelGGL(qgemm_batched_kernel<128>, dim3((unsigned)(per * 8), nbeam), dim3(256), 0, st,
-                                   beams, Sh, s);
-            else
-                hipLaunchKernelGGL(qgemm_batched_kernel<256>, dim3((unsigned)(per * 8), nbeam), dim3(512), 0, st,
-                                   beams, Sh, s);
+            const dim3 grid((unsigned)(per * 8), nbeam);
+#define PBS_QB(BN_, NP_) hipLaunchKernelGGL((qgemm_batched_kernel<BN_, NP_>), grid, dim3(2 * BN_), 0, st, beams, Sh, s)
+            if (bn == 128) {
+                if (Sh.nprod == 3) PBS_QB(128, 3); else PBS_QB(128, 2);
+            } else {
+                if (Sh.nprod == 3) PBS_QB(256, 3); else PBS_QB(256, 2);
+            }
+#undef PBS_QB
         }
     }
     hipLaunchKernelGGL(dose_batched_kernel, dim3(Sh.NPB, nbeam), dim3(1024), 0, st, beams, Sh, s);

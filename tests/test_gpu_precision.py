@@ -1,7 +1,8 @@
 """Precision of the FP32 path at full size: configuration 2 (150 MeV, 64x64 lateral, 32x32 angles,
-128 groups, 300 steps, primary + 3 scattered generations) in FP32 -- with the default split-BF16
-source product -- against the FP64 instantiation of the same kernels, which itself matches the
-FP64 oracle to <= 1e-12 on the configurations the oracle can run.  Tolerance: dose rel-L2 <= 1e-4.
+128 groups, 300 steps, primary + 3 scattered generations; water, bone slab, lung slab) in FP32 --
+with each split-BF16 form of the source product -- against the FP64 instantiation of the same
+kernels, which itself matches the FP64 oracle to <= 1e-12 on the configurations the oracle can run.
+Tolerance: dose rel-L2 <= 1e-4.
 """
 import numpy as np
 import pytest
@@ -28,25 +29,42 @@ def _run(c, prec, src=None):
     return d
 
 
-def test_config2_fp32_dose_within_1e4_of_fp64():
-    c = I.config2("water")
-    ref = _run(c, "fp64")
-    d = _run(c, "fp32")
+_REF = {}
+
+
+def _ref(case):
+    if case not in _REF:
+        _REF.clear()                       # one FP64 reference resident at a time
+        _REF[case] = _run(I.config2(case), "fp64")
+    return _REF[case]
+
+
+@pytest.mark.parametrize("src", ["bf16x3", "bf16x2"])
+@pytest.mark.parametrize("case", ["water", "bone", "lung"])
+def test_config2_fp32_dose_within_1e4_of_fp64(case, src):
+    from paper_2504_00340_amd.pbsplit import PBS_SRC_BF16X2, PBS_SRC_BF16X3
+
+    c = I.config2(case)
+    print("case config 2", case, "source", src, flush=True)
+    ref = _ref(case)
+    d = _run(c, "fp32", PBS_SRC_BF16X3 if src == "bf16x3" else PBS_SRC_BF16X2)
     rel = float(np.linalg.norm(d - ref) / np.linalg.norm(ref))
-    print("config 2 water: FP32 (split-BF16 source) vs FP64 dose rel-L2", rel, flush=True)
+    print(f"config 2 {case}: FP32 ({src} source) vs FP64 dose rel-L2 {rel:.3e}", flush=True)
     assert rel <= 1e-4
-    # the Bragg peak of the integrated depth dose lies before the CSDA range (15.6 cm)
+    # the Bragg peak of the integrated depth dose lies before the water CSDA range (15.6 cm); the
+    # bone slab pulls it in, the lung slab pushes it out
     idd = ref.sum(axis=(1, 2))
     zpk = (np.argmax(idd) + 0.5) * c["grid"]["dz"]
-    assert 13.0 < zpk < 15.7, zpk
+    lo, hi = {"water": (13.0, 15.7), "bone": (11.0, 14.5), "lung": (14.0, 17.5)}[case]
+    assert lo < zpk < hi, zpk
 
 
 def test_source_precision_modes_agree():
-    from paper_2504_00340_amd.pbsplit import PBS_SRC_BF16X3, PBS_SRC_FP32, PbsError, Solver
+    from paper_2504_00340_amd.pbsplit import PBS_SRC_BF16X2, PBS_SRC_BF16X3, PBS_SRC_FP32, PbsError, Solver
 
     c = I.small(nx=7, ny=9, nth=32, ng=6, nz=4, ngen=3, e0=32.0, e_hi=40.0, depth=1.0, seed=7)
     out = {}
-    for src in (PBS_SRC_FP32, PBS_SRC_BF16X3):
+    for src in (PBS_SRC_FP32, PBS_SRC_BF16X3, PBS_SRC_BF16X2):
         s = Solver(c["grid"], c["phys"], precision="fp32")
         s.set_source_precision(src)
         s.set_phantom(c["rho"])
@@ -55,11 +73,15 @@ def test_source_precision_modes_agree():
         out[src] = (s.dose(), s.state())
         s.close()
     d32, st32 = out[PBS_SRC_FP32]
-    db, stb = out[PBS_SRC_BF16X3]
-    assert np.linalg.norm(db - d32) / np.linalg.norm(d32) < 1e-5
-    # the scattered generations carry the source; compare them on their own
-    for k in (1, 2):
-        assert np.linalg.norm(stb[k] - st32[k]) / np.linalg.norm(st32[k]) < 1e-4
+    for src, tol in ((PBS_SRC_BF16X3, 1e-4), (PBS_SRC_BF16X2, 1e-2)):
+        db, stb = out[src]
+        assert np.linalg.norm(db - d32) / np.linalg.norm(d32) < 1e-5
+        # the scattered generations carry the source; compare them on their own (the two-product
+        # form rounds the scanned fluence to BF16 once: ~2^-9 per element, unbiased)
+        for k in (1, 2):
+            e = np.linalg.norm(stb[k] - st32[k]) / np.linalg.norm(st32[k])
+            print("source mode", src, "generation", k, "state rel-L2", e, flush=True)
+            assert e < tol
     # FP64 contexts do not take the split-BF16 product
     s = Solver(c["grid"], c["phys"], precision="fp64")
     with pytest.raises(PbsError):
