@@ -392,11 +392,23 @@ template <typename T>
 pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
 {
     const int K1 = c->kact;
+    // FP32 with the split-BF16 product: octet-per-thread E-pass, deposits summed per octet
+    bool e8 = false;
+    if constexpr (sizeof(T) == 4) e8 = c->Kpb > 0 && c->src_mode != PBS_SRC_FP32;
+    const int nslot = e8 ? epass8_slots(c->NOCT) : c->NA;
     for (int k = 0; k < K1; ++k) {
         EParams<T> P = eparams<T>(c, k, (mode & MODE_CLOSE) ? lay_c : -1, (mode & MODE_OPEN) ? lay_o : -1, h);
         {
             ProfScope ps(c, PBS_K_EPASS);
-            HIPCHK(c, launch_epass<T>(P, mode, c->stream));
+            if constexpr (sizeof(T) == 4) {
+                if (e8) {
+                    HIPCHK(c, launch_epass8(P, mode, c->stream));
+                } else {
+                    HIPCHK(c, launch_epass<T>(P, mode, c->stream));
+                }
+            } else {
+                HIPCHK(c, launch_epass<T>(P, mode, c->stream));
+            }
         }
         if (k + 1 < K1) {
             QParams<T> Q;
@@ -429,23 +441,25 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
     }
     ProfScope ps(c, PBS_K_DOSE);
     if (mode & MODE_CLOSE)
-        HIPCHK(c, launch_dose_reduce(c->edep(lay_c), c->dep(0, 0), K1, c->NA, c->NLINE, c->NP, c->stream));
+        HIPCHK(c, launch_dose_reduce(c->edep(lay_c), c->dep(0, 0), K1, c->NA, nslot, c->NLINE, c->NP, c->stream));
     if (mode & MODE_OPEN)
-        HIPCHK(c, launch_dose_reduce(c->edep(lay_o), c->dep(1, 0), K1, c->NA, c->NLINE, c->NP, c->stream));
+        HIPCHK(c, launch_dose_reduce(c->edep(lay_o), c->dep(1, 0), K1, c->NA, nslot, c->NLINE, c->NP, c->stream));
     if (c->feat_on) {
         // per-layer surrogate records: injected energy of both halves, moments after the opening half,
         // and the deposit of the primaries alone when further generations are marched
         const int NA = c->NA, NP = c->NP;
         const long NL = c->NLINE;
         if (mode & MODE_CLOSE) {
-            HIPCHK(c, launch_dose_reduce(c->frec(0, lay_c), c->fline(0), 1, NA, NL, NP, c->stream));
-            if (K1 > 1) HIPCHK(c, launch_dose_reduce(c->frec(3, lay_c), c->dep(0, 0), 1, NA, NL, NP, c->stream));
+            HIPCHK(c, launch_dose_reduce(c->frec(0, lay_c), c->fline(0), 1, NA, nslot, NL, NP, c->stream));
+            if (K1 > 1)
+                HIPCHK(c, launch_dose_reduce(c->frec(3, lay_c), c->dep(0, 0), 1, NA, nslot, NL, NP, c->stream));
         }
         if (mode & MODE_OPEN) {
-            HIPCHK(c, launch_dose_reduce(c->frec(0, lay_o), c->fline(1), 1, NA, NL, NP, c->stream));
-            HIPCHK(c, launch_dose_reduce(c->frec(1, lay_o), c->fline(2), 1, NA, NL, NP, c->stream));
-            HIPCHK(c, launch_dose_reduce(c->frec(2, lay_o), c->fline(3), 1, NA, NL, NP, c->stream));
-            if (K1 > 1) HIPCHK(c, launch_dose_reduce(c->frec(3, lay_o), c->dep(1, 0), 1, NA, NL, NP, c->stream));
+            HIPCHK(c, launch_dose_reduce(c->frec(0, lay_o), c->fline(1), 1, NA, nslot, NL, NP, c->stream));
+            HIPCHK(c, launch_dose_reduce(c->frec(1, lay_o), c->fline(2), 1, NA, nslot, NL, NP, c->stream));
+            HIPCHK(c, launch_dose_reduce(c->frec(2, lay_o), c->fline(3), 1, NA, nslot, NL, NP, c->stream));
+            if (K1 > 1)
+                HIPCHK(c, launch_dose_reduce(c->frec(3, lay_o), c->dep(1, 0), 1, NA, nslot, NL, NP, c->stream));
         }
     }
     return PBS_OK;

@@ -13,6 +13,9 @@
 
 #define PBS_PT 32            // lateral tile: 32 consecutive cells = 128 B of FP32
 #define PBS_MAX_NSEG 4       // transport sweep supports ny <= 64 * PBS_MAX_NSEG
+#ifndef PBS_EPASS_LPT
+#define PBS_EPASS_LPT 4      // angular lines per thread of the split-scan energy pass (4 or 8)
+#endif
 
 namespace pbs {
 
@@ -123,11 +126,18 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
 
 // launchers (explicitly instantiated for float and double); return hipGetLastError()
 template <typename T> hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st);
+// FP32 with split-BF16 scans (Wh set or no next generation): thread per (cell, group of
+// PBS_EPASS_LPT lines of an octet); deposits and records summed per group at line slot a = group
+// (reduce over epass8_slots(NOCT) slots)
+hipError_t launch_epass8(const EParams<float> &P, int mode, hipStream_t st);
+// deposit slots per cell written by launch_epass8
+__host__ __device__ inline int epass8_slots(int NOCT) { return NOCT * (8 / PBS_EPASS_LPT); }
 template <typename T> hipError_t launch_tpass(const TParams<T> &P, hipStream_t st);
 template <typename T> hipError_t launch_apass(const AParams<T> &P, int nth, long nstack, hipStream_t st);
 template <typename T> hipError_t launch_qgemm(const QParams<T> &P, hipStream_t st);
 template <typename T> hipError_t launch_fill(T *p, T v, long n, hipStream_t st);
-hipError_t launch_dose_reduce(double *edep_layer, const double *dep, int ngen, int NA, long NLINE, int NP,
+// edep_layer[pq] += sum over generations and the first nslot angular slots of dep
+hipError_t launch_dose_reduce(double *edep_layer, const double *dep, int ngen, int NA, int nslot, long NLINE, int NP,
                               hipStream_t st);
 hipError_t launch_dose_finalize(double *out, const double *edep, const double *rho, double vol, long n,
                                 hipStream_t st);

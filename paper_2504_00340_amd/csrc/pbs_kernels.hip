@@ -195,6 +195,188 @@ hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st)
     return hipGetLastError();
 }
 
+// Energy pass of FP32 contexts with the split-BF16 source product: one thread per (lateral cell,
+// group of PBS_EPASS_LPT consecutive angular lines of an octet a = 8 oct + e).  The thread sweeps the
+// groups of its lines together, so the scans of consecutive source nodes form one chunk (8 or 16
+// bytes) of the [oct][cell][8] split layout that the thread writes itself (no exchange between
+// threads, no barrier).  The FP64 deposits (and surrogate records) of those lines are summed into
+// one partial per (cell, line group), stored at line slot a = line group; the dose reduction then
+// sums NOCT * 8 / PBS_EPASS_LPT slots per cell instead of NA.  Lanes 0-31 hold the 32 cells of one
+// tile.
+template <int MODE>
+__device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
+{
+    constexpr int L = PBS_EPASS_LPT;
+    constexpr int NSUB = 8 / L;
+    constexpr bool CL = (MODE & MODE_CLOSE) != 0;
+    constexpr bool OP = (MODE & MODE_OPEN) != 0;
+    const int NA = (int)(P.NAPT / PBS_PT);
+    const long NPB = P.NLINE / P.NAPT;
+    const int pt = (int)(gid & 31);
+    const long r = gid >> 5;
+    const int grp = (int)(r % (P.NOCT * NSUB));   // line group: octet grp / NSUB, lines 8 oct + L sub + e
+    const int oct = grp / NSUB, sub = grp % NSUB;
+    const long pbk = r / (P.NOCT * NSUB);
+    if (pbk >= NPB) return;
+    const int nval = min(L, NA - 8 * oct - L * sub);   // lines of this group that exist (may be <= 0)
+    const long S = P.NLINE;
+    const long QS = (long)P.G * S;
+    const long line0 = ((long)pbk * NA + 8 * oct + L * sub) * PBS_PT + pt;   // line of e = 0; e adds PBS_PT
+    const long pq = pbk * PBS_PT + pt;
+    const double rc = CL ? (double)P.rho_c[pq] : 0.0;
+    const double ro = OP ? (double)P.rho_o[pq] : 0.0;
+    const double dac = 0.5 * (double)P.h * rc, dao = 0.5 * (double)P.h * ro;
+    const float ac = (float)dac, ao = (float)dao;
+    float fin[L], fcl[L], fop[L], U0[L], U1[L], U2[L];
+#pragma unroll
+    for (int e = 0; e < L; ++e) fin[e] = fcl[e] = fop[e] = U0[e] = U1[e] = U2[e] = 0.f;
+    double ph0 = 0, ph1 = 0, ph2 = 0, injc = 0, injo = 0;
+    float fic = 0, fio = 0, fme = 0, fmn = 0;
+    const bool hasQ = P.Q != nullptr, hasW = P.Wh != nullptr, hasL = P.Wl != nullptr, feat = P.inj_c != nullptr;
+    const long SB = (long)P.G * NPB * P.NOCT * (PBS_PT * 8);
+    for (int g = P.G - 1; g >= 0; --g) {
+        const float sm = P.Sm[g], sp = P.Sp[g], kp = P.kap[g];
+        const float d11 = -(sm + kp), d12 = sm, d21 = -3.f * sp, d22 = -(sp + 2.f * sm + kp);
+        const float c1 = sp, c2 = 3.f * sp;
+        const float mc11 = 1.f - ac * d11, mc12 = -ac * d12, mc21 = -ac * d21, mc22 = 1.f - ac * d22;
+        const float mo11 = 1.f - ao * d11, mo12 = -ao * d12, mo21 = -ao * d21, mo22 = 1.f - ao * d22;
+        const float ic = CL ? fast_rcp(mc11 * mc22 - mc12 * mc21) : 0.f;
+        const float io = OP ? fast_rcp(mo11 * mo22 - mo12 * mo21) : 0.f;
+        float *p1 = P.psi + (2L * g) * S + line0;
+        float *p2 = p1 + S;
+        float x1[L], x2[L], qc[L], qo[L];
+#pragma unroll
+        for (int e = 0; e < L; ++e) {
+            const bool v = e < nval;
+            x1[e] = v ? p1[e * PBS_PT] : 0.f;
+            x2[e] = v ? p2[e * PBS_PT] : 0.f;
+            qc[e] = qo[e] = 0.f;
+            if (hasQ && v) {
+                const long o = (long)g * S + line0 + e * PBS_PT;
+                if (CL) qc[e] = P.Q[o];
+                if (OP) qo[e] = P.Q[QS + o];
+            }
+        }
+        const float w = P.wc[g], dec = P.wdec[g], idE = P.invdE[g];
+        double s0a = 0, s0b = 0, s1a = 0, s1b = 0, s2a = 0, s2b = 0, sqc = 0, sqo = 0;
+        typedef unsigned short chunk_t __attribute__((ext_vector_type(L)));
+        chunk_t hc, lc, ho, lo;
+#pragma unroll
+        for (int e = 0; e < L; ++e) {
+            float y1 = x1[e], y2 = x2[e];
+            if (CL) {
+                const float f = fin[e] + fcl[e];
+                const float r1 = x1[e] + ac * (d11 * x1[e] + d12 * x2[e] + c1 * f + qc[e]);
+                const float r2 = x2[e] + ac * (d21 * x1[e] + d22 * x2[e] + c2 * f);
+                y1 = (r1 * mc22 - mc12 * r2) * ic;
+                y2 = (mc11 * r2 - mc21 * r1) * ic;
+            }
+            float z1 = y1, z2 = y2;
+            if (OP) {
+                const float f = (CL ? fcl[e] : fin[e]) + fop[e];
+                const float r1 = y1 + ao * (d11 * y1 + d12 * y2 + c1 * f + qo[e]);
+                const float r2 = y2 + ao * (d21 * y1 + d22 * y2 + c2 * f);
+                z1 = (r1 * mo22 - mo12 * r2) * io;
+                z2 = (mo11 * r2 - mo21 * r1) * io;
+            }
+            if (e < nval) {
+                p1[e * PBS_PT] = z1;
+                p2[e * PBS_PT] = z2;
+            }
+            if (CL) {
+                s0a += (double)x1[e];
+                s0b += (double)x2[e];
+                sqc += (double)qc[e];
+            }
+            s1a += (double)y1;
+            s1b += (double)y2;
+            if (OP) {
+                s2a += (double)z1;
+                s2b += (double)z2;
+                sqo += (double)qo[e];
+            }
+            if (hasW || feat) {
+                if (CL) U0[e] = w * x1[e] + dec * U0[e];
+                U1[e] = w * y1 + dec * U1[e];
+                if (OP) U2[e] = w * z1 + dec * U2[e];
+                const float vc = CL ? (U0[e] + U1[e]) * idE : 0.f;
+                const float vo = OP ? (U1[e] + U2[e]) * idE : 0.f;
+                const __bf16 bc = (__bf16)vc, bo = (__bf16)vo;
+                hc[e] = __builtin_bit_cast(unsigned short, bc);
+                ho[e] = __builtin_bit_cast(unsigned short, bo);
+                lc[e] = __builtin_bit_cast(unsigned short, (__bf16)(vc - (float)bc));
+                lo[e] = __builtin_bit_cast(unsigned short, (__bf16)(vo - (float)bo));
+                if (feat) {
+                    const float wi = (float)P.dInj[g];
+                    if (CL) fic += wi * vc;
+                    if (OP) {
+                        fio += wi * vo;
+                        fme += (float)P.wmom[g] * z1 + (float)P.wmom[2 * P.G + g] * z2;
+                        fmn += (float)P.wmom[P.G + g] * z1;
+                    }
+                }
+            }
+            fin[e] = x1[e] - x2[e];
+            fcl[e] = y1 - y2;
+            fop[e] = z1 - z2;
+        }
+        // deposit functional (FP64), summed over the lines: A, B depend on the energy group only
+        const double A = P.dA[g], B = P.dB[g];
+        if (CL) ph0 += A * s0a + B * s0b;
+        ph1 += A * s1a + B * s1b;
+        if (OP) ph2 += A * s2a + B * s2b;
+        if (g == 0) {
+            if (CL) ph0 += P.dBot * (s0a - s0b);
+            ph1 += P.dBot * (s1a - s1b);
+            if (OP) ph2 += P.dBot * (s2a - s2b);
+        }
+        if (hasQ) {
+            const double wi = P.dInj[g];
+            if (CL) injc += wi * sqc;
+            if (OP) injo += wi * sqo;
+        }
+        if (hasW) {
+            const long ob = (((long)g * NPB + pbk) * P.NOCT + oct) * (PBS_PT * 8) + pt * 8 + L * sub;
+            if (CL) *reinterpret_cast<chunk_t *>(P.Wh + ob) = hc;
+            if (OP) *reinterpret_cast<chunk_t *>(P.Wh + SB + ob) = ho;
+            if (hasL) {
+                if (CL) *reinterpret_cast<chunk_t *>(P.Wl + ob) = lc;
+                if (OP) *reinterpret_cast<chunk_t *>(P.Wl + SB + ob) = lo;
+            }
+        }
+    }
+    const long slot = ((long)pbk * NA + grp) * PBS_PT + pt;
+    if (CL) P.dep_c[slot] = dac * (ph0 + ph1 - injc) * P.scale;
+    if (OP) P.dep_o[slot] = dao * (ph1 + ph2 - injo) * P.scale;
+    if (feat) {
+        if (CL) P.inj_c[slot] = dac * (double)fic * P.scale;
+        if (OP) {
+            P.inj_o[slot] = dao * (double)fio * P.scale;
+            P.mom_e[slot] = (double)fme * P.scale;
+            P.mom_n[slot] = (double)fmn * P.scale;
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void epass8_kernel(EParams<float> P)
+{
+    epass8_body<MODE>(P, (long)blockIdx.x * 256 + threadIdx.x);
+}
+
+hipError_t launch_epass8(const EParams<float> &P, int mode, hipStream_t st)
+{
+    const long nthreads = (P.NLINE / P.NAPT) * P.NOCT * (8 / PBS_EPASS_LPT) * PBS_PT;
+    const unsigned nb = (unsigned)((nthreads + 255) / 256);
+    if (mode == MODE_PAIR)
+        hipLaunchKernelGGL(epass8_kernel<MODE_PAIR>, dim3(nb), dim3(256), 0, st, P);
+    else if (mode == MODE_OPEN)
+        hipLaunchKernelGGL(epass8_kernel<MODE_OPEN>, dim3(nb), dim3(256), 0, st, P);
+    else
+        hipLaunchKernelGGL(epass8_kernel<MODE_CLOSE>, dim3(nb), dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------- transport pass
 // Superbee-limited face slope without division: delta = Dface * eta(Dup / Dface).
 template <typename T>
@@ -1269,15 +1451,15 @@ hipError_t launch_fill(T *p, T v, long n, hipStream_t st)
 
 // edep[pq] += sum over generations and angles of dep[k][line(pq, a)], fixed order: one block per
 // lateral tile, 32 lanes per cell x 32 angle slices, then a fixed-order tree over the slices.
-__device__ __forceinline__ void dose_reduce_body(double *edep, const double *dep, int ngen, int NA, long NLINE,
-                                                 int NP, int pb)
+__device__ __forceinline__ void dose_reduce_body(double *edep, const double *dep, int ngen, int NA, int nslot,
+                                                 long NLINE, int NP, int pb)
 {
     __shared__ double part[32][33];
     const int pt = threadIdx.x & 31, sl = threadIdx.x >> 5;
     const long base = (long)pb * NA * PBS_PT + pt;
     double s = 0.0;
     for (int k = 0; k < ngen; ++k)
-        for (int a = sl; a < NA; a += 32) s += dep[(long)k * NLINE + base + (long)a * PBS_PT];
+        for (int a = sl; a < nslot; a += 32) s += dep[(long)k * NLINE + base + (long)a * PBS_PT];
     part[sl][pt] = s;
     __syncthreads();
     for (int w = 16; w > 0; w >>= 1) {
@@ -1289,16 +1471,17 @@ __device__ __forceinline__ void dose_reduce_body(double *edep, const double *dep
 }
 
 __global__ __launch_bounds__(1024) void dose_reduce_kernel(double *edep, const double *dep, int ngen, int NA,
-                                                           long NLINE, int NP)
+                                                           int nslot, long NLINE, int NP)
 {
-    dose_reduce_body(edep, dep, ngen, NA, NLINE, NP, blockIdx.x);
+    dose_reduce_body(edep, dep, ngen, NA, nslot, NLINE, NP, blockIdx.x);
 }
 
-hipError_t launch_dose_reduce(double *edep_layer, const double *dep, int ngen, int NA, long NLINE, int NP,
+hipError_t launch_dose_reduce(double *edep_layer, const double *dep, int ngen, int NA, int nslot, long NLINE, int NP,
                               hipStream_t st)
 {
     const int npb = (NP + PBS_PT - 1) / PBS_PT;
-    hipLaunchKernelGGL(dose_reduce_kernel, dim3(npb), dim3(1024), 0, st, edep_layer, dep, ngen, NA, NLINE, NP);
+    hipLaunchKernelGGL(dose_reduce_kernel, dim3(npb), dim3(1024), 0, st, edep_layer, dep, ngen, NA, nslot, NLINE,
+                       NP);
     return hipGetLastError();
 }
 
@@ -1357,7 +1540,7 @@ __global__ __launch_bounds__(256) void epass_batched_kernel(const BeamDev *__res
 {
     const BeamDev &B = beams[blockIdx.y];
     const int mode = beam_mode(s, B.nz);
-    if (mode == 0 || blockIdx.x >= (unsigned)(Sh.NPB * Sh.NOCT)) return;
+    if (mode == 0) return;
     EParams<float> P;
     const int G = B.G;
     P.psi = B.psi + (long)k * G * 2 * Sh.NLINE;
@@ -1386,12 +1569,13 @@ __global__ __launch_bounds__(256) void epass_batched_kernel(const BeamDev *__res
     P.G = G;
     P.NLINE = Sh.NLINE;
     P.NAPT = (long)Sh.NA * PBS_PT;
+    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
     if (mode == MODE_PAIR)
-        epass_body<float, MODE_PAIR, true>(P, blockIdx.x);
+        epass8_body<MODE_PAIR>(P, gid);
     else if (mode == MODE_OPEN)
-        epass_body<float, MODE_OPEN, true>(P, blockIdx.x);
+        epass8_body<MODE_OPEN>(P, gid);
     else
-        epass_body<float, MODE_CLOSE, true>(P, blockIdx.x);
+        epass8_body<MODE_CLOSE>(P, gid);
 }
 
 template <int BN, int NPROD>
@@ -1488,18 +1672,20 @@ __global__ __launch_bounds__(1024) void dose_batched_kernel(const BeamDev *__res
     const int mode = beam_mode(s, B.nz);
     const int NP = Sh.nx * Sh.ny;
     if (mode & MODE_CLOSE)
-        dose_reduce_body(B.edep + (long)(s - 1) * NP, B.dep, Sh.ngen, Sh.NA, Sh.NLINE, NP, blockIdx.x);
+        dose_reduce_body(B.edep + (long)(s - 1) * NP, B.dep, Sh.ngen, Sh.NA, epass8_slots(Sh.NOCT), Sh.NLINE, NP,
+                         blockIdx.x);
     __syncthreads();
     if (mode & MODE_OPEN)
-        dose_reduce_body(B.edep + (long)s * NP, B.dep + (long)Sh.ngen * Sh.NLINE, Sh.ngen, Sh.NA, Sh.NLINE, NP,
-                         blockIdx.x);
+        dose_reduce_body(B.edep + (long)s * NP, B.dep + (long)Sh.ngen * Sh.NLINE, Sh.ngen, Sh.NA,
+                         epass8_slots(Sh.NOCT), Sh.NLINE, NP, blockIdx.x);
 }
 
 hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &Sh, int s, int maxG,
                              const BatchTuning &tu, hipStream_t st)
 {
     for (int k = 0; k < Sh.ngen; ++k) {
-        hipLaunchKernelGGL(epass_batched_kernel, dim3(Sh.NPB * Sh.NOCT, nbeam), dim3(256), 0, st, beams, Sh, k, s);
+        const unsigned nbe = (unsigned)(((long)Sh.NPB * Sh.NOCT * (8 / PBS_EPASS_LPT) * PBS_PT + 255) / 256);
+        hipLaunchKernelGGL(epass_batched_kernel, dim3(nbe, nbeam), dim3(256), 0, st, beams, Sh, k, s);
         if (k + 1 < Sh.ngen) {
             const int bn = tu.gemm_bn;
             const int nmt = Sh.Mp / 128, nnt = (Sh.NPB + bn / 32 - 1) / (bn / 32);
