@@ -26,6 +26,34 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+namespace pbs {
+// nth = 32: the 31-point sine transform split by mode parity, [(mat*4 + s)*64 + lane] =
+// A_mat[lane % 16][4 s + lane / 16] for mat = Sodd, Seven, Sodd^T, Seven^T.
+// nth = 16: the dense 15-point transform zero-padded to 16 x 16, [s*64 + lane] = S[lane % 16][4 s + lane / 16].
+void apass_mfma_table(int nth, float *t)
+{
+    for (int i = 0; i < 1024; ++i) t[i] = 0.f;
+    if (nth == 32) {
+        auto sodd = [](int r, int i) { return std::sin(M_PI * (2 * r + 1) * (i + 1) / 32.0); };
+        auto seven = [](int r, int i) { return (r < 15 && i < 15) ? std::sin(M_PI * 2 * (r + 1) * (i + 1) / 32.0) : 0.0; };
+        for (int s = 0; s < 4; ++s)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int row = lane % 16, k = 4 * s + lane / 16;
+                t[(0 * 4 + s) * 64 + lane] = (float)sodd(row, k);
+                t[(1 * 4 + s) * 64 + lane] = (float)seven(row, k);
+                t[(2 * 4 + s) * 64 + lane] = (float)sodd(k, row);
+                t[(3 * 4 + s) * 64 + lane] = (float)seven(k, row);
+            }
+    } else if (nth == 16) {
+        for (int s = 0; s < 4; ++s)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int row = lane % 16, k = 4 * s + lane / 16;
+                t[s * 64 + lane] = (row < 15 && k < 15) ? (float)std::sin(M_PI * (row + 1) * (k + 1) / 16.0) : 0.f;
+            }
+    }
+}
+}  // namespace pbs
+
 
 namespace {
 
@@ -260,19 +288,11 @@ pbs_status upload_tables(pbs_ctx *c)
     for (int k = 0; k < c->Kp; ++k)
         for (int a = 0; a < c->Mp; ++a)
             t[c->t_P2p + (size_t)k * c->Mp + a] = (k < c->NA && a < c->NA) ? (T)c->P2T[(size_t)a * c->NA + k] : T(0);
-    // MFMA operand constants of the 31-point sine transform split by mode parity (nth = 32):
-    // [(mat*4 + s)*64 + lane] = A_mat[lane % 16][4 s + lane / 16]
-    if (c->g.nth == 32) {
-        auto sodd = [](int r, int i) { return std::sin(M_PI * (2 * r + 1) * (i + 1) / 32.0); };
-        auto seven = [](int r, int i) { return (r < 15 && i < 15) ? std::sin(M_PI * 2 * (r + 1) * (i + 1) / 32.0) : 0.0; };
-        for (int s = 0; s < 4; ++s)
-            for (int lane = 0; lane < 64; ++lane) {
-                const int row = lane % 16, k = 4 * s + lane / 16;
-                t[c->t_K32 + (0 * 4 + s) * 64 + lane] = (T)sodd(row, k);
-                t[c->t_K32 + (1 * 4 + s) * 64 + lane] = (T)seven(row, k);
-                t[c->t_K32 + (2 * 4 + s) * 64 + lane] = (T)sodd(k, row);
-                t[c->t_K32 + (3 * 4 + s) * 64 + lane] = (T)seven(k, row);
-            }
+    // MFMA operand constants of the angular pass (nth = 16, 32)
+    if (c->g.nth == 16 || c->g.nth == 32) {
+        std::vector<float> kt(1024);
+        apass_mfma_table(c->g.nth, kt.data());
+        for (int i = 0; i < 1024; ++i) t[c->t_K32 + i] = (T)kt[i];
     }
     std::vector<double> d(c->d_count, 0.0);
     std::memcpy(&d[c->d_A], c->dA.data(), c->G() * sizeof(double));
@@ -503,6 +523,10 @@ pbs_status angular(pbs_ctx *c, int layer, double h)
     if constexpr (sizeof(T) == 4) {
         if (c->g.nth == 32) {
             HIPCHK(c, launch_apass_mfma32(P, tb + c->t_K32, (long)c->kact * c->G() * 2, c->stream));
+            return PBS_OK;
+        }
+        if (c->g.nth == 16) {
+            HIPCHK(c, launch_apass_mfma16(P, tb + c->t_K32, (long)c->kact * c->G() * 2, c->stream));
             return PBS_OK;
         }
     }

@@ -44,7 +44,7 @@ struct pbs_batch {
     std::vector<std::vector<int>> waves;
     std::vector<size_t> dose_off;   // doubles, per beam
     size_t o_shared = 0, o_beams = 0, o_dose = 0, o_wave = 0, total = 0;
-    size_t sh_theta = 0, sh_lam = 0, sh_S = 0, sh_A = 0;   // byte offsets inside the shared block
+    size_t sh_theta = 0, sh_lam = 0, sh_S = 0, sh_A = 0, sh_K = 0;   // byte offsets inside the shared block
     char *ws = nullptr;
     hipStream_t stream = nullptr;
     std::vector<std::vector<double>> rho;
@@ -214,6 +214,7 @@ BatchShape shape(const pbs_batch *b)
     Sh.theta = reinterpret_cast<const float *>(S + b->sh_theta);
     Sh.lam = reinterpret_cast<const float *>(S + b->sh_lam);
     Sh.S = reinterpret_cast<const float *>(S + b->sh_S);
+    Sh.K = reinterpret_cast<const float *>(S + b->sh_K);
     Sh.Ahi = reinterpret_cast<const unsigned short *>(S + b->sh_A);
     Sh.Alo = Sh.Ahi + (size_t)b->Mp * b->Kpb;
     Sh.Kpb = b->Kpb;
@@ -362,6 +363,8 @@ pbs_status pbs_batch_create(const pbs_grid *grids, const pbs_beam *beams, int nb
     sh = a256(sh + (size_t)b->m * b->m * 4);
     b->sh_A = sh;
     sh = a256(sh + (size_t)2 * b->Mp * b->Kpb * 2);
+    b->sh_K = sh;
+    sh = a256(sh + (size_t)1024 * 4);
     b->o_shared = o;
     o = a256(o + sh);
     b->o_beams = o;
@@ -432,6 +435,9 @@ pbs_status pbs_batch_bind(pbs_batch *b, void *ws, size_t bytes, void *stream)
     BHIP(b, hipMemcpyAsync(Sp + b->sh_lam, lam.data(), lam.size() * 4, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(Sp + b->sh_S, S.data(), S.size() * 4, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(Sp + b->sh_A, A.data(), A.size() * 2, hipMemcpyHostToDevice, b->stream));
+    std::vector<float> Kt(1024);
+    apass_mfma_table(b->nth, Kt.data());
+    BHIP(b, hipMemcpyAsync(Sp + b->sh_K, Kt.data(), Kt.size() * 4, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipStreamSynchronize(b->stream));
     b->state = 1;
     return PBS_OK;

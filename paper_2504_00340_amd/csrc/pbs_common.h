@@ -104,6 +104,7 @@ struct BeamDev {
 
 struct BatchShape {
     const float *theta, *lam, *S;          // angular tables
+    const float *K;                        // MFMA operand table of the angular pass (nth 16 or 32)
     const unsigned short *Ahi, *Alo;       // split-BF16 P2, [Mp][Kpb]
     int Kpb, Mp;
     int nprod;                             // 3: scanned fluence as hi + lo; 2: hi only (no lo array)
@@ -150,6 +151,9 @@ hipError_t launch_initial(T *psi0, const double *E1, const double *E2, const dou
 hipError_t launch_qgemm_bf16s(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
                               int nprod, hipStream_t st, int bn = 256);
 hipError_t launch_apass_mfma32(const AParams<float> &P, const float *Ktab, long nstack, hipStream_t st);
+hipError_t launch_apass_mfma16(const AParams<float> &P, const float *Ktab, long nstack, hipStream_t st);
+// operand table of the MFMA angular pass for nth (16 or 32; 1024 floats, unused entries zero)
+void apass_mfma_table(int nth, float *out1024);
 
 bool apass_supported(int nth);
 

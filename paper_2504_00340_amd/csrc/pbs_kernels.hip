@@ -838,21 +838,20 @@ __device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__global__ __launch_bounds__(256) void apass_mfma32_kernel(AParams<float> P, const float *__restrict__ Ktab, int npb)
+// 16 waves per block: the dependent MFMA chains of a line are short, so latency is hidden by the
+// number of lines in flight (2 blocks of 61.5 KB LDS per CU = 32 waves)
+constexpr int APASS32_NT = 1024;
+__device__ __forceinline__ void apass_mfma32_body(const AParams<float> &P, const float *__restrict__ Ktab, long stack,
+                                                  int pb, int half)
 {
     constexpr int m = 31, NA = 961, PC = 16;
     __shared__ float L[NA * PC];   // L[a*16 + c], a = i*31 + j
-    // the two 16-column halves of one lateral tile are 8 workgroups apart -> same XCD, same L2 lines
-    const int bid = blockIdx.x;
-    const int pb = (bid >> 4) * 8 + (bid & 7), half = (bid >> 3) & 1;
-    if (pb >= npb) return;
     const int c0 = half * PC;
-    const long stack = blockIdx.y;
     const int g = (int)((stack / 2) % P.G);
     float *blk = P.psi + stack * P.NLINE + (long)pb * NA * PBS_PT + c0;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int r4 = lane >> 4, cc = lane & 15;
-    for (int idx = tid; idx < NA * 4; idx += 256) {
+    for (int idx = tid; idx < NA * 4; idx += APASS32_NT) {
         const int a = idx >> 2, q = idx & 3;
         *reinterpret_cast<float4 *>(&L[a * PC + q * 4]) = *reinterpret_cast<const float4 *>(blk + (long)a * PBS_PT + q * 4);
     }
@@ -875,7 +874,7 @@ __global__ __launch_bounds__(256) void apass_mfma32_kernel(AParams<float> P, con
     __syncthreads();
 
     // forward over the first angular index; line = column j
-    for (int j = wid; j < m; j += 4) {
+    for (int j = wid; j < m; j += APASS32_NT / 64) {
         floatx4 yo = {0.f, 0.f, 0.f, 0.f}, ye = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -894,7 +893,7 @@ __global__ __launch_bounds__(256) void apass_mfma32_kernel(AParams<float> P, con
     }
     __syncthreads();
     // over the second index: forward, CN factor, inverse; line = mode k of the first index
-    for (int k = wid; k < m; k += 4) {
+    for (int k = wid; k < m; k += APASS32_NT / 64) {
         floatx4 zo = {0.f, 0.f, 0.f, 0.f}, ze = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -947,7 +946,7 @@ __global__ __launch_bounds__(256) void apass_mfma32_kernel(AParams<float> P, con
     __syncthreads();
     // inverse over the first index, with the (2/N)^2 normalisation
     constexpr float sc = (2.f / 32.f) * (2.f / 32.f);
-    for (int j = wid; j < m; j += 4) {
+    for (int j = wid; j < m; j += APASS32_NT / 64) {
         floatx4 u = {0.f, 0.f, 0.f, 0.f}, v = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -971,16 +970,149 @@ __global__ __launch_bounds__(256) void apass_mfma32_kernel(AParams<float> P, con
         }
     }
     __syncthreads();
-    for (int idx = tid; idx < NA * 4; idx += 256) {
+    for (int idx = tid; idx < NA * 4; idx += APASS32_NT) {
         const int a = idx >> 2, q = idx & 3;
         *reinterpret_cast<float4 *>(blk + (long)a * PBS_PT + q * 4) = *reinterpret_cast<const float4 *>(&L[a * PC + q * 4]);
     }
 }
 
+// MFMA version for nth = 16 (15 interior nodes), FP32: each 15-point sine transform is one dense
+// 16 x 16 product (the matrix zero-padded), a chain of four v_mfma_f32_16x16x4_f32 whose 16 columns
+// are 16 lateral cells of one angular line; the 15 x 15 x 16 block (14.4 KB) stays in LDS.  The sine
+// matrix is symmetric, so the inverse uses the same operand table with the factor 2/N.
+//   Ktab[s*64 + lane] = S[lane % 16][4 s + lane / 16], S[r][k] = sin(pi (r+1)(k+1) / 16), zero at 15.
+__device__ __forceinline__ void apass_mfma16_body(const AParams<float> &P, const float *__restrict__ Ktab, long stack,
+                                                  int pb, int half)
+{
+    constexpr int m = 15, NA = 225, PC = 16, NT = 256;
+    __shared__ float L[NA * PC];   // L[a*16 + c], a = i*15 + j
+    const int c0 = half * PC;
+    const int g = (int)((stack / 2) % P.G);
+    float *blk = P.psi + stack * P.NLINE + (long)pb * NA * PBS_PT + c0;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int r4 = lane >> 4, cc = lane & 15;
+    for (int idx = tid; idx < NA * 4; idx += NT) {
+        const int a = idx >> 2, q = idx & 3;
+        *reinterpret_cast<float4 *>(&L[a * PC + q * 4]) = *reinterpret_cast<const float4 *>(blk + (long)a * PBS_PT + q * 4);
+    }
+    float A[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) A[s] = Ktab[s * 64 + lane];
+    float lamR[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 4 * r4 + q;
+        lamR[q] = r < m ? P.lam[r] : 0.f;
+    }
+    const float al = 0.25f * P.h * P.sig[g] * P.rho[(long)pb * PBS_PT + c0 + cc];
+    constexpr float sc = 2.f / 16.f;
+    __syncthreads();
+    // forward over the first angular index; line = column j
+    for (int j = wid; j < m; j += NT / 64) {
+        floatx4 y = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int ip = 4 * s + r4;
+            y = mfma16(A[s], ip < m ? L[(ip * m + j) * PC + cc] : 0.f, y);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 4 * r4 + q;
+            if (r < m) L[(r * m + j) * PC + cc] = y[q];
+        }
+    }
+    __syncthreads();
+    // over the second index: forward, CN factor, inverse; line = mode k of the first index
+    for (int k = wid; k < m; k += NT / 64) {
+        floatx4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int jp = 4 * s + r4;
+            z = mfma16(A[s], jp < m ? L[(k * m + jp) * PC + cc] : 0.f, z);
+        }
+        const float lk = P.lam[k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float t = al * (lk + lamR[q]);
+            z[q] = z[q] * (1.f + t) * __builtin_amdgcn_rcpf(1.f - t);
+        }
+        // modes back through LDS into the operand layout (same wave, same line: in-order LDS)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 4 * r4 + q;
+            if (r < m) L[(k * m + r) * PC + cc] = z[q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        floatx4 u = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int r = 4 * s + r4;
+            u = mfma16(A[s], r < m ? L[(k * m + r) * PC + cc] : 0.f, u);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int jp = 4 * r4 + q;
+            if (jp < m) L[(k * m + jp) * PC + cc] = u[q] * sc;
+        }
+    }
+    __syncthreads();
+    // inverse over the first index
+    for (int j = wid; j < m; j += NT / 64) {
+        floatx4 u = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int r = 4 * s + r4;
+            u = mfma16(A[s], r < m ? L[(r * m + j) * PC + cc] : 0.f, u);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ip = 4 * r4 + q;
+            if (ip < m) L[(ip * m + j) * PC + cc] = u[q] * sc;
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NA * 4; idx += NT) {
+        const int a = idx >> 2, q = idx & 3;
+        *reinterpret_cast<float4 *>(blk + (long)a * PBS_PT + q * 4) = *reinterpret_cast<const float4 *>(&L[a * PC + q * 4]);
+    }
+}
+
+__global__ __launch_bounds__(256) void apass_mfma16_kernel(AParams<float> P, const float *__restrict__ Ktab, int npb)
+{
+    // the two 16-column halves of one lateral tile are 8 workgroups apart -> same XCD, same L2 lines
+    const int bid = blockIdx.x;
+    const int pb = (bid >> 4) * 8 + (bid & 7), half = (bid >> 3) & 1;
+    if (pb >= npb) return;
+    apass_mfma16_body(P, Ktab, blockIdx.y, pb, half);
+}
+
+hipError_t launch_apass_mfma16(const AParams<float> &P, const float *Ktab, long nstack, hipStream_t st)
+{
+    const int nb = (P.NPB + 7) / 8 * 16;
+    hipLaunchKernelGGL(apass_mfma16_kernel, dim3(nb, (unsigned)nstack), dim3(256), 0, st, P, Ktab, P.NPB);
+    return hipGetLastError();
+}
+
+// two blocks per CU need <= 64 VGPRs (8 waves per SIMD)
+__global__ __launch_bounds__(APASS32_NT) __attribute__((amdgpu_waves_per_eu(8))) void apass_mfma32_kernel(
+    AParams<float> P, const float *__restrict__ Ktab, int npb)
+{
+    // the two 16-column halves of one lateral tile are 8 workgroups apart -> same XCD, same L2 lines
+    const int bid = blockIdx.x;
+    const int pb = (bid >> 4) * 8 + (bid & 7), half = (bid >> 3) & 1;
+    if (pb >= npb) return;
+    apass_mfma32_body(P, Ktab, blockIdx.y, pb, half);
+}
+
 hipError_t launch_apass_mfma32(const AParams<float> &P, const float *Ktab, long nstack, hipStream_t st)
 {
     const int nb = (P.NPB + 7) / 8 * 16;
-    hipLaunchKernelGGL(apass_mfma32_kernel, dim3(nb, (unsigned)nstack), dim3(256), 0, st, P, Ktab, P.NPB);
+    hipLaunchKernelGGL(apass_mfma32_kernel, dim3(nb, (unsigned)nstack), dim3(APASS32_NT), 0, st, P, Ktab, P.NPB);
     return hipGetLastError();
 }
 
@@ -1666,6 +1798,33 @@ __global__ __launch_bounds__(256) void apass_batched_kernel(const BeamDev *__res
     apass_body<float, N, PC>(P, blockIdx.x, blockIdx.y);
 }
 
+// batched MFMA angular passes (nth = 16 and 32): the single-beam bodies, beam = blockIdx.z
+template <int NTH>
+__global__ __launch_bounds__(NTH == 32 ? APASS32_NT : 256) __attribute__((amdgpu_waves_per_eu(8)))
+void apass_mfma_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
+{
+    const BeamDev &B = beams[blockIdx.z];
+    if (s >= B.nz || blockIdx.y >= (unsigned)(Sh.ngen * B.G * 2)) return;
+    const int bid = blockIdx.x;
+    const int pb = (bid >> 4) * 8 + (bid & 7), half = (bid >> 3) & 1;
+    if (pb >= Sh.NPB) return;
+    AParams<float> P;
+    P.psi = B.psi;
+    P.rho = B.rho + (long)s * Sh.NPB * PBS_PT;
+    P.sig = B.tabf + 6 * B.G;
+    P.S = Sh.S;
+    P.lam = Sh.lam;
+    P.h = B.dz;
+    P.G = B.G;
+    P.NA = Sh.NA;
+    P.NPB = Sh.NPB;
+    P.NLINE = Sh.NLINE;
+    if constexpr (NTH == 32)
+        apass_mfma32_body(P, Sh.K, blockIdx.y, pb, half);
+    else
+        apass_mfma16_body(P, Sh.K, blockIdx.y, pb, half);
+}
+
 __global__ __launch_bounds__(1024) void dose_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
 {
     const BeamDev &B = beams[blockIdx.y];
@@ -1730,7 +1889,13 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
 #undef PBS_TA
     };
     if (s < tu.max_nz) tpass();
-    if (s < tu.max_nz) {
+    if (s < tu.max_nz && (Sh.nth == 16 || Sh.nth == 32)) {
+        dim3 grid((unsigned)((Sh.NPB + 7) / 8 * 16), (unsigned)(Sh.ngen * maxG * 2), nbeam);
+        if (Sh.nth == 32)
+            hipLaunchKernelGGL(apass_mfma_batched_kernel<32>, grid, dim3(APASS32_NT), 0, st, beams, Sh, s);
+        else
+            hipLaunchKernelGGL(apass_mfma_batched_kernel<16>, grid, dim3(256), 0, st, beams, Sh, s);
+    } else if (s < tu.max_nz) {
         const int pc = tu.apass_pc;
         dim3 grid((unsigned)(Sh.NPB * (PBS_PT / pc)), (unsigned)(Sh.ngen * maxG * 2), nbeam);
 #define PBS_AB(N)                                                                                           \
