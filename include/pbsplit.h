@@ -190,8 +190,9 @@ pbs_status pbs_batch_set_phantom(pbs_batch *batch, int beam, const double *rho, 
 pbs_status pbs_batch_run(pbs_batch *batch);
 /* Dose of one beam, [nz][nx][ny] FP64 host array (MeV/g per incident proton). */
 pbs_status pbs_batch_get_dose(pbs_batch *batch, int beam, double *out, size_t n);
-/* Launch variants chosen by the autotuner: {source-product block columns, transport planes per
- * block, angular-pass cells per block}. */
+/* Launch variants chosen by the autotuner: {source-product kernel (0: scans read from global memory,
+ * 1: scans staged in LDS, 256-column blocks, 2: the same with 128 columns), transport planes per
+ * block, angular-pass cells per block (angular grids other than 16 and 32 nodes)}. */
 pbs_status pbs_batch_tuning(const pbs_batch *batch, int *out3);
 const char *pbs_batch_last_error(const pbs_batch *batch);
 void pbs_batch_destroy(pbs_batch *batch);

@@ -792,7 +792,7 @@ pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precisi
         c->Kp = (c->NA + 15) / 16 * 16;
         c->Mp = (c->NA + 127) / 128 * 128;
         if (precision == PBS_FP32) {
-            c->Kpb = (c->NA + 31) / 32 * 32;
+            c->Kpb = (c->NA + PBS_KPB_ALIGN - 1) / PBS_KPB_ALIGN * PBS_KPB_ALIGN;
             c->src_mode = PBS_DEFAULT_SRC;
         }
     }

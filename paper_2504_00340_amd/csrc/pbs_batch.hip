@@ -264,7 +264,7 @@ pbs_status autotune(pbs_batch *b, int nw, int maxG)
 {
     BatchTuning t = b->tune;
     t.max_nz = 2;
-    const int bn[] = {128, 256}, wpb[] = {1, 2, 4}, pc[] = {8, 16, 32};
+    const int gk[] = {QGEMM_GLOBAL_B, QGEMM_LDS_256, QGEMM_LDS_128}, wpb[] = {1, 2, 4}, pc[] = {8, 16, 32};
     auto pick = [&](int *field, const int *vals, int nv) {
         float bestms = 1e30f;
         int bestv = *field;
@@ -279,11 +279,11 @@ pbs_status autotune(pbs_batch *b, int nw, int maxG)
         }
         *field = bestv;
     };
-    pick(&t.gemm_bn, bn, 2);
+    pick(&t.gemm_kind, gk, 3);
     pick(&t.tpass_wpb, wpb, 3);
     pick(&t.apass_pc, pc, 3);
     BHIP(b, hipGetLastError());
-    b->tune.gemm_bn = t.gemm_bn;
+    b->tune.gemm_kind = t.gemm_kind;
     b->tune.tpass_wpb = t.tpass_wpb;
     b->tune.apass_pc = t.apass_pc;
     b->tuned = true;
@@ -535,7 +535,7 @@ pbs_status pbs_batch_get_dose(pbs_batch *b, int beam, double *out, size_t n)
 pbs_status pbs_batch_tuning(const pbs_batch *b, int *out3)
 {
     if (!b || !out3) return PBS_EINVAL;
-    out3[0] = b->tune.gemm_bn;
+    out3[0] = b->tune.gemm_kind;
     out3[1] = b->tune.tpass_wpb;
     out3[2] = b->tune.apass_pc;
     return PBS_OK;

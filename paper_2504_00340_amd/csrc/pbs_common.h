@@ -13,6 +13,7 @@
 
 #define PBS_PT 32            // lateral tile: 32 consecutive cells = 128 B of FP32
 #define PBS_MAX_NSEG 4       // transport sweep supports ny <= 64 * PBS_MAX_NSEG
+#define PBS_KPB_ALIGN 64     // source-node padding of the split-BF16 transfer matrix (the K stage)
 #ifndef PBS_EPASS_LPT
 #define PBS_EPASS_LPT 4      // angular lines per thread of the split-scan energy pass (4 or 8)
 #endif
@@ -116,7 +117,7 @@ struct BatchShape {
 
 // bitwise-neutral launch variants picked by the batch autotuner
 struct BatchTuning {
-    int gemm_bn = 256;        // split-BF16 product: 128 or 256 columns per block
+    int gemm_kind = 0;        // split-BF16 product kernel (QGEMM_*)
     int tpass_wpb = 4;        // transport: planes (waves) per block, 1, 2 or 4
     int apass_pc = 32;        // angular pass: lateral cells per block, 8, 16 or 32
     int max_nz = 0;           // longest beam of the wave (set by the driver)
@@ -147,9 +148,12 @@ hipError_t launch_initial(T *psi0, const double *E1, const double *E2, const dou
                           int NA, int NPB, int NP, hipStream_t st);
 
 // split-BF16 source product: P2 as hi + lo; the scanned fluence as hi + lo (nprod = 3: three BF16
-// products) or rounded once to BF16 (nprod = 2: two products)
+// products) or rounded once to BF16 (nprod = 2: two products).  Kernel kinds (same arithmetic, the
+// same accumulation order per output): the scans read straight from global memory (default), or
+// staged in LDS with 256- or 128-column blocks.
+enum { QGEMM_GLOBAL_B = 0, QGEMM_LDS_256 = 1, QGEMM_LDS_128 = 2 };
 hipError_t launch_qgemm_bf16s(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
-                              int nprod, hipStream_t st, int bn = 256);
+                              int nprod, hipStream_t st, int kind = QGEMM_GLOBAL_B);
 hipError_t launch_apass_mfma32(const AParams<float> &P, const float *Ktab, long nstack, hipStream_t st);
 hipError_t launch_apass_mfma16(const AParams<float> &P, const float *Ktab, long nstack, hipStream_t st);
 // operand table of the MFMA angular pass for nth (16 or 32; 1024 floats, unused entries zero)

@@ -1418,6 +1418,155 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
         }
 }
 
+// Source product with the energy-scanned fluence read straight from global memory: its split
+// layout [g][pb][oct][cell][8] is the register layout of the v_mfma_f32_32x32x16_bf16 B operand
+// (lane l: cell l % 32, source nodes 8 (2 kk + l / 32) + 0..7 of the 16-node step kk), so one 16-byte
+// load per lane fetches a whole fragment, 1 KB contiguous per wave.  Only the transfer-matrix tile
+// (128 destination rows x 64 source nodes, hi and lo) is staged in LDS and shared by the 4 waves; the
+// next 16-node step's B fragments are loaded while the current one computes.
+// Block = 128 rows x 256 cells (8 lateral tiles); wave (wm, wn) owns 64 rows x 128 cells as 2 x 4
+// tiles of 32 x 32.
+template <int NPROD>
+__device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const unsigned short *__restrict__ Ahi,
+                                                 const unsigned short *__restrict__ Alo, int Kp, int nmt, int nnt,
+                                                 long nlogical, long per_xcd, long bid)
+{
+    constexpr int BK = 64, LD = BK + 8;   // 64-node stages (the split table is padded to 64); LDS row stride
+    constexpr int KS = BK / 16;                  // 16-node steps per stage
+    constexpr int NCH = 128 * (BK / 8) / 256;    // A chunks of 8 nodes per thread
+    constexpr int NT = 256;
+    constexpr bool BLO = NPROD == 3;
+    __shared__ unsigned short sAh[128 * LD], sAl[128 * LD];
+    const long logical = (bid & 7) * per_xcd + (bid >> 3);
+    if (logical >= nlogical) return;
+    const int mt = (int)(logical % nmt);
+    const long rest = logical / nmt;
+    const int nt = (int)(rest % nnt);
+    const long batch = rest / nnt;
+    const int s = P.s0 + (int)(batch / P.G), g = (int)(batch % P.G);
+    const long off = ((long)s * P.G + g) * P.NLINE;
+    float *__restrict__ C = P.Q + off;
+    const long NAPT = (long)P.NA * PBS_PT;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid >> 1, wn = wid & 1;
+    floatx16 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    const int nk = Kp / BK;
+    // B fragments: tile j of this wave is lateral tile pb_j = nt*8 + wn*4 + j
+    const unsigned short *bph[4], *bpl[4];
+    bool bok[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int pb = nt * 8 + wn * 4 + j;
+        bok[j] = pb < P.NPB;
+        const long base = (((long)s * P.G + g) * P.NPB + (bok[j] ? pb : 0)) * P.NOCT * (PBS_PT * 8) +
+                          (lane & 31) * 8 + (long)(lane >> 5) * (PBS_PT * 8);
+        bph[j] = P.Bh + base;
+        bpl[j] = BLO ? P.Bl + base : nullptr;
+    }
+    // octet of this lane's half at 16-node step kk: 2 kk + lane / 32
+    auto bload = [&](int kk, u16x8 (&bh)[4], u16x8 (&bl)[4]) {
+        const int oc = 2 * kk + (lane >> 5);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (bok[j] && oc < P.NOCT) {
+                bh[j] = *reinterpret_cast<const u16x8 *>(bph[j] + (long)2 * kk * (PBS_PT * 8));
+                if constexpr (BLO) bl[j] = *reinterpret_cast<const u16x8 *>(bpl[j] + (long)2 * kk * (PBS_PT * 8));
+            } else {
+                bh[j] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                if constexpr (BLO) bl[j] = bh[j];
+            }
+        }
+    };
+    // A staging: 128 rows x 4 chunks of 8 source nodes, hi and lo, 2 chunks per thread
+    u16x8 rah[NCH], ral[NCH];
+    auto aload = [&](int kt) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int ch = tid + NT * c, arow = ch / (BK / 8), akq = ch % (BK / 8);
+            const long ao = (long)(mt * 128 + arow) * Kp + kt * BK + akq * 8;
+            rah[c] = *reinterpret_cast<const u16x8 *>(Ahi + ao);
+            ral[c] = *reinterpret_cast<const u16x8 *>(Alo + ao);
+        }
+    };
+    auto astore = [&]() {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int ch = tid + NT * c, arow = ch / (BK / 8), akq = ch % (BK / 8);
+            *reinterpret_cast<u16x8 *>(&sAh[arow * LD + akq * 8]) = rah[c];
+            *reinterpret_cast<u16x8 *>(&sAl[arow * LD + akq * 8]) = ral[c];
+        }
+    };
+    u16x8 b0h[4], b0l[4], b1h[4], b1l[4];
+    aload(0);
+    astore();
+    bload(0, b0h, b0l);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) aload(kt + 1);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int kk = KS * kt + ks;
+            // prefetch the next step's B fragments while this step computes
+            u16x8(&cbh)[4] = (ks & 1) == 0 ? b0h : b1h;
+            u16x8(&cbl)[4] = (ks & 1) == 0 ? b0l : b1l;
+            u16x8(&nbh)[4] = (ks & 1) == 0 ? b1h : b0h;
+            u16x8(&nbl)[4] = (ks & 1) == 0 ? b1l : b0l;
+            if (kk + 1 < KS * nk) bload(kk + 1, nbh, nbl);
+            const int ko = ks * 16 + 8 * (lane >> 5);
+            bf16x8 ah[2], al[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int r = wm * 64 + i * 32 + (lane & 31);
+                ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAh[r * LD + ko]));
+                al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAl[r * LD + ko]));
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bf16x8 bh = __builtin_bit_cast(bf16x8, cbh[j]);
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+                    if constexpr (BLO)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], __builtin_bit_cast(bf16x8, cbl[j]),
+                                                                             acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            astore();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int pb = nt * 8 + wn * 4 + j;
+            if (pb >= P.NPB) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = mt * 128 + wm * 64 + i * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+                if (row < P.NA) C[pb * NAPT + (long)row * PBS_PT + (lane & 31)] = acc[i][j][r];
+            }
+        }
+}
+
+template <int NPROD>
+__global__ __launch_bounds__(256) void qgemm_bf16g_kernel(QParams<float> P, const unsigned short *__restrict__ Ahi,
+                                                          const unsigned short *__restrict__ Alo, int Kp, int nmt,
+                                                          int nnt, long nlogical, long per_xcd)
+{
+    qgemm_bf16g_body<NPROD>(P, Ahi, Alo, Kp, nmt, nnt, nlogical, per_xcd, blockIdx.x);
+}
+
 template <int BN, int NPROD>
 __global__ __launch_bounds__(2 * BN) void qgemm_bf16s_kernel(QParams<float> P, const unsigned short *__restrict__ Ahi,
                                                              const unsigned short *__restrict__ Alo, int Kp, int nmt,
@@ -1427,11 +1576,24 @@ __global__ __launch_bounds__(2 * BN) void qgemm_bf16s_kernel(QParams<float> P, c
 }
 
 hipError_t launch_qgemm_bf16s(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
-                              int nprod, hipStream_t st, int bn)
+                              int nprod, hipStream_t st, int kind)
 {
+    const int bn = kind == QGEMM_LDS_128 ? 128 : 256;
     const int nmt = P.Mp / 128, nnt = (P.NPB + bn / 32 - 1) / (bn / 32);
     const long nlog = (long)P.ns * P.G * nnt * nmt;
     const long per = (nlog + 7) / 8;
+    if (kind == QGEMM_GLOBAL_B) {
+        const int nmt2 = P.Mp / 128, nnt2 = (P.NPB + 7) / 8;
+        const long nlog2 = (long)P.ns * P.G * nnt2 * nmt2;
+        const long per2 = (nlog2 + 7) / 8;
+        if (nprod == 3)
+            hipLaunchKernelGGL(qgemm_bf16g_kernel<3>, dim3((unsigned)(per2 * 8)), dim3(256), 0, st, P, Ahi, Alo, Kp,
+                               nmt2, nnt2, nlog2, per2);
+        else
+            hipLaunchKernelGGL(qgemm_bf16g_kernel<2>, dim3((unsigned)(per2 * 8)), dim3(256), 0, st, P, Ahi, Alo, Kp,
+                               nmt2, nnt2, nlog2, per2);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)(per * 8));
 #define PBS_QG(BN_, NP_) \
     hipLaunchKernelGGL((qgemm_bf16s_kernel<BN_, NP_>), grid, dim3(2 * BN_), 0, st, P, Ahi, Alo, Kp, nmt, nnt, nlog, per)
@@ -1710,8 +1872,10 @@ __global__ __launch_bounds__(256) void epass_batched_kernel(const BeamDev *__res
         epass8_body<MODE_CLOSE>(P, gid);
 }
 
+// BN = 128 / 256: LDS-staged kernel with BN-column blocks; BN = 0: global-B kernel (256 columns)
 template <int BN, int NPROD>
-__global__ __launch_bounds__(2 * BN) void qgemm_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
+__global__ __launch_bounds__(BN == 0 ? 256 : 2 * BN) void qgemm_batched_kernel(const BeamDev *__restrict__ beams,
+                                                                               BatchShape Sh, int s)
 {
     const BeamDev &B = beams[blockIdx.y];
     const int mode = beam_mode(s, B.nz);
@@ -1732,11 +1896,15 @@ __global__ __launch_bounds__(2 * BN) void qgemm_batched_kernel(const BeamDev *__
     P.s0 = (mode == MODE_OPEN) ? 1 : 0;
     P.ns = (mode == MODE_PAIR) ? 2 : 1;
     P.NLINE = Sh.NLINE;
-    const int nmt = Sh.Mp / 128, nnt = (Sh.NPB + BN / 32 - 1) / (BN / 32);
+    constexpr int BW = BN == 0 ? 256 : BN;
+    const int nmt = Sh.Mp / 128, nnt = (Sh.NPB + BW / 32 - 1) / (BW / 32);
     const long nlog = (long)P.ns * P.G * nnt * nmt;
     const long per = (nlog + 7) / 8;
     if ((long)blockIdx.x >= per * 8) return;
-    qgemm_bf16s_body<BN, NPROD>(P, Sh.Ahi, Sh.Alo, Sh.Kpb, nmt, nnt, nlog, per, blockIdx.x);
+    if constexpr (BN == 0)
+        qgemm_bf16g_body<NPROD>(P, Sh.Ahi, Sh.Alo, Sh.Kpb, nmt, nnt, nlog, per, blockIdx.x);
+    else
+        qgemm_bf16s_body<BN, NPROD>(P, Sh.Ahi, Sh.Alo, Sh.Kpb, nmt, nnt, nlog, per, blockIdx.x);
 }
 
 template <int NSEG, int WPB>
@@ -1846,17 +2014,22 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
         const unsigned nbe = (unsigned)(((long)Sh.NPB * Sh.NOCT * (8 / PBS_EPASS_LPT) * PBS_PT + 255) / 256);
         hipLaunchKernelGGL(epass_batched_kernel, dim3(nbe, nbeam), dim3(256), 0, st, beams, Sh, k, s);
         if (k + 1 < Sh.ngen) {
-            const int bn = tu.gemm_bn;
+            const int kind = tu.gemm_kind;
+            const int bn = kind == QGEMM_LDS_128 ? 128 : 256;
             const int nmt = Sh.Mp / 128, nnt = (Sh.NPB + bn / 32 - 1) / (bn / 32);
             const long per = ((long)2 * maxG * nnt * nmt + 7) / 8;
             const dim3 grid((unsigned)(per * 8), nbeam);
 #define PBS_QB(BN_, NP_) hipLaunchKernelGGL((qgemm_batched_kernel<BN_, NP_>), grid, dim3(2 * BN_), 0, st, beams, Sh, s)
-            if (bn == 128) {
+#define PBS_QG(NP_) hipLaunchKernelGGL((qgemm_batched_kernel<0, NP_>), grid, dim3(256), 0, st, beams, Sh, s)
+            if (kind == QGEMM_GLOBAL_B) {
+                if (Sh.nprod == 3) PBS_QG(3); else PBS_QG(2);
+            } else if (bn == 128) {
                 if (Sh.nprod == 3) PBS_QB(128, 3); else PBS_QB(128, 2);
             } else {
                 if (Sh.nprod == 3) PBS_QB(256, 3); else PBS_QB(256, 2);
             }
 #undef PBS_QB
+#undef PBS_QG
         }
     }
     hipLaunchKernelGGL(dose_batched_kernel, dim3(Sh.NPB, nbeam), dim3(1024), 0, st, beams, Sh, s);

@@ -344,7 +344,8 @@ class Batch:
     def tuning(self) -> dict:
         t = (C.c_int * 3)()
         self._check(self.L.pbs_batch_tuning(self.h, t))
-        return {"gemm_bn": t[0], "tpass_waves_per_block": t[1], "apass_cells_per_block": t[2]}
+        return {"gemm_kernel": ["global", "lds256", "lds128"][t[0]], "tpass_waves_per_block": t[1],
+                "apass_cells_per_block": t[2]}
 
     def close(self):
         if getattr(self, "h", None):
