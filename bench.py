@@ -188,6 +188,8 @@ def main():
                     help="config-4 beams for the batched leg (0 = skip)")
     ap.add_argument("--surrogate-beams", type=int, default=4,
                     help="config-5 held-out beams for the surrogate leg (0 = skip)")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="run only the surrogate leg (for profiling it alone; prints that leg's JSON object)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -201,6 +203,9 @@ def main():
     from paper_2504_00340_amd import inputs as I
     from paper_2504_00340_amd.pbsplit import Solver
 
+    if args.surrogate_only:
+        print(json.dumps({"surrogate": surrogate(max(1, args.surrogate_beams))}))
+        return
     cfg = I.config2(args.case)
     g = cfg["grid"]
     if args.warmup + args.steps > g["nz"]:

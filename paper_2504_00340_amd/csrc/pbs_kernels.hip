@@ -24,10 +24,10 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
 // ------------------------------------------------------------------------------- energy pass
-// Block = one lateral tile pb and one octet of angular lines a = 8*oct + e (e = tid/32), 32 cells
-// pt = tid%32: the split-BF16 scans of the 8 lines of a cell are gathered in LDS and written as one
-// 16-byte chunk (one LDS buffer per group parity, one barrier per group).
-template <typename T, int MODE, bool SPLIT>
+// One thread per line (FP64 contexts, and FP32 contexts whose source product takes the plain scan W):
+// block = one lateral tile pb and one octet of angular lines a = 8*oct + e (e = tid/32), 32 cells
+// pt = tid%32.  FP32 contexts with the split-BF16 product use epass8_body below.
+template <typename T, int MODE>
 __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
 {
     constexpr bool CL = (MODE & MODE_CLOSE) != 0;
@@ -36,10 +36,8 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
     const int pbk = bx / P.NOCT, oct = bx % P.NOCT;
     const int e = threadIdx.x >> 5, ptc = threadIdx.x & 31;
     const int a = oct * 8 + e;
-    const bool valid = a < NA;
-    if (!SPLIT && !valid) return;
-    const long line = ((long)pbk * NA + (valid ? a : 0)) * PBS_PT + ptc;
-    __shared__ unsigned short wsh[2][4][PBS_PT * 8];   // [group parity][hi c, lo c, hi o, lo o][pt*8 + e]
+    if (a >= NA) return;
+    const long line = ((long)pbk * NA + a) * PBS_PT + ptc;
     const long pq = (line / P.NAPT) * PBS_PT + (line % PBS_PT);
     const long S = P.NLINE;
     const long QS = (long)P.G * S;
@@ -51,19 +49,19 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
     T U0 = 0, U1 = 0, U2 = 0;       // re-emission energy scans of states 0, 1, 2
     double ph0 = 0, ph1 = 0, ph2 = 0, injc = 0, injo = 0;
     T fic = 0, fio = 0, fme = 0, fmn = 0;   // surrogate records (energy sent to the next generation, moments)
-    const bool hasQ = P.Q != nullptr, hasW = SPLIT ? P.Wh != nullptr : P.W != nullptr;
+    const bool hasQ = P.Q != nullptr, hasW = P.W != nullptr;
     const bool feat = P.inj_c != nullptr;
     for (int g = P.G - 1; g >= 0; --g) {
         T *p1 = P.psi + (2L * g) * S + line;
         T *p2 = p1 + S;
-        const T x1 = valid ? *p1 : T(0), x2 = valid ? *p2 : T(0);
+        const T x1 = *p1, x2 = *p2;
         const T sm = P.Sm[g], sp = P.Sp[g], kp = P.kap[g];
         // rho-free operator: psi1 row [-(S-+k), S-], psi2 row [-3S+, -(S+ + 2S- + k)], coupling S+[1,3]
         const T d11 = -(sm + kp), d12 = sm, d21 = T(-3) * sp, d22 = -(sp + T(2) * sm + kp);
         const T c1 = sp, c2 = T(3) * sp;
         // trapezoidal sources of the two half-steps: Q^n + Q* (close), Q^n + Q* (open)
         T qc = 0, qo = 0;
-        if (hasQ && valid) {
+        if (hasQ) {
             const long o = (long)g * S + line;
             if (CL) qc = P.Q[o];
             if (OP) qo = P.Q[QS + o];
@@ -88,10 +86,8 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
             z1 = (r1 * m22 - m12 * r2) * inv;
             z2 = (m11 * r2 - m21 * r1) * inv;
         }
-        if (valid) {
-            *p1 = z1;
-            *p2 = z2;
-        }
+        *p1 = z1;
+        *p2 = z2;
         // deposit functional (FP64): stopping + removal of every state, bottom-face outflow
         const double A = P.dA[g], B = P.dB[g];
         if (CL) ph0 += A * (double)x1 + B * (double)x2;
@@ -126,40 +122,14 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
                 }
             }
             if (hasW) {
-                if constexpr (SPLIT) {
-                    // hi + lo bfloat16 pair of each sum; 8 lines of a cell -> one 16-byte chunk
-                    unsigned short *buf = &wsh[g & 1][0][0];
-                    const int so = ptc * 8 + e;
-                    float vc = valid && CL ? (float)((U0 + U1) * idE) : 0.f;
-                    float vo = valid && OP ? (float)((U1 + U2) * idE) : 0.f;
-                    const __bf16 hc = (__bf16)vc, ho = (__bf16)vo;
-                    buf[0 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, hc);
-                    buf[1 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, (__bf16)(vc - (float)hc));
-                    buf[2 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, ho);
-                    buf[3 * PBS_PT * 8 + so] = __builtin_bit_cast(unsigned short, (__bf16)(vo - (float)ho));
-                    __syncthreads();
-                    const int t = threadIdx.x;
-                    const int arr = t >> 5;   // 0 hi c, 1 lo c, 2 hi o, 3 lo o (lo parts only with Wl)
-                    const bool want = t < 128 && ((arr < 2) ? CL : OP) && (!(arr & 1) || P.Wl != nullptr);
-                    if (want) {
-                        const long SB = (long)P.G * (S / P.NAPT) * P.NOCT * (PBS_PT * 8);
-                        const long ob = (((long)g * (S / P.NAPT) + pbk) * P.NOCT + oct) * (PBS_PT * 8) + (t & 31) * 8 +
-                                        (arr >= 2 ? SB : 0);
-                        unsigned short *dst = (arr & 1) ? P.Wl : P.Wh;
-                        *reinterpret_cast<u16x8v *>(dst + ob) =
-                            *reinterpret_cast<const u16x8v *>(&buf[arr * PBS_PT * 8 + (t & 31) * 8]);
-                    }
-                } else {
-                    if (CL) P.W[o] = (U0 + U1) * idE;
-                    if (OP) P.W[QS + o] = (U1 + U2) * idE;
-                }
+                if (CL) P.W[o] = (U0 + U1) * idE;
+                if (OP) P.W[QS + o] = (U1 + U2) * idE;
             }
         }
         fin = x1 - x2;
         fcl = y1 - y2;
         fop = z1 - z2;
     }
-    if (!valid) return;
     if (CL) P.dep_c[line] = dac * (ph0 + ph1 - injc) * P.scale;
     if (OP) P.dep_o[line] = dao * (ph1 + ph2 - injo) * P.scale;
     if (feat) {
@@ -172,26 +142,23 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
     }
 }
 
-template <typename T, int MODE, bool SPLIT>
+template <typename T, int MODE>
 __global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
 {
-    epass_body<T, MODE, SPLIT>(P, blockIdx.x);
+    epass_body<T, MODE>(P, blockIdx.x);
 }
 
 template <typename T>
 hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st)
 {
+    if (P.Wh != nullptr) return hipErrorInvalidValue;   // split scans: launch_epass8
     const unsigned nb = (unsigned)((P.NLINE / P.NAPT) * P.NOCT);
-    const bool split = P.Wh != nullptr;
-#define PBS_EP(M, SP) hipLaunchKernelGGL((epass_kernel<T, M, SP>), dim3(nb), dim3(256), 0, st, P)
-    if (mode == MODE_PAIR) {
-        if (split) PBS_EP(MODE_PAIR, true); else PBS_EP(MODE_PAIR, false);
-    } else if (mode == MODE_OPEN) {
-        if (split) PBS_EP(MODE_OPEN, true); else PBS_EP(MODE_OPEN, false);
-    } else {
-        if (split) PBS_EP(MODE_CLOSE, true); else PBS_EP(MODE_CLOSE, false);
-    }
-#undef PBS_EP
+    if (mode == MODE_PAIR)
+        hipLaunchKernelGGL((epass_kernel<T, MODE_PAIR>), dim3(nb), dim3(256), 0, st, P);
+    else if (mode == MODE_OPEN)
+        hipLaunchKernelGGL((epass_kernel<T, MODE_OPEN>), dim3(nb), dim3(256), 0, st, P);
+    else
+        hipLaunchKernelGGL((epass_kernel<T, MODE_CLOSE>), dim3(nb), dim3(256), 0, st, P);
     return hipGetLastError();
 }
 
@@ -584,7 +551,9 @@ __global__ __launch_bounds__(256) void tpass_dpp_kernel(TParams<float> P)
     tpass_dpp_body(P, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
-// Same sweep when ny is 32 or 64 and nx a multiple of 8: a lane's address is affine in the row
+constexpr int TPASS_PF = 8;   // rows of the row-affine sweep loaded ahead (nx must be a multiple)
+
+// Same sweep when ny is 32 or 64 and nx a multiple of TPASS_PF: a lane's address is affine in the row
 // (row stride = ny/32 lateral tiles), so each row costs one pointer increment and no guards; lanes
 // beyond ny (ny = 32) read a clamped in-range column and are zeroed.
 template <int NY>
@@ -622,24 +591,25 @@ __device__ __forceinline__ void tpass_affine_body(const TParams<float> &P, long 
         }
     }
     const float vmask = valid ? 1.f : 0.f;
-    float rb[16];
+    constexpr int PF = TPASS_PF;   // rows loaded ahead of the sweep
+    float rb[2 * PF];
     const float *ld = ptr;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        rb[i] = *ld * vmask;
-        ld += step;
+    for (int i = 0; i < PF; ++i) {
+        rb[i] = i < nx ? *ld * vmask : 0.f;
+        if (i < nx) ld += step;
     }
     float *st = ptr;
     float pm1 = 0.f, dxm = 0.f, ym1 = 0.f;
-    for (int r0 = 0; r0 < nx; r0 += 8) {
-        const bool more = r0 + 8 < nx;
+    for (int r0 = 0; r0 < nx; r0 += PF) {
+        const bool more = r0 + PF < nx;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            rb[8 + i] = more ? *ld * vmask : 0.f;
+        for (int i = 0; i < PF; ++i) {
+            rb[PF + i] = more ? *ld * vmask : 0.f;
             if (more) ld += step;
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < PF; ++i) {
             const float p0 = rb[i], p1 = rb[i + 1];
             const float left = dpp_f<0x138, 0xF>(p0);
             const float right = dpp_f<0x130, 0xF>(p0);
@@ -661,7 +631,7 @@ __device__ __forceinline__ void tpass_affine_body(const TParams<float> &P, long 
             ym1 = y;
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) rb[i] = rb[8 + i];
+        for (int i = 0; i < PF; ++i) rb[i] = rb[PF + i];
     }
 }
 
@@ -676,11 +646,11 @@ hipError_t launch_tpass(const TParams<T> &P, hipStream_t st)
 {
     if constexpr (sizeof(T) == 4) {
         const dim3 grid((unsigned)((P.nplanes + 3) / 4));
-        if (P.nx % 8 == 0 && P.ny == 64) {
+        if (P.nx % TPASS_PF == 0 && P.ny == 64) {
             hipLaunchKernelGGL(tpass_affine_kernel<64>, grid, dim3(256), 0, st, P);
             return hipGetLastError();
         }
-        if (P.nx % 8 == 0 && P.ny == 32) {
+        if (P.nx % TPASS_PF == 0 && P.ny == 32) {
             hipLaunchKernelGGL(tpass_affine_kernel<32>, grid, dim3(256), 0, st, P);
             return hipGetLastError();
         }
@@ -2042,11 +2012,11 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
 #define PBS_TW(NS) do { if (w == 1) PBS_TB(NS, 1); else if (w == 2) PBS_TB(NS, 2); else PBS_TB(NS, 4); } while (0)
 #define PBS_TA(NY, W) hipLaunchKernelGGL((tpass_batched_affine_kernel<NY, W>), dim3(nb, nbeam), dim3(64 * W), 0, st, beams, Sh, s)
 #define PBS_TAW(NY) do { if (w == 1) PBS_TA(NY, 1); else if (w == 2) PBS_TA(NY, 2); else PBS_TA(NY, 4); } while (0)
-        if (Sh.nx % 8 == 0 && Sh.ny == 64) {
+        if (Sh.nx % TPASS_PF == 0 && Sh.ny == 64) {
             PBS_TAW(64);
             return;
         }
-        if (Sh.nx % 8 == 0 && Sh.ny == 32) {
+        if (Sh.nx % TPASS_PF == 0 && Sh.ny == 32) {
             PBS_TAW(32);
             return;
         }

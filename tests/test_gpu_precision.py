@@ -59,6 +59,24 @@ def test_config2_fp32_dose_within_1e4_of_fp64(case, src):
     assert lo < zpk < hi, zpk
 
 
+def test_config3_fp32_dose_within_1e4_of_fp64():
+    """Configuration 3: 180 MeV, 96x96 lateral (the transport sweep spans two 64-column segments),
+    32x32 angles, 160 groups, 400 steps over 26 cm, K = 1, seeded layered water/bone/lung phantom
+    with a half-plane bone insert and smooth noise."""
+    import time
+
+    c = I.config3(0)
+    print("case config 3 seed 0", flush=True)
+    ref = _run(c, "fp64")
+    t0 = time.perf_counter()
+    d = _run(c, "fp32")
+    dt = time.perf_counter() - t0
+    rel = float(np.linalg.norm(d - ref) / np.linalg.norm(ref))
+    print(f"config 3: FP32 vs FP64 dose rel-L2 {rel:.3e}; FP32 beam {dt:.1f} s", flush=True)
+    assert rel <= 1e-4
+    assert np.all(np.isfinite(d))
+
+
 def test_source_precision_modes_agree():
     from paper_2504_00340_amd.pbsplit import PBS_SRC_BF16X2, PBS_SRC_BF16X3, PBS_SRC_FP32, PbsError, Solver
 
