@@ -48,7 +48,7 @@ def algorithmic(grid, tsz=4):
                 qgemm=("flops", qg_flops, qg_bytes))
 
 
-KIND_KERNEL = {"tpass": "tpass_affine_kernel<64>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16s_kernel<256, 2>",
+KIND_KERNEL = {"tpass": "tpass_affine_kernel<64>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16g_kernel<1>",
                "epass": "epass_kernel<float, 3, true>"}
 
 
@@ -181,7 +181,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--case", default="water", choices=["water", "bone", "lung"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--source", default="bf16x2", choices=["bf16x2", "bf16x3", "fp32"],
+    ap.add_argument("--source", default="bf16x1", choices=["bf16x1", "bf16x2", "bf16x3", "fp32"],
                     help="arithmetic of the angular source product (FP32 contexts)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-beams", type=int, default=8,
@@ -214,11 +214,12 @@ def main():
           flush=True)
     s = Solver(g, cfg["phys"], precision=args.precision, device="cuda:0")
     split = args.precision == "fp32" and args.source != "fp32"
-    nprod = 3 if args.source == "bf16x3" else 2
+    nprod = {"bf16x3": 3, "bf16x2": 2, "bf16x1": 1}.get(args.source, 2)
     if args.precision == "fp32":
-        from paper_2504_00340_amd.pbsplit import PBS_SRC_BF16X2, PBS_SRC_BF16X3, PBS_SRC_FP32
+        from paper_2504_00340_amd.pbsplit import PBS_SRC_BF16X1, PBS_SRC_BF16X2, PBS_SRC_BF16X3, PBS_SRC_FP32
 
-        s.set_source_precision({"bf16x2": PBS_SRC_BF16X2, "bf16x3": PBS_SRC_BF16X3}.get(args.source, PBS_SRC_FP32))
+        s.set_source_precision({"bf16x1": PBS_SRC_BF16X1, "bf16x2": PBS_SRC_BF16X2,
+                                "bf16x3": PBS_SRC_BF16X3}.get(args.source, PBS_SRC_FP32))
     s.set_phantom(cfg["rho"])
     s.set_beam(cfg["beam"])
     s.step(args.warmup)
@@ -244,7 +245,7 @@ def main():
     avg_s = ms / max(n, 1) / 1e3
     if alg[dom][0] == "bytes":
         achieved = alg[dom][1] / avg_s / 1e9
-        split_ok = args.precision == "fp32" and args.case == "water" and args.source == "bf16x2"
+        split_ok = args.precision == "fp32" and args.case == "water" and args.source == "bf16x1"
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom) if split_ok else None, "kernel": dom,
                 "algorithmic_bytes_per_launch": alg[dom][1], "avg_launch_ms": avg_s * 1e3}
@@ -259,7 +260,7 @@ def main():
             peak = FP32_MFMA_TFLOPS if mfma else FP32_VALU_TFLOPS
         roof = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "dtype": args.source if split else args.precision,
-                "traffic": measured_traffic(dom) if args.source == "bf16x2" and args.case == "water" else None,
+                "traffic": measured_traffic(dom) if args.source == "bf16x1" and args.case == "water" else None,
                 "kernel": dom, "algorithmic_flops_per_launch": alg[dom][1],
                 "avg_launch_ms": avg_s * 1e3}
     out = {

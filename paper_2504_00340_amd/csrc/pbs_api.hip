@@ -27,6 +27,76 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 namespace pbs {
+namespace {
+unsigned short bf16_rne(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+double bf16_val(unsigned short h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+}
+}  // namespace
+
+// The transfer matrix for the split-BF16 source product, [3][Mp][Kpb] zero-padded, row = destination:
+// hi = bf16(P2), lo = bf16(P2 - hi), and a single-BF16 copy whose columns are compensated so that
+// each column (one source node) still sums to its exact total: starting from bf16(P2), entries are
+// moved by one BF16 ulp at a time, each time the entry whose ulp best reduces the residual, until
+// the residual is below 1e-7 of the total (or no step reduces it).  Without the compensation the
+// rounding of this fixed table would bias the number of re-emitted protons the same way in every
+// cell and group.
+void transfer_table_bf16(const std::vector<double> &P2T, int NA, int Mp, int Kpb, std::vector<unsigned short> &out)
+{
+    const size_t MK = (size_t)Mp * Kpb;
+    out.assign(3 * MK, 0);
+    for (int a = 0; a < NA; ++a)
+        for (int k = 0; k < NA; ++k) {
+            const double x = P2T[(size_t)a * NA + k];
+            const unsigned short hi = bf16_rne((float)x);
+            out[(size_t)a * Kpb + k] = hi;
+            out[MK + (size_t)a * Kpb + k] = bf16_rne((float)(x - bf16_val(hi)));
+            out[2 * MK + (size_t)a * Kpb + k] = hi;
+        }
+    for (int k = 0; k < NA; ++k) {
+        double target = 0.0, cur = 0.0;
+        for (int a = 0; a < NA; ++a) {
+            target += P2T[(size_t)a * NA + k];
+            cur += bf16_val(out[2 * MK + (size_t)a * Kpb + k]);
+        }
+        double r = target - cur;
+        for (int it = 0; it < 256 && std::fabs(r) > 1e-7 * std::fabs(target); ++it) {
+            int best = -1;
+            double bestr = std::fabs(r), bstep = 0.0;
+            for (int a = 0; a < NA; ++a) {
+                const unsigned short h = out[2 * MK + (size_t)a * Kpb + k];
+                const double v = bf16_val(h);
+                if (!(v > 0.0)) continue;
+                // the neighbouring BF16 value in the direction of the residual (positive entries only)
+                const unsigned short hn = r > 0 ? (unsigned short)(h + 1) : (unsigned short)(h - 1);
+                const double vn = bf16_val(hn);
+                if (!(vn > 0.0) || !std::isfinite(vn)) continue;
+                const double step = vn - v;
+                const double nr = std::fabs(r - step);
+                if (nr < bestr) {
+                    bestr = nr;
+                    best = a;
+                    bstep = step;
+                }
+            }
+            if (best < 0) break;
+            unsigned short &h = out[2 * MK + (size_t)best * Kpb + k];
+            h = r > 0 ? (unsigned short)(h + 1) : (unsigned short)(h - 1);
+            r -= bstep;
+        }
+    }
+}
+
 // nth = 32: the 31-point sine transform split by mode parity, [(mat*4 + s)*64 + lane] =
 // A_mat[lane % 16][4 s + lane / 16] for mat = Sodd, Seven, Sodd^T, Seven^T.
 // nth = 16: the dense 15-point transform zero-padded to 16 x 16, [s*64 + lane] = S[lane % 16][4 s + lane / 16].
@@ -262,7 +332,7 @@ void layout(pbs_ctx *c)
     c->o_tabD = o;
     o = align256(o + d * sizeof(double));
     c->o_bf = o;
-    if (c->Kpb > 0) o = align256(o + (size_t)2 * c->Mp * c->Kpb * sizeof(unsigned short));
+    if (c->Kpb > 0) o = align256(o + (size_t)3 * c->Mp * c->Kpb * sizeof(unsigned short));
     c->total = o;
 }
 
@@ -305,28 +375,7 @@ pbs_status upload_tables(pbs_ctx *c)
     }
     std::vector<unsigned short> bf;
     if (c->Kpb > 0) {
-        // P2 as hi + lo bfloat16 (round to nearest even), row-major [Mp][Kpb]: row = destination
-        auto rne = [](float x) {
-            uint32_t u;
-            std::memcpy(&u, &x, 4);
-            u += 0x7FFFu + ((u >> 16) & 1u);
-            return (unsigned short)(u >> 16);
-        };
-        auto tof = [](unsigned short h) {
-            uint32_t u = (uint32_t)h << 16;
-            float f;
-            std::memcpy(&f, &u, 4);
-            return f;
-        };
-        bf.assign((size_t)2 * c->Mp * c->Kpb, 0);
-        for (int a = 0; a < c->NA; ++a)
-            for (int k = 0; k < c->NA; ++k) {
-                const double x = c->P2T[(size_t)a * c->NA + k];
-                const unsigned short hi = rne((float)x);
-                const unsigned short lo = rne((float)(x - (double)tof(hi)));
-                bf[(size_t)a * c->Kpb + k] = hi;
-                bf[(size_t)c->Mp * c->Kpb + (size_t)a * c->Kpb + k] = lo;
-            }
+        transfer_table_bf16(c->P2T, c->NA, c->Mp, c->Kpb, bf);
         HIPCHK(c, hipMemcpyAsync(c->ws + c->o_bf, bf.data(), bf.size() * sizeof(unsigned short), hipMemcpyHostToDevice,
                                  c->stream));
     }
@@ -373,7 +422,7 @@ EParams<T> eparams(pbs_ctx *c, int k, int lay_c, int lay_o, double h)
     P.W = (k + 1 < c->kact) ? c->W<T>() : nullptr;
     P.Wh = P.Wl = nullptr;
     P.NOCT = c->NOCT;
-    if (P.W && c->Kpb > 0 && (c->src_mode == PBS_SRC_BF16X3 || c->src_mode == PBS_SRC_BF16X2)) {
+    if (P.W && c->Kpb > 0 && c->src_mode != PBS_SRC_FP32) {
         P.Wh = reinterpret_cast<unsigned short *>(c->ws + c->o_W);
         P.Wl = c->src_mode == PBS_SRC_BF16X3 ? P.Wh + c->Wb_half : nullptr;
     }
@@ -449,10 +498,11 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
             Q.ns = (mode == MODE_PAIR) ? 2 : 1;
             ProfScope ps(c, PBS_K_QGEMM);
             if constexpr (sizeof(T) == 4) {
-                if (c->Kpb > 0 && (c->src_mode == PBS_SRC_BF16X3 || c->src_mode == PBS_SRC_BF16X2)) {
+                if (c->Kpb > 0 && c->src_mode != PBS_SRC_FP32) {
                     const unsigned short *ah = reinterpret_cast<const unsigned short *>(c->ws + c->o_bf);
-                    HIPCHK(c, launch_qgemm_bf16s(Q, ah, ah + (size_t)c->Mp * c->Kpb, c->Kpb,
-                                                 c->src_mode == PBS_SRC_BF16X3 ? 3 : 2, c->stream));
+                    const size_t MK = (size_t)c->Mp * c->Kpb;
+                    const int np = src_nprod(c->src_mode);
+                    HIPCHK(c, launch_qgemm_bf16s(Q, np == 1 ? ah + 2 * MK : ah, ah + MK, c->Kpb, np, c->stream));
                     continue;
                 }
             }
@@ -1037,7 +1087,7 @@ pbs_status pbs_apply(pbs_ctx *c, int op, int layer, double h)
 pbs_status pbs_set_source_precision(pbs_ctx *c, int mode)
 {
     if (!c) return PBS_EINVAL;
-    if (mode != PBS_SRC_FP32 && mode != PBS_SRC_BF16X3 && mode != PBS_SRC_BF16X2)
+    if (mode != PBS_SRC_FP32 && mode != PBS_SRC_BF16X3 && mode != PBS_SRC_BF16X2 && mode != PBS_SRC_BF16X1)
         return fail(c, PBS_EINVAL, "unknown source precision");
     if (mode != PBS_SRC_FP32 && c->Kpb == 0)
         return fail(c, PBS_EUNSUPPORTED, "split-BF16 source product needs an FP32 context with >= 128 angular unknowns");

@@ -217,6 +217,7 @@ BatchShape shape(const pbs_batch *b)
     Sh.K = reinterpret_cast<const float *>(S + b->sh_K);
     Sh.Ahi = reinterpret_cast<const unsigned short *>(S + b->sh_A);
     Sh.Alo = Sh.Ahi + (size_t)b->Mp * b->Kpb;
+    if (src_nprod(PBS_DEFAULT_SRC) == 1) Sh.Ahi += (size_t)2 * b->Mp * b->Kpb;   // the compensated copy
     Sh.Kpb = b->Kpb;
     Sh.Mp = b->Mp;
     Sh.nprod = src_nprod(PBS_DEFAULT_SRC);
@@ -362,7 +363,7 @@ pbs_status pbs_batch_create(const pbs_grid *grids, const pbs_beam *beams, int nb
     b->sh_S = sh;
     sh = a256(sh + (size_t)b->m * b->m * 4);
     b->sh_A = sh;
-    sh = a256(sh + (size_t)2 * b->Mp * b->Kpb * 2);
+    sh = a256(sh + (size_t)3 * b->Mp * b->Kpb * 2);
     b->sh_K = sh;
     sh = a256(sh + (size_t)1024 * 4);
     b->o_shared = o;
@@ -410,26 +411,8 @@ pbs_status pbs_batch_bind(pbs_batch *b, void *ws, size_t bytes, void *stream)
         lam[i] = (float)c0->lam[i];
     }
     for (size_t i = 0; i < S.size(); ++i) S[i] = (float)c0->sinS[i];
-    std::vector<unsigned short> A((size_t)2 * b->Mp * b->Kpb, 0);
-    auto rne = [](float x) {
-        uint32_t u;
-        std::memcpy(&u, &x, 4);
-        u += 0x7FFFu + ((u >> 16) & 1u);
-        return (unsigned short)(u >> 16);
-    };
-    auto tof = [](unsigned short h) {
-        uint32_t u = (uint32_t)h << 16;
-        float f;
-        std::memcpy(&f, &u, 4);
-        return f;
-    };
-    for (int a = 0; a < b->NA; ++a)
-        for (int k = 0; k < b->NA; ++k) {
-            const double x = c0->P2T[(size_t)a * b->NA + k];
-            const unsigned short hi = rne((float)x);
-            A[(size_t)a * b->Kpb + k] = hi;
-            A[(size_t)b->Mp * b->Kpb + (size_t)a * b->Kpb + k] = rne((float)(x - (double)tof(hi)));
-        }
+    std::vector<unsigned short> A;
+    transfer_table_bf16(c0->P2T, b->NA, b->Mp, b->Kpb, A);
     char *Sp = b->ws + b->o_shared;
     BHIP(b, hipMemcpyAsync(Sp + b->sh_theta, th.data(), th.size() * 4, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(Sp + b->sh_lam, lam.data(), lam.size() * 4, hipMemcpyHostToDevice, b->stream));

@@ -108,7 +108,8 @@ struct BatchShape {
     const float *K;                        // MFMA operand table of the angular pass (nth 16 or 32)
     const unsigned short *Ahi, *Alo;       // split-BF16 P2, [Mp][Kpb]
     int Kpb, Mp;
-    int nprod;                             // 3: scanned fluence as hi + lo; 2: hi only (no lo array)
+    int nprod;                             // 3: scanned fluence as hi + lo; 2: hi only (no lo array);
+                                           // 1: hi only, with the compensated single-BF16 matrix as Ahi
     int nx, ny, nth, m, NA, NPB, NOCT, ngen;
     long NLINE;
     float dx, dy;
@@ -148,7 +149,8 @@ hipError_t launch_initial(T *psi0, const double *E1, const double *E2, const dou
                           int NA, int NPB, int NP, hipStream_t st);
 
 // split-BF16 source product: P2 as hi + lo; the scanned fluence as hi + lo (nprod = 3: three BF16
-// products) or rounded once to BF16 (nprod = 2: two products).  Kernel kinds (same arithmetic, the
+// products) or rounded once to BF16 (nprod = 2: two products); nprod = 1: one product of the
+// column-compensated single-BF16 matrix (passed as Ahi) with the rounded scan.  Kernel kinds (same arithmetic, the
 // same accumulation order per output): the scans read straight from global memory (default), or
 // staged in LDS with 256- or 128-column blocks.
 enum { QGEMM_GLOBAL_B = 0, QGEMM_LDS_256 = 1, QGEMM_LDS_128 = 2 };

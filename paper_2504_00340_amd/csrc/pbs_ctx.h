@@ -10,8 +10,13 @@
 enum { ST_CREATED = 0, ST_BOUND = 1, ST_PHANTOM = 2, ST_BEAM = 3 };
 
 // source-product arithmetic of FP32 contexts with >= 128 angular unknowns (and of every batch)
-constexpr int PBS_DEFAULT_SRC = PBS_SRC_BF16X2;
-inline int src_nprod(int mode) { return mode == PBS_SRC_BF16X2 ? 2 : 3; }
+constexpr int PBS_DEFAULT_SRC = PBS_SRC_BF16X1;
+inline int src_nprod(int mode) { return mode == PBS_SRC_BF16X1 ? 1 : mode == PBS_SRC_BF16X2 ? 2 : 3; }
+
+namespace pbs {
+// split-BF16 transfer matrix [3][Mp][Kpb]: hi, lo, and a column-compensated single-BF16 copy
+void transfer_table_bf16(const std::vector<double> &P2T, int NA, int Mp, int Kpb, std::vector<unsigned short> &out);
+}  // namespace pbs
 
 struct pbs_ctx {
     pbs_grid g;

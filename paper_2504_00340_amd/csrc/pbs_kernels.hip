@@ -1274,7 +1274,8 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
     constexpr int WN = BN / 64;           // waves along N (2 along M)
     constexpr int NT = 128 * WN;          // threads
     constexpr bool BLO = NPROD == 3;      // the lo part of the scanned fluence takes part
-    __shared__ unsigned short sAh[128 * LD], sAl[128 * LD], sBh[BN * LD], sBl[BLO ? BN * LD : 8];
+    constexpr bool ALO = NPROD >= 2;      // the lo part of the transfer matrix takes part
+    __shared__ unsigned short sAh[128 * LD], sAl[ALO ? 128 * LD : 8], sBh[BN * LD], sBl[BLO ? BN * LD : 8];
     const long logical = (bid & 7) * per_xcd + (bid >> 3);
     if (logical >= nlogical) return;
     const int mt = (int)(logical % nmt);
@@ -1309,7 +1310,7 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
             const int ch = tid + NT * c, arow = ch >> 2, akq = ch & 3;
             const long ao = (long)(mt * 128 + arow) * Kp + kt * BK + akq * 8;
             rah[c] = *reinterpret_cast<const u16x8 *>(Ahi + ao);
-            ral[c] = *reinterpret_cast<const u16x8 *>(Alo + ao);
+            if constexpr (ALO) ral[c] = *reinterpret_cast<const u16x8 *>(Alo + ao);
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -1328,7 +1329,7 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
         for (int c = 0; c < NA_CH; ++c) {
             const int ch = tid + NT * c, arow = ch >> 2, akq = ch & 3;
             *reinterpret_cast<u16x8 *>(&sAh[arow * LD + akq * 8]) = rah[c];
-            *reinterpret_cast<u16x8 *>(&sAl[arow * LD + akq * 8]) = ral[c];
+            if constexpr (ALO) *reinterpret_cast<u16x8 *>(&sAl[arow * LD + akq * 8]) = ral[c];
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -1349,7 +1350,8 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
             for (int i = 0; i < 2; ++i) {
                 const int r = wm * 64 + i * 32 + (lane & 31);
                 ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAh[r * LD + ko]));
-                al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAl[r * LD + ko]));
+                if constexpr (ALO)
+                    al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAl[r * LD + ko]));
             }
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -1362,7 +1364,8 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    if constexpr (ALO)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
                     if constexpr (BLO)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
@@ -1406,7 +1409,8 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
     constexpr int NCH = 128 * (BK / 8) / 256;    // A chunks of 8 nodes per thread
     constexpr int NT = 256;
     constexpr bool BLO = NPROD == 3;
-    __shared__ unsigned short sAh[128 * LD], sAl[128 * LD];
+    constexpr bool ALO = NPROD >= 2;
+    __shared__ unsigned short sAh[128 * LD], sAl[ALO ? 128 * LD : 8];
     const long logical = (bid & 7) * per_xcd + (bid >> 3);
     if (logical >= nlogical) return;
     const int mt = (int)(logical % nmt);
@@ -1461,7 +1465,7 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
             const int ch = tid + NT * c, arow = ch / (BK / 8), akq = ch % (BK / 8);
             const long ao = (long)(mt * 128 + arow) * Kp + kt * BK + akq * 8;
             rah[c] = *reinterpret_cast<const u16x8 *>(Ahi + ao);
-            ral[c] = *reinterpret_cast<const u16x8 *>(Alo + ao);
+            if constexpr (ALO) ral[c] = *reinterpret_cast<const u16x8 *>(Alo + ao);
         }
     };
     auto astore = [&]() {
@@ -1469,7 +1473,7 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
         for (int c = 0; c < NCH; ++c) {
             const int ch = tid + NT * c, arow = ch / (BK / 8), akq = ch % (BK / 8);
             *reinterpret_cast<u16x8 *>(&sAh[arow * LD + akq * 8]) = rah[c];
-            *reinterpret_cast<u16x8 *>(&sAl[arow * LD + akq * 8]) = ral[c];
+            if constexpr (ALO) *reinterpret_cast<u16x8 *>(&sAl[arow * LD + akq * 8]) = ral[c];
         }
     };
     u16x8 b0h[4], b0l[4], b1h[4], b1l[4];
@@ -1494,14 +1498,16 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
             for (int i = 0; i < 2; ++i) {
                 const int r = wm * 64 + i * 32 + (lane & 31);
                 ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAh[r * LD + ko]));
-                al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAl[r * LD + ko]));
+                if constexpr (ALO)
+                    al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAl[r * LD + ko]));
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const bf16x8 bh = __builtin_bit_cast(bf16x8, cbh[j]);
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+                    if constexpr (ALO)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh, acc[i][j], 0, 0, 0);
                     if constexpr (BLO)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], __builtin_bit_cast(bf16x8, cbl[j]),
                                                                              acc[i][j], 0, 0, 0);
@@ -1556,21 +1562,22 @@ hipError_t launch_qgemm_bf16s(const QParams<float> &P, const unsigned short *Ahi
         const int nmt2 = P.Mp / 128, nnt2 = (P.NPB + 7) / 8;
         const long nlog2 = (long)P.ns * P.G * nnt2 * nmt2;
         const long per2 = (nlog2 + 7) / 8;
+        const dim3 g2((unsigned)(per2 * 8));
         if (nprod == 3)
-            hipLaunchKernelGGL(qgemm_bf16g_kernel<3>, dim3((unsigned)(per2 * 8)), dim3(256), 0, st, P, Ahi, Alo, Kp,
-                               nmt2, nnt2, nlog2, per2);
+            hipLaunchKernelGGL(qgemm_bf16g_kernel<3>, g2, dim3(256), 0, st, P, Ahi, Alo, Kp, nmt2, nnt2, nlog2, per2);
+        else if (nprod == 2)
+            hipLaunchKernelGGL(qgemm_bf16g_kernel<2>, g2, dim3(256), 0, st, P, Ahi, Alo, Kp, nmt2, nnt2, nlog2, per2);
         else
-            hipLaunchKernelGGL(qgemm_bf16g_kernel<2>, dim3((unsigned)(per2 * 8)), dim3(256), 0, st, P, Ahi, Alo, Kp,
-                               nmt2, nnt2, nlog2, per2);
+            hipLaunchKernelGGL(qgemm_bf16g_kernel<1>, g2, dim3(256), 0, st, P, Ahi, Alo, Kp, nmt2, nnt2, nlog2, per2);
         return hipGetLastError();
     }
     const dim3 grid((unsigned)(per * 8));
 #define PBS_QG(BN_, NP_) \
     hipLaunchKernelGGL((qgemm_bf16s_kernel<BN_, NP_>), grid, dim3(2 * BN_), 0, st, P, Ahi, Alo, Kp, nmt, nnt, nlog, per)
     if (bn == 128) {
-        if (nprod == 3) PBS_QG(128, 3); else PBS_QG(128, 2);
+        if (nprod == 3) PBS_QG(128, 3); else if (nprod == 2) PBS_QG(128, 2); else PBS_QG(128, 1);
     } else {
-        if (nprod == 3) PBS_QG(256, 3); else PBS_QG(256, 2);
+        if (nprod == 3) PBS_QG(256, 3); else if (nprod == 2) PBS_QG(256, 2); else PBS_QG(256, 1);
     }
 #undef PBS_QG
     return hipGetLastError();
@@ -1992,11 +1999,11 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
 #define PBS_QB(BN_, NP_) hipLaunchKernelGGL((qgemm_batched_kernel<BN_, NP_>), grid, dim3(2 * BN_), 0, st, beams, Sh, s)
 #define PBS_QG(NP_) hipLaunchKernelGGL((qgemm_batched_kernel<0, NP_>), grid, dim3(256), 0, st, beams, Sh, s)
             if (kind == QGEMM_GLOBAL_B) {
-                if (Sh.nprod == 3) PBS_QG(3); else PBS_QG(2);
+                if (Sh.nprod == 3) PBS_QG(3); else if (Sh.nprod == 2) PBS_QG(2); else PBS_QG(1);
             } else if (bn == 128) {
-                if (Sh.nprod == 3) PBS_QB(128, 3); else PBS_QB(128, 2);
+                if (Sh.nprod == 3) PBS_QB(128, 3); else if (Sh.nprod == 2) PBS_QB(128, 2); else PBS_QB(128, 1);
             } else {
-                if (Sh.nprod == 3) PBS_QB(256, 3); else PBS_QB(256, 2);
+                if (Sh.nprod == 3) PBS_QB(256, 3); else if (Sh.nprod == 2) PBS_QB(256, 2); else PBS_QB(256, 1);
             }
 #undef PBS_QB
 #undef PBS_QG

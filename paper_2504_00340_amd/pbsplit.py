@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpbsplit.so")
 PBS_OK, PBS_EINVAL, PBS_ESTATE, PBS_ENOMEM, PBS_EDEVICE, PBS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PBS_FP32, PBS_FP64 = 0, 1
 PBS_OP_E, PBS_OP_T, PBS_OP_A = 1, 2, 3
-PBS_SRC_FP32, PBS_SRC_BF16X3, PBS_SRC_BF16X2 = 0, 1, 2
+PBS_SRC_FP32, PBS_SRC_BF16X3, PBS_SRC_BF16X2, PBS_SRC_BF16X1 = 0, 1, 2, 3
 _NAMES = {0: "PBS_OK", -1: "PBS_EINVAL", -2: "PBS_ESTATE", -3: "PBS_ENOMEM", -4: "PBS_EDEVICE",
           -5: "PBS_EUNSUPPORTED"}
 
