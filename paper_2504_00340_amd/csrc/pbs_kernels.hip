@@ -1394,12 +1394,31 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
 // Source product with the energy-scanned fluence read straight from global memory: its split
 // layout [g][pb][oct][cell][8] is the register layout of the v_mfma_f32_32x32x16_bf16 B operand
 // (lane l: cell l % 32, source nodes 8 (2 kk + l / 32) + 0..7 of the 16-node step kk), so one 16-byte
-// load per lane fetches a whole fragment, 1 KB contiguous per wave.  Only the transfer-matrix tile
-// (128 destination rows x 64 source nodes, hi and lo) is staged in LDS and shared by the 4 waves; the
-// next 16-node step's B fragments are loaded while the current one computes.
-// Block = 128 rows x 256 cells (8 lateral tiles); wave (wm, wn) owns 64 rows x 128 cells as 2 x 4
-// tiles of 32 x 32.
-template <int NPROD>
+// buffer load per lane fetches a whole fragment, 1 KB contiguous per wave.  Only the transfer-matrix
+// tile (128 destination rows x 64 source nodes, hi and lo) is staged in LDS and shared by the 4 waves.
+// Block = 128 rows x 256 cells (8 lateral tiles of 32 cells).  With QG_WM = 1 each wave owns all 128
+// rows of 2 lateral tiles (4 x 2 tiles of 32 x 32), so every B fragment is fetched by one wave only;
+// with QG_WM = 2 a wave owns 64 rows x 4 lateral tiles.  B fragments of the next QG_PFD 16-node steps
+// are in flight while a step computes.
+// Tuning knobs (compile-time): B prefetch depth in 16-node steps (single-beam and batched kernels),
+// minimum waves per SIMD for the one-product kernels, waves along rows, and non-temporal stores of
+// the source (it is read once, by the next generation's energy pass).
+#ifndef QG_PFD
+#define QG_PFD 3
+#endif
+#ifndef QG_PFD_BATCH
+#define QG_PFD_BATCH 1
+#endif
+#ifndef QG_WPE
+#define QG_WPE 2
+#endif
+#ifndef QG_WM
+#define QG_WM 1
+#endif
+#ifndef QG_NT
+#define QG_NT 1
+#endif
+template <int NPROD, int PFD_ = QG_PFD>
 __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const unsigned short *__restrict__ Ahi,
                                                  const unsigned short *__restrict__ Alo, int Kp, int nmt, int nnt,
                                                  long nlogical, long per_xcd, long bid)
@@ -1410,6 +1429,8 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
     constexpr int NT = 256;
     constexpr bool BLO = NPROD == 3;
     constexpr bool ALO = NPROD >= 2;
+    constexpr int WM = QG_WM, WN = 4 / WM;       // waves along rows / along lateral tiles
+    constexpr int TI = 4 / WM, TJ = 8 / WN;      // 32-row tiles and lateral tiles per wave
     __shared__ unsigned short sAh[128 * LD], sAl[ALO ? 128 * LD : 8];
     const long logical = (bid & 7) * per_xcd + (bid >> 3);
     if (logical >= nlogical) return;
@@ -1422,42 +1443,38 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
     float *__restrict__ C = P.Q + off;
     const long NAPT = (long)P.NA * PBS_PT;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int wm = wid >> 1, wn = wid & 1;
-    floatx16 acc[2][4];
+    const int wm = wid / WN, wn = wid % WN;
+    floatx16 acc[TI][TJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < TJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
     const int nk = Kp / BK;
-    // B fragments: tile j of this wave is lateral tile pb_j = nt*8 + wn*4 + j
-    const unsigned short *bph[4], *bpl[4];
-    bool bok[4];
+    // B fragments through buffer loads on the (s, g) slab of the split fluence: tile j of this wave
+    // is lateral tile nt*8 + wn*TJ + j, and this lane's octet at 16-node step kk is 2 kk + lane / 32.
+    // An octet past the last one of a tile reads the next tile (finite values that meet the zero
+    // columns of the padded transfer matrix); anything past the slab, including lateral tiles past
+    // the last one (never stored), reads zero through the buffer range check.  No lane branches, so
+    // the waits before the products count exactly the loads in flight.
+    const long slab = ((long)s * P.G + g) * P.NPB * P.NOCT * (PBS_PT * 8);
+    const int tile_bytes = P.NOCT * (PBS_PT * 8) * 2;
+    const int slab_bytes = P.NPB * tile_bytes;
+    const __amdgpu_buffer_rsrc_t rbh =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(P.Bh + slab), (short)0, slab_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rbl =
+        __builtin_amdgcn_make_buffer_rsrc((void *)((BLO ? P.Bl : P.Bh) + slab), (short)0, slab_bytes, 0x00020000);
+    const int vb = (nt * 8 + wn * TJ) * tile_bytes + (lane & 31) * 16 + (lane >> 5) * (PBS_PT * 8 * 2);
+    auto bload = [&](int kk, u16x8 (&bh)[TJ], u16x8 (&bl)[TJ]) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int pb = nt * 8 + wn * 4 + j;
-        bok[j] = pb < P.NPB;
-        const long base = (((long)s * P.G + g) * P.NPB + (bok[j] ? pb : 0)) * P.NOCT * (PBS_PT * 8) +
-                          (lane & 31) * 8 + (long)(lane >> 5) * (PBS_PT * 8);
-        bph[j] = P.Bh + base;
-        bpl[j] = BLO ? P.Bl + base : nullptr;
-    }
-    // octet of this lane's half at 16-node step kk: 2 kk + lane / 32
-    auto bload = [&](int kk, u16x8 (&bh)[4], u16x8 (&bl)[4]) {
-        const int oc = 2 * kk + (lane >> 5);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (bok[j] && oc < P.NOCT) {
-                bh[j] = *reinterpret_cast<const u16x8 *>(bph[j] + (long)2 * kk * (PBS_PT * 8));
-                if constexpr (BLO) bl[j] = *reinterpret_cast<const u16x8 *>(bpl[j] + (long)2 * kk * (PBS_PT * 8));
-            } else {
-                bh[j] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-                if constexpr (BLO) bl[j] = bh[j];
-            }
+        for (int j = 0; j < TJ; ++j) {
+            const int o = vb + j * tile_bytes + kk * (2 * PBS_PT * 8 * 2);
+            bh[j] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rbh, o, 0, 0));
+            if constexpr (BLO) bl[j] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(rbl, o, 0, 0));
         }
     };
-    // A staging: 128 rows x 4 chunks of 8 source nodes, hi and lo, 2 chunks per thread
+    // A staging: 128 rows x 8 chunks of 8 source nodes, hi and lo, 4 chunks per thread
     u16x8 rah[NCH], ral[NCH];
     auto aload = [&](int kt) {
 #pragma unroll
@@ -1476,36 +1493,41 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
             if constexpr (ALO) *reinterpret_cast<u16x8 *>(&sAl[arow * LD + akq * 8]) = ral[c];
         }
     };
-    u16x8 b0h[4], b0l[4], b1h[4], b1l[4];
+    // ring of B fragments: step kk lives in slot kk % NR; steps kk + 1 .. kk + PFD are in flight.
+    // Every load is unconditional (past the end they re-read the last stage or step).
+    constexpr int PFD = NPROD == 1 ? PFD_ : 1;
+    constexpr int NR = PFD == 1 ? 2 : KS;
+    static_assert(PFD < NR && KS % NR == 0, "B ring");
+    u16x8 bbh[NR][TJ], bbl[NR][TJ];
     aload(0);
     astore();
-    bload(0, b0h, b0l);
+#pragma unroll
+    for (int d = 0; d < PFD; ++d) bload(min(d, KS * nk - 1), bbh[d], bbl[d]);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
-        if (kt + 1 < nk) aload(kt + 1);
+        aload(min(kt + 1, nk - 1));
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int kk = KS * kt + ks;
-            // prefetch the next step's B fragments while this step computes
-            u16x8(&cbh)[4] = (ks & 1) == 0 ? b0h : b1h;
-            u16x8(&cbl)[4] = (ks & 1) == 0 ? b0l : b1l;
-            u16x8(&nbh)[4] = (ks & 1) == 0 ? b1h : b0h;
-            u16x8(&nbl)[4] = (ks & 1) == 0 ? b1l : b0l;
-            if (kk + 1 < KS * nk) bload(kk + 1, nbh, nbl);
+            bload(min(kk + PFD, KS * nk - 1), bbh[(ks + PFD) % NR], bbl[(ks + PFD) % NR]);
+            // keep the prefetch ahead of this step's products (the scheduler would sink it to its use)
+            __builtin_amdgcn_sched_barrier(0);
+            u16x8(&cbh)[TJ] = bbh[ks % NR];
+            u16x8(&cbl)[TJ] = bbl[ks % NR];
             const int ko = ks * 16 + 8 * (lane >> 5);
-            bf16x8 ah[2], al[2];
+            bf16x8 ah[TI], al[TI];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int r = wm * 64 + i * 32 + (lane & 31);
+            for (int i = 0; i < TI; ++i) {
+                const int r = wm * (32 * TI) + i * 32 + (lane & 31);
                 ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAh[r * LD + ko]));
                 if constexpr (ALO)
                     al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAl[r * LD + ko]));
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < TJ; ++j) {
                 const bf16x8 bh = __builtin_bit_cast(bf16x8, cbh[j]);
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
+                for (int i = 0; i < TI; ++i) {
                     if constexpr (ALO)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh, acc[i][j], 0, 0, 0);
                     if constexpr (BLO)
@@ -1522,21 +1544,25 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
         }
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int pb = nt * 8 + wn * 4 + j;
+        for (int j = 0; j < TJ; ++j) {
+            const int pb = nt * 8 + wn * TJ + j;
             if (pb >= P.NPB) continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int row = mt * 128 + wm * 64 + i * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+                const int row = mt * 128 + wm * (32 * TI) + i * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+#if QG_NT
+                if (row < P.NA) __builtin_nontemporal_store(acc[i][j][r], &C[pb * NAPT + (long)row * PBS_PT + (lane & 31)]);
+#else
                 if (row < P.NA) C[pb * NAPT + (long)row * PBS_PT + (lane & 31)] = acc[i][j][r];
+#endif
             }
         }
 }
 
 template <int NPROD>
-__global__ __launch_bounds__(256) void qgemm_bf16g_kernel(QParams<float> P, const unsigned short *__restrict__ Ahi,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NPROD <= 2 ? QG_WPE : 1))) void qgemm_bf16g_kernel(QParams<float> P, const unsigned short *__restrict__ Ahi,
                                                           const unsigned short *__restrict__ Alo, int Kp, int nmt,
                                                           int nnt, long nlogical, long per_xcd)
 {
@@ -1851,8 +1877,9 @@ __global__ __launch_bounds__(256) void epass_batched_kernel(const BeamDev *__res
 
 // BN = 128 / 256: LDS-staged kernel with BN-column blocks; BN = 0: global-B kernel (256 columns)
 template <int BN, int NPROD>
-__global__ __launch_bounds__(BN == 0 ? 256 : 2 * BN) void qgemm_batched_kernel(const BeamDev *__restrict__ beams,
-                                                                               BatchShape Sh, int s)
+__global__ __launch_bounds__(BN == 0 ? 256 : 2 * BN)
+__attribute__((amdgpu_waves_per_eu(BN == 0 && NPROD == 1 ? QG_WPE : 1))) void qgemm_batched_kernel(
+    const BeamDev *__restrict__ beams, BatchShape Sh, int s)
 {
     const BeamDev &B = beams[blockIdx.y];
     const int mode = beam_mode(s, B.nz);
@@ -1879,7 +1906,7 @@ __global__ __launch_bounds__(BN == 0 ? 256 : 2 * BN) void qgemm_batched_kernel(c
     const long per = (nlog + 7) / 8;
     if ((long)blockIdx.x >= per * 8) return;
     if constexpr (BN == 0)
-        qgemm_bf16g_body<NPROD>(P, Sh.Ahi, Sh.Alo, Sh.Kpb, nmt, nnt, nlog, per, blockIdx.x);
+        qgemm_bf16g_body<NPROD, QG_PFD_BATCH>(P, Sh.Ahi, Sh.Alo, Sh.Kpb, nmt, nnt, nlog, per, blockIdx.x);
     else
         qgemm_bf16s_body<BN, NPROD>(P, Sh.Ahi, Sh.Alo, Sh.Kpb, nmt, nnt, nlog, per, blockIdx.x);
 }
