@@ -170,7 +170,8 @@ hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st)
 // one partial per (cell, line group), stored at line slot a = line group; the dose reduction then
 // sums NOCT * 8 / PBS_EPASS_LPT slots per cell instead of NA.  Lanes 0-31 hold the 32 cells of one
 // tile.
-template <int MODE>
+// FEAT / LO = false compile out the surrogate records and the lo half of the split scans.
+template <int MODE, bool FEAT = true, bool LO = true>
 __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
 {
     constexpr int L = PBS_EPASS_LPT;
@@ -199,7 +200,8 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
     for (int e = 0; e < L; ++e) fin[e] = fcl[e] = fop[e] = U0[e] = U1[e] = U2[e] = 0.f;
     double ph0 = 0, ph1 = 0, ph2 = 0, injc = 0, injo = 0;
     float fic = 0, fio = 0, fme = 0, fmn = 0;
-    const bool hasQ = P.Q != nullptr, hasW = P.Wh != nullptr, hasL = P.Wl != nullptr, feat = P.inj_c != nullptr;
+    const bool hasQ = P.Q != nullptr, hasW = P.Wh != nullptr, hasL = LO && P.Wl != nullptr,
+               feat = FEAT && P.inj_c != nullptr;
     const long SB = (long)P.G * NPB * P.NOCT * (PBS_PT * 8);
     for (int g = P.G - 1; g >= 0; --g) {
         const float sm = P.Sm[g], sp = P.Sp[g], kp = P.kap[g];
@@ -271,8 +273,10 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
                 const __bf16 bc = (__bf16)vc, bo = (__bf16)vo;
                 hc[e] = __builtin_bit_cast(unsigned short, bc);
                 ho[e] = __builtin_bit_cast(unsigned short, bo);
-                lc[e] = __builtin_bit_cast(unsigned short, (__bf16)(vc - (float)bc));
-                lo[e] = __builtin_bit_cast(unsigned short, (__bf16)(vo - (float)bo));
+                if constexpr (LO) {
+                    lc[e] = __builtin_bit_cast(unsigned short, (__bf16)(vc - (float)bc));
+                    lo[e] = __builtin_bit_cast(unsigned short, (__bf16)(vo - (float)bo));
+                }
                 if (feat) {
                     const float wi = (float)P.dInj[g];
                     if (CL) fic += wi * vc;
@@ -306,9 +310,11 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
             const long ob = (((long)g * NPB + pbk) * P.NOCT + oct) * (PBS_PT * 8) + pt * 8 + L * sub;
             if (CL) *reinterpret_cast<chunk_t *>(P.Wh + ob) = hc;
             if (OP) *reinterpret_cast<chunk_t *>(P.Wh + SB + ob) = ho;
-            if (hasL) {
-                if (CL) *reinterpret_cast<chunk_t *>(P.Wl + ob) = lc;
-                if (OP) *reinterpret_cast<chunk_t *>(P.Wl + SB + ob) = lo;
+            if constexpr (LO) {
+                if (hasL) {
+                    if (CL) *reinterpret_cast<chunk_t *>(P.Wl + ob) = lc;
+                    if (OP) *reinterpret_cast<chunk_t *>(P.Wl + SB + ob) = lo;
+                }
             }
         }
     }
@@ -325,22 +331,35 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
     }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void epass8_kernel(EParams<float> P)
+// 5 waves per SIMD for the plain kernels (96 VGPRs, a few spilled registers): measured faster than 4
+// waves without spills
+template <int MODE, bool FEAT, bool LO>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT ? 1 : 5))) void epass8_kernel(EParams<float> P)
 {
-    epass8_body<MODE>(P, (long)blockIdx.x * 256 + threadIdx.x);
+    epass8_body<MODE, FEAT, LO>(P, (long)blockIdx.x * 256 + threadIdx.x);
+}
+
+template <bool FEAT, bool LO>
+static void launch_epass8_t(const EParams<float> &P, int mode, unsigned nb, hipStream_t st)
+{
+    if (mode == MODE_PAIR)
+        hipLaunchKernelGGL((epass8_kernel<MODE_PAIR, FEAT, LO>), dim3(nb), dim3(256), 0, st, P);
+    else if (mode == MODE_OPEN)
+        hipLaunchKernelGGL((epass8_kernel<MODE_OPEN, FEAT, LO>), dim3(nb), dim3(256), 0, st, P);
+    else
+        hipLaunchKernelGGL((epass8_kernel<MODE_CLOSE, FEAT, LO>), dim3(nb), dim3(256), 0, st, P);
 }
 
 hipError_t launch_epass8(const EParams<float> &P, int mode, hipStream_t st)
 {
     const long nthreads = (P.NLINE / P.NAPT) * P.NOCT * (8 / PBS_EPASS_LPT) * PBS_PT;
     const unsigned nb = (unsigned)((nthreads + 255) / 256);
-    if (mode == MODE_PAIR)
-        hipLaunchKernelGGL(epass8_kernel<MODE_PAIR>, dim3(nb), dim3(256), 0, st, P);
-    else if (mode == MODE_OPEN)
-        hipLaunchKernelGGL(epass8_kernel<MODE_OPEN>, dim3(nb), dim3(256), 0, st, P);
+    if (P.inj_c != nullptr)
+        launch_epass8_t<true, true>(P, mode, nb, st);
+    else if (P.Wl != nullptr)
+        launch_epass8_t<false, true>(P, mode, nb, st);
     else
-        hipLaunchKernelGGL(epass8_kernel<MODE_CLOSE>, dim3(nb), dim3(256), 0, st, P);
+        launch_epass8_t<false, false>(P, mode, nb, st);
     return hipGetLastError();
 }
 
@@ -1868,11 +1887,11 @@ __global__ __launch_bounds__(256) void epass_batched_kernel(const BeamDev *__res
     P.NAPT = (long)Sh.NA * PBS_PT;
     const long gid = (long)blockIdx.x * 256 + threadIdx.x;
     if (mode == MODE_PAIR)
-        epass8_body<MODE_PAIR>(P, gid);
+        epass8_body<MODE_PAIR, false>(P, gid);
     else if (mode == MODE_OPEN)
-        epass8_body<MODE_OPEN>(P, gid);
+        epass8_body<MODE_OPEN, false>(P, gid);
     else
-        epass8_body<MODE_CLOSE>(P, gid);
+        epass8_body<MODE_CLOSE, false>(P, gid);
 }
 
 // BN = 128 / 256: LDS-staged kernel with BN-column blocks; BN = 0: global-B kernel (256 columns)
