@@ -1339,7 +1339,7 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
                 if constexpr (BLO) rbl[h] = *reinterpret_cast<const u16x8 *>(P.Bl + bbase + (long)oc * (PBS_PT * 8));
             } else {
                 rbh[h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-                rbl[h] = rbh[h];
+                if constexpr (BLO) rbl[h] = rbh[h];
             }
         }
     };
