@@ -49,7 +49,7 @@ def algorithmic(grid, tsz=4):
 
 
 KIND_KERNEL = {"tpass": "tpass_affine_kernel<64>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16g_kernel<1>",
-               "epass": "epass8_kernel<3>"}
+               "epass": "epass8_kernel<3, false, false>"}
 
 
 def measured_traffic(kind):
