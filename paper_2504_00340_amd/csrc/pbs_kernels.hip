@@ -1596,9 +1596,17 @@ __global__ __launch_bounds__(2 * BN) void qgemm_bf16s_kernel(QParams<float> P, c
     qgemm_bf16s_body<BN, NPROD>(P, Ahi, Alo, Kp, nmt, nnt, nlogical, per_xcd, blockIdx.x);
 }
 
+// The global-B kernel addresses a (half, g) slab of the split scans with 32-bit buffer offsets; larger
+// slabs take the LDS-staged kernel (bitwise the same products: the same accumulation order per output).
+static inline bool qgemm_global_b_fits(long NPB, int NOCT)
+{
+    return (NPB + 9) * NOCT * (long)(PBS_PT * 8 * 2) < (1L << 31);   // tiles up to a block past the end
+}
+
 hipError_t launch_qgemm_bf16s(const QParams<float> &P, const unsigned short *Ahi, const unsigned short *Alo, int Kp,
                               int nprod, hipStream_t st, int kind)
 {
+    if (kind == QGEMM_GLOBAL_B && !qgemm_global_b_fits(P.NPB, P.NOCT)) kind = QGEMM_LDS_256;
     const int bn = kind == QGEMM_LDS_128 ? 128 : 256;
     const int nmt = P.Mp / 128, nnt = (P.NPB + bn / 32 - 1) / (bn / 32);
     const long nlog = (long)P.ns * P.G * nnt * nmt;
@@ -2037,7 +2045,8 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
         const unsigned nbe = (unsigned)(((long)Sh.NPB * Sh.NOCT * (8 / PBS_EPASS_LPT) * PBS_PT + 255) / 256);
         hipLaunchKernelGGL(epass_batched_kernel, dim3(nbe, nbeam), dim3(256), 0, st, beams, Sh, k, s);
         if (k + 1 < Sh.ngen) {
-            const int kind = tu.gemm_kind;
+            const int kind = tu.gemm_kind == QGEMM_GLOBAL_B && !qgemm_global_b_fits(Sh.NPB, Sh.NOCT) ? QGEMM_LDS_256
+                                                                                                  : tu.gemm_kind;
             const int bn = kind == QGEMM_LDS_128 ? 128 : 256;
             const int nmt = Sh.Mp / 128, nnt = (Sh.NPB + bn / 32 - 1) / (bn / 32);
             const long per = ((long)2 * maxG * nnt * nmt + 7) / 8;
