@@ -11,6 +11,15 @@
 #include "pbs_common.h"
 #include "pbs_ctx.h"
 #include "pbs_net_internal.h"
+
+// The depth march runs on two streams (a generation's T A T beside the energy chain) when one
+// generation holds fewer phase-space cells than this: such kernels leave most of the GPU idle (a 32 x 32
+// beam with 15 x 15 angles and 128 groups: +11 % beams/s), while at config-2 size every kernel already
+// saturates HBM and the concurrent ones mostly slow each other (1 % per step gained, every kernel 1.4-2.6x
+// longer), so there the sub-steps stay in order on one stream and each kernel's own rate stays measurable.
+#ifndef PBS_OVERLAP_CELLS
+#define PBS_OVERLAP_CELLS 100000000L
+#endif
 #include "pbsplit.h"
 
 using namespace pbs;
@@ -389,9 +398,10 @@ pbs_status upload_tables(pbs_ctx *c)
 struct ProfScope {
     pbs_ctx *c;
     int kind;
+    hipStream_t st;
     size_t i0 = 0;
     bool on = false;
-    ProfScope(pbs_ctx *c_, int k) : c(c_), kind(k)
+    ProfScope(pbs_ctx *c_, int k, hipStream_t st_ = nullptr) : c(c_), kind(k), st(st_ ? st_ : c_->stream)
     {
         if (!c->prof) return;
         while (c->ev_pool.size() < c->ev_used + 2) {
@@ -401,12 +411,12 @@ struct ProfScope {
         }
         i0 = c->ev_used;
         c->ev_used += 2;
-        on = hipEventRecord(c->ev_pool[i0], c->stream) == hipSuccess;
+        on = hipEventRecord(c->ev_pool[i0], st) == hipSuccess;
     }
     ~ProfScope()
     {
         if (!on) return;
-        if (hipEventRecord(c->ev_pool[i0 + 1], c->stream) == hipSuccess) c->ev_pairs.push_back({kind, i0});
+        if (hipEventRecord(c->ev_pool[i0 + 1], st) == hipSuccess) c->ev_pairs.push_back({kind, i0});
     }
 };
 
@@ -455,10 +465,22 @@ EParams<T> eparams(pbs_ctx *c, int k, int lay_c, int lay_o, double h)
     return P;
 }
 
+// Transport and angular sub-steps over all generations (k < 0) or generation k alone, on the context's
+// stream or on st.
+template <typename T>
+pbs_status transport(pbs_ctx *c, double h, int k = -1, hipStream_t st = nullptr);
+template <typename T>
+pbs_status angular(pbs_ctx *c, int layer, double h, int k = -1, hipStream_t st = nullptr);
+
 // Energy half-step(s) for all generations in order.  mode: close the layer lay_c (state 0 -> 1),
 // open the layer lay_o (state 1 -> 2), or both in one sweep.  Deposits go to the FP64 dose.
+//
+// With tat_layer >= 0 (a depth step), generation k's T(h) A(2h) T(h) is issued on the side stream as soon
+// as its energy pass is done: it touches only that generation's fluence, while the main stream goes on
+// with k's source product and the later generations' energy passes.  A generation's next energy pass
+// waits for its pending T A T; the march joins the side stream back at its end (join_side).
 template <typename T>
-pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
+pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h, int tat_layer = -1)
 {
     const int K1 = c->kact;
     // FP32 with the split-BF16 product: octet-per-thread E-pass, deposits summed per octet
@@ -467,6 +489,10 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
     const int nslot = e8 ? epass8_slots(c->NOCT) : c->NA;
     for (int k = 0; k < K1; ++k) {
         EParams<T> P = eparams<T>(c, k, (mode & MODE_CLOSE) ? lay_c : -1, (mode & MODE_OPEN) ? lay_o : -1, h);
+        if (c->tat_pend[k]) {
+            HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_tat[k], 0));
+            c->tat_pend[k] = false;
+        }
         {
             ProfScope ps(c, PBS_K_EPASS);
             if constexpr (sizeof(T) == 4) {
@@ -478,6 +504,16 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
             } else {
                 HIPCHK(c, launch_epass<T>(P, mode, c->stream));
             }
+        }
+        if (tat_layer >= 0) {
+            HIPCHK(c, hipEventRecord(c->ev_e[k], c->stream));
+            HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_e[k], 0));
+            pbs_status r;
+            if ((r = transport<T>(c, h, k, c->side)) != PBS_OK) return r;
+            if ((r = angular<T>(c, tat_layer, 2 * h, k, c->side)) != PBS_OK) return r;
+            if ((r = transport<T>(c, h, k, c->side)) != PBS_OK) return r;
+            HIPCHK(c, hipEventRecord(c->ev_tat[k], c->side));
+            c->tat_pend[k] = true;
         }
         if (k + 1 < K1) {
             QParams<T> Q;
@@ -536,10 +572,10 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h)
 }
 
 template <typename T>
-pbs_status transport(pbs_ctx *c, double h)
+pbs_status transport(pbs_ctx *c, double h, int k, hipStream_t st)
 {
     TParams<T> P;
-    P.psi = c->psi<T>(0);
+    P.psi = c->psi<T>(k < 0 ? 0 : k);
     P.theta = c->tabT<T>() + c->t_theta;
     P.h_half_over_dx = (T)(0.5 * h / c->dx);
     P.h_half_over_dy = (T)(0.5 * h / c->dy);
@@ -548,18 +584,21 @@ pbs_status transport(pbs_ctx *c, double h)
     P.m = c->m;
     P.NA = c->NA;
     P.NLINE = c->NLINE;
-    P.nplanes = (long)c->kact * c->G() * 2 * c->NA;
-    ProfScope ps(c, PBS_K_TPASS);
-    HIPCHK(c, launch_tpass<T>(P, c->stream));
+    P.nplanes = (long)(k < 0 ? c->kact : 1) * c->G() * 2 * c->NA;
+    if (!st) st = c->stream;
+    ProfScope ps(c, PBS_K_TPASS, st);
+    HIPCHK(c, launch_tpass<T>(P, st));
     return PBS_OK;
 }
 
 template <typename T>
-pbs_status angular(pbs_ctx *c, int layer, double h)
+pbs_status angular(pbs_ctx *c, int layer, double h, int k, hipStream_t st)
 {
     AParams<T> P;
     T *tb = c->tabT<T>();
-    P.psi = c->psi<T>(0);
+    P.psi = c->psi<T>(k < 0 ? 0 : k);
+    const long nstack = (long)(k < 0 ? c->kact : 1) * c->G() * 2;
+    if (!st) st = c->stream;
     P.rho = c->rhoT<T>(layer);
     P.sig = tb + c->t_sig;
     P.S = tb + c->t_S;
@@ -569,18 +608,29 @@ pbs_status angular(pbs_ctx *c, int layer, double h)
     P.NA = c->NA;
     P.NPB = c->NPB;
     P.NLINE = c->NLINE;
-    ProfScope ps(c, PBS_K_APASS);
+    ProfScope ps(c, PBS_K_APASS, st);
     if constexpr (sizeof(T) == 4) {
         if (c->g.nth == 32) {
-            HIPCHK(c, launch_apass_mfma32(P, tb + c->t_K32, (long)c->kact * c->G() * 2, c->stream));
+            HIPCHK(c, launch_apass_mfma32(P, tb + c->t_K32, nstack, st));
             return PBS_OK;
         }
         if (c->g.nth == 16) {
-            HIPCHK(c, launch_apass_mfma16(P, tb + c->t_K32, (long)c->kact * c->G() * 2, c->stream));
+            HIPCHK(c, launch_apass_mfma16(P, tb + c->t_K32, nstack, st));
             return PBS_OK;
         }
     }
-    HIPCHK(c, launch_apass<T>(P, c->g.nth, (long)c->kact * c->G() * 2, c->stream));
+    HIPCHK(c, launch_apass<T>(P, c->g.nth, nstack, st));
+    return PBS_OK;
+}
+
+// the main stream waits for every generation's pending T A T
+static pbs_status join_side(pbs_ctx *c)
+{
+    for (int k = 0; k < (int)c->tat_pend.size(); ++k)
+        if (c->tat_pend[k]) {
+            HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_tat[k], 0));
+            c->tat_pend[k] = false;
+        }
     return PBS_OK;
 }
 
@@ -589,12 +639,16 @@ pbs_status one_step(pbs_ctx *c)
 {
     const int s = c->step;
     const double dz = c->g.dz;
-    pbs_status r = (s == 0) ? energy_chain<T>(c, MODE_OPEN, -1, 0, 0.5 * dz)
-                            : energy_chain<T>(c, MODE_PAIR, s - 1, s, 0.5 * dz);
+    const bool ovl = (long)c->NP * c->NA * c->G() < PBS_OVERLAP_CELLS;
+    const int tat = ovl ? s : -1;
+    pbs_status r = (s == 0) ? energy_chain<T>(c, MODE_OPEN, -1, 0, 0.5 * dz, tat)
+                            : energy_chain<T>(c, MODE_PAIR, s - 1, s, 0.5 * dz, tat);
     if (r != PBS_OK) return r;
-    if ((r = transport<T>(c, 0.5 * dz)) != PBS_OK) return r;
-    if ((r = angular<T>(c, s, dz)) != PBS_OK) return r;
-    if ((r = transport<T>(c, 0.5 * dz)) != PBS_OK) return r;
+    if (!ovl) {
+        if ((r = transport<T>(c, 0.5 * dz)) != PBS_OK) return r;
+        if ((r = angular<T>(c, s, dz)) != PBS_OK) return r;
+        if ((r = transport<T>(c, 0.5 * dz)) != PBS_OK) return r;
+    }
     c->step = s + 1;
     return PBS_OK;
 }
@@ -604,9 +658,12 @@ pbs_status steps(pbs_ctx *c, int n)
 {
     for (int i = 0; i < n; ++i) {
         pbs_status r = one_step<T>(c);
-        if (r != PBS_OK) return r;
+        if (r != PBS_OK) {
+            join_side(c);
+            return r;
+        }
     }
-    return PBS_OK;
+    return join_side(c);
 }
 
 template <typename T>
@@ -872,6 +929,17 @@ pbs_status pbs_bind(pbs_ctx *c, void *ws, size_t bytes, void *stream)
     c->ws = (char *)ws;
     c->ws_bytes = bytes;
     c->stream = (hipStream_t)stream;
+    if (!c->side) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        const int ng = c->g.ngen;
+        c->ev_e.assign(ng, nullptr);
+        c->ev_tat.assign(ng, nullptr);
+        c->tat_pend.assign(ng, 0);
+        for (int k = 0; k < ng; ++k) {
+            HIPCHK(c, hipEventCreateWithFlags(&c->ev_e[k], hipEventDisableTiming));
+            HIPCHK(c, hipEventCreateWithFlags(&c->ev_tat[k], hipEventDisableTiming));
+        }
+    }
     c->state = ST_CREATED;
     pbs_status r = DISPATCH(c, upload_tables, c);
     if (r != PBS_OK) return r;
@@ -1134,6 +1202,12 @@ const char *pbs_last_error(const pbs_ctx *c)
 void pbs_destroy(pbs_ctx *c)
 {
     if (!c) return;
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    for (hipEvent_t e : c->ev_e)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_tat)
+        if (e) (void)hipEventDestroy(e);
+    if (c->side) (void)hipStreamDestroy(c->side);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }

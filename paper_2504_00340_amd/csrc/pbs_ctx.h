@@ -34,6 +34,11 @@ struct pbs_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
+    // side stream of the depth march: generation k's T A T runs there while the main stream continues
+    // with the source product and the later generations' energy passes
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> ev_e, ev_tat;   // per generation: energy pass done / T A T done
+    std::vector<char> tat_pend;             // T A T issued and not yet waited for by the main stream
     size_t o_psi = 0, o_W = 0, o_Q = 0, o_dep = 0, o_edep = 0, o_dout = 0, o_rhoT = 0, o_rhoD = 0, o_tabT = 0,
            o_tabD = 0, total = 0;
     // table offsets (elements) inside the T and double table blocks
