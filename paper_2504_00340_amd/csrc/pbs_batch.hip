@@ -47,6 +47,10 @@ struct pbs_batch {
     size_t sh_theta = 0, sh_lam = 0, sh_S = 0, sh_A = 0, sh_K = 0;   // byte offsets inside the shared block
     char *ws = nullptr;
     hipStream_t stream = nullptr;
+    // side stream of the captured march (each generation's T A T beside the energy chain)
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> ev_e, ev_tat;
+    std::vector<char> pend;
     std::vector<std::vector<double>> rho;
     std::vector<char> have_rho;
     BatchTuning tune;
@@ -403,6 +407,16 @@ pbs_status pbs_batch_bind(pbs_batch *b, void *ws, size_t bytes, void *stream)
     if (!stream) return bfail(b, PBS_EINVAL, "the batch needs a non-NULL stream (its march is captured into a graph)");
     b->ws = (char *)ws;
     b->stream = (hipStream_t)stream;
+    if (!b->side) {
+        BHIP(b, hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+        b->ev_e.assign(b->ngen, nullptr);
+        b->ev_tat.assign(b->ngen, nullptr);
+        b->pend.assign(b->ngen, 0);
+        for (int k = 0; k < b->ngen; ++k) {
+            BHIP(b, hipEventCreateWithFlags(&b->ev_e[k], hipEventDisableTiming));
+            BHIP(b, hipEventCreateWithFlags(&b->ev_tat[k], hipEventDisableTiming));
+        }
+    }
     // shared angular tables and the split-BF16 nuclear angular transfer (identical for every beam)
     const pbs_ctx *c0 = b->ctx[0];
     std::vector<float> th(b->m), lam(b->m), S((size_t)b->m * b->m);
@@ -468,7 +482,17 @@ pbs_status pbs_batch_run(pbs_batch *b)
         const BeamDev *bd = reinterpret_cast<const BeamDev *>(b->ws + b->o_beams);
         const BatchShape Sh = shape(b);
         hipError_t le = hipSuccess;
-        for (int s = 0; s <= maxnz && le == hipSuccess; ++s) le = launch_batch_step(bd, (int)w.size(), Sh, s, maxG, t, b->stream);
+        BatchSide sd{b->side, b->ev_e.data(), b->ev_tat.data(), b->pend.data()};
+        for (int k = 0; k < b->ngen; ++k) b->pend[k] = 0;
+        for (int s = 0; s <= maxnz && le == hipSuccess; ++s)
+            le = launch_batch_step(bd, (int)w.size(), Sh, s, maxG, t, b->stream, &sd);
+        // join the side stream before the capture ends
+        for (int k = 0; k < b->ngen; ++k)
+            if (b->pend[k]) {
+                const hipError_t je = hipStreamWaitEvent(b->stream, b->ev_tat[k], 0);
+                if (le == hipSuccess) le = je;
+                b->pend[k] = 0;
+            }
         const hipError_t ce = hipStreamEndCapture(b->stream, &graph);
         if (le != hipSuccess || ce != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -529,6 +553,12 @@ const char *pbs_batch_last_error(const pbs_batch *b) { return b ? b->err.c_str()
 void pbs_batch_destroy(pbs_batch *b)
 {
     if (!b) return;
+    if (b->side) (void)hipStreamSynchronize(b->side);
+    for (hipEvent_t e : b->ev_e)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->ev_tat)
+        if (e) (void)hipEventDestroy(e);
+    if (b->side) (void)hipStreamDestroy(b->side);
     for (pbs_ctx *c : b->ctx) pbs_destroy(c);
     delete b;
 }

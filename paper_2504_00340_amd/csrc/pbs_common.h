@@ -124,8 +124,17 @@ struct BatchTuning {
     int max_nz = 0;           // longest beam of the wave (set by the driver)
 };
 
+// Side stream of a batch march: each generation's T A T runs there after its energy pass (events per
+// generation; pend marks a T A T that the main stream has not waited for yet).
+struct BatchSide {
+    hipStream_t side;
+    hipEvent_t *ev_e, *ev_tat;
+    char *pend;
+};
+
+// One fused depth step s of a wave.  Without sd every sub-step runs on st in order.
 hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &Sh, int s, int maxG,
-                             const BatchTuning &tu, hipStream_t st);
+                             const BatchTuning &tu, hipStream_t st, const BatchSide *sd = nullptr);
 
 // launchers (explicitly instantiated for float and double); return hipGetLastError()
 template <typename T> hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st);

@@ -1940,12 +1940,12 @@ __attribute__((amdgpu_waves_per_eu(BN == 0 && NPROD == 1 ? QG_WPE : 1))) void qg
 
 template <int NSEG, int WPB>
 __global__ __launch_bounds__(64 * WPB) void tpass_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh,
-                                                                 int s)
+                                                                 int s, int k)
 {
     const BeamDev &B = beams[blockIdx.y];
     if (s >= B.nz) return;
     TParams<float> P;
-    P.psi = B.psi;
+    P.psi = k < 0 ? B.psi : B.psi + (long)k * B.G * 2 * Sh.NLINE;
     P.theta = Sh.theta;
     P.h_half_over_dx = 0.25f * B.dz / Sh.dx;
     P.h_half_over_dy = 0.25f * B.dz / Sh.dy;
@@ -1954,18 +1954,18 @@ __global__ __launch_bounds__(64 * WPB) void tpass_batched_kernel(const BeamDev *
     P.m = Sh.m;
     P.NA = Sh.NA;
     P.NLINE = Sh.NLINE;
-    P.nplanes = (long)Sh.ngen * B.G * 2 * Sh.NA;
+    P.nplanes = (long)(k < 0 ? Sh.ngen : 1) * B.G * 2 * Sh.NA;
     tpass_body<float, NSEG>(P, (long)blockIdx.x * WPB + (threadIdx.x >> 6));
 }
 
 template <int NY, int WPB>
 __global__ __launch_bounds__(64 * WPB) void tpass_batched_affine_kernel(const BeamDev *__restrict__ beams,
-                                                                        BatchShape Sh, int s)
+                                                                        BatchShape Sh, int s, int k)
 {
     const BeamDev &B = beams[blockIdx.y];
     if (s >= B.nz) return;
     TParams<float> P;
-    P.psi = B.psi;
+    P.psi = k < 0 ? B.psi : B.psi + (long)k * B.G * 2 * Sh.NLINE;
     P.theta = Sh.theta;
     P.h_half_over_dx = 0.25f * B.dz / Sh.dx;
     P.h_half_over_dy = 0.25f * B.dz / Sh.dy;
@@ -1974,17 +1974,17 @@ __global__ __launch_bounds__(64 * WPB) void tpass_batched_affine_kernel(const Be
     P.m = Sh.m;
     P.NA = Sh.NA;
     P.NLINE = Sh.NLINE;
-    P.nplanes = (long)Sh.ngen * B.G * 2 * Sh.NA;
+    P.nplanes = (long)(k < 0 ? Sh.ngen : 1) * B.G * 2 * Sh.NA;
     tpass_affine_body<NY>(P, (long)blockIdx.x * WPB + (threadIdx.x >> 6));
 }
 
 template <int N, int PC>
-__global__ __launch_bounds__(256) void apass_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
+__global__ __launch_bounds__(256) void apass_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s, int k)
 {
     const BeamDev &B = beams[blockIdx.z];
-    if (s >= B.nz || blockIdx.y >= (unsigned)(Sh.ngen * B.G * 2)) return;
+    if (s >= B.nz || blockIdx.y >= (unsigned)((k < 0 ? Sh.ngen : 1) * B.G * 2)) return;
     AParams<float> P;
-    P.psi = B.psi;
+    P.psi = k < 0 ? B.psi : B.psi + (long)k * B.G * 2 * Sh.NLINE;
     P.rho = B.rho + (long)s * Sh.NPB * PBS_PT;
     P.sig = B.tabf + 6 * B.G;
     P.S = Sh.S;
@@ -2000,15 +2000,15 @@ __global__ __launch_bounds__(256) void apass_batched_kernel(const BeamDev *__res
 // batched MFMA angular passes (nth = 16 and 32): the single-beam bodies, beam = blockIdx.z
 template <int NTH>
 __global__ __launch_bounds__(NTH == 32 ? APASS32_NT : 256) __attribute__((amdgpu_waves_per_eu(8)))
-void apass_mfma_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
+void apass_mfma_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s, int k)
 {
     const BeamDev &B = beams[blockIdx.z];
-    if (s >= B.nz || blockIdx.y >= (unsigned)(Sh.ngen * B.G * 2)) return;
+    if (s >= B.nz || blockIdx.y >= (unsigned)((k < 0 ? Sh.ngen : 1) * B.G * 2)) return;
     const int bid = blockIdx.x;
     const int pb = (bid >> 4) * 8 + (bid & 7), half = (bid >> 3) & 1;
     if (pb >= Sh.NPB) return;
     AParams<float> P;
-    P.psi = B.psi;
+    P.psi = k < 0 ? B.psi : B.psi + (long)k * B.G * 2 * Sh.NLINE;
     P.rho = B.rho + (long)s * Sh.NPB * PBS_PT;
     P.sig = B.tabf + 6 * B.G;
     P.S = Sh.S;
@@ -2039,11 +2039,86 @@ __global__ __launch_bounds__(1024) void dose_batched_kernel(const BeamDev *__res
 }
 
 hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &Sh, int s, int maxG,
-                             const BatchTuning &tu, hipStream_t st)
+                             const BatchTuning &tu, hipStream_t st, const BatchSide *sd)
 {
+    // T(dz/2) A(dz) T(dz/2) of generation k (all generations for k < 0) on stream q
+    auto tat = [&](int k, hipStream_t q) {
+        const long planes = (long)(k < 0 ? Sh.ngen : 1) * maxG * 2 * Sh.NA;
+        const int nstack = (k < 0 ? Sh.ngen : 1) * maxG * 2;
+        const int nseg = (Sh.ny + 63) / 64;
+        auto tpass = [&]() {
+            const int w = tu.tpass_wpb;
+            const unsigned nb = (unsigned)((planes + w - 1) / w);
+#define PBS_TB(NS, W) hipLaunchKernelGGL((tpass_batched_kernel<NS, W>), dim3(nb, nbeam), dim3(64 * W), 0, q, beams, Sh, s, k)
+#define PBS_TW(NS) do { if (w == 1) PBS_TB(NS, 1); else if (w == 2) PBS_TB(NS, 2); else PBS_TB(NS, 4); } while (0)
+#define PBS_TA(NY, W) hipLaunchKernelGGL((tpass_batched_affine_kernel<NY, W>), dim3(nb, nbeam), dim3(64 * W), 0, q, beams, Sh, s, k)
+#define PBS_TAW(NY) do { if (w == 1) PBS_TA(NY, 1); else if (w == 2) PBS_TA(NY, 2); else PBS_TA(NY, 4); } while (0)
+            if (Sh.nx % TPASS_PF == 0 && Sh.ny == 64) {
+                PBS_TAW(64);
+                return;
+            }
+            if (Sh.nx % TPASS_PF == 0 && Sh.ny == 32) {
+                PBS_TAW(32);
+                return;
+            }
+            switch (nseg) {
+            case 1: PBS_TW(1); break;
+            case 2: PBS_TW(2); break;
+            case 3: PBS_TW(3); break;
+            default: PBS_TW(4); break;
+            }
+#undef PBS_TW
+#undef PBS_TB
+#undef PBS_TAW
+#undef PBS_TA
+        };
+        tpass();
+        if (Sh.nth == 16 || Sh.nth == 32) {
+            dim3 grid((unsigned)((Sh.NPB + 7) / 8 * 16), (unsigned)nstack, nbeam);
+            if (Sh.nth == 32)
+                hipLaunchKernelGGL(apass_mfma_batched_kernel<32>, grid, dim3(APASS32_NT), 0, q, beams, Sh, s, k);
+            else
+                hipLaunchKernelGGL(apass_mfma_batched_kernel<16>, grid, dim3(256), 0, q, beams, Sh, s, k);
+        } else {
+            const int pc = tu.apass_pc;
+            dim3 grid((unsigned)(Sh.NPB * (PBS_PT / pc)), (unsigned)nstack, nbeam);
+#define PBS_AB(N)                                                                                              \
+    do {                                                                                                       \
+        const size_t sh = (size_t)(N - 1) * (N - 1) * pc * sizeof(float);                                      \
+        if (pc == 32) hipLaunchKernelGGL((apass_batched_kernel<N, 32>), grid, dim3(256), sh, q, beams, Sh, s, k); \
+        else if (pc == 16) hipLaunchKernelGGL((apass_batched_kernel<N, 16>), grid, dim3(256), sh, q, beams, Sh, s, k); \
+        else hipLaunchKernelGGL((apass_batched_kernel<N, 8>), grid, dim3(256), sh, q, beams, Sh, s, k);         \
+    } while (0)
+            switch (Sh.nth) {
+            case 16: PBS_AB(16); break;
+            case 20: PBS_AB(20); break;
+            case 24: PBS_AB(24); break;
+            case 32: PBS_AB(32); break;
+            default: return hipErrorInvalidValue;
+            }
+#undef PBS_AB
+        }
+        tpass();
+        return hipGetLastError();
+    };
+    const bool march = s < tu.max_nz;
     for (int k = 0; k < Sh.ngen; ++k) {
+        if (sd && sd->pend[k]) {
+            // this generation's T A T of the previous step
+            if (hipStreamWaitEvent(st, sd->ev_tat[k], 0) != hipSuccess) return hipErrorUnknown;
+            sd->pend[k] = 0;
+        }
         const unsigned nbe = (unsigned)(((long)Sh.NPB * Sh.NOCT * (8 / PBS_EPASS_LPT) * PBS_PT + 255) / 256);
         hipLaunchKernelGGL(epass_batched_kernel, dim3(nbe, nbeam), dim3(256), 0, st, beams, Sh, k, s);
+        if (sd && march) {
+            // generation k's T A T beside the source product and the later generations' energy passes
+            hipError_t e = hipEventRecord(sd->ev_e[k], st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(sd->side, sd->ev_e[k], 0);
+            if (e == hipSuccess) e = tat(k, sd->side);
+            if (e == hipSuccess) e = hipEventRecord(sd->ev_tat[k], sd->side);
+            if (e != hipSuccess) return e;
+            sd->pend[k] = 1;
+        }
         if (k + 1 < Sh.ngen) {
             const int kind = tu.gemm_kind == QGEMM_GLOBAL_B && !qgemm_global_b_fits(Sh.NPB, Sh.NOCT) ? QGEMM_LDS_256
                                                                                                   : tu.gemm_kind;
@@ -2065,61 +2140,10 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
         }
     }
     hipLaunchKernelGGL(dose_batched_kernel, dim3(Sh.NPB, nbeam), dim3(1024), 0, st, beams, Sh, s);
-    const long planes = (long)Sh.ngen * maxG * 2 * Sh.NA;
-    const int nseg = (Sh.ny + 63) / 64;
-    auto tpass = [&]() {
-        const int w = tu.tpass_wpb;
-        const unsigned nb = (unsigned)((planes + w - 1) / w);
-#define PBS_TB(NS, W) hipLaunchKernelGGL((tpass_batched_kernel<NS, W>), dim3(nb, nbeam), dim3(64 * W), 0, st, beams, Sh, s)
-#define PBS_TW(NS) do { if (w == 1) PBS_TB(NS, 1); else if (w == 2) PBS_TB(NS, 2); else PBS_TB(NS, 4); } while (0)
-#define PBS_TA(NY, W) hipLaunchKernelGGL((tpass_batched_affine_kernel<NY, W>), dim3(nb, nbeam), dim3(64 * W), 0, st, beams, Sh, s)
-#define PBS_TAW(NY) do { if (w == 1) PBS_TA(NY, 1); else if (w == 2) PBS_TA(NY, 2); else PBS_TA(NY, 4); } while (0)
-        if (Sh.nx % TPASS_PF == 0 && Sh.ny == 64) {
-            PBS_TAW(64);
-            return;
-        }
-        if (Sh.nx % TPASS_PF == 0 && Sh.ny == 32) {
-            PBS_TAW(32);
-            return;
-        }
-        switch (nseg) {
-        case 1: PBS_TW(1); break;
-        case 2: PBS_TW(2); break;
-        case 3: PBS_TW(3); break;
-        default: PBS_TW(4); break;
-        }
-#undef PBS_TW
-#undef PBS_TB
-#undef PBS_TAW
-#undef PBS_TA
-    };
-    if (s < tu.max_nz) tpass();
-    if (s < tu.max_nz && (Sh.nth == 16 || Sh.nth == 32)) {
-        dim3 grid((unsigned)((Sh.NPB + 7) / 8 * 16), (unsigned)(Sh.ngen * maxG * 2), nbeam);
-        if (Sh.nth == 32)
-            hipLaunchKernelGGL(apass_mfma_batched_kernel<32>, grid, dim3(APASS32_NT), 0, st, beams, Sh, s);
-        else
-            hipLaunchKernelGGL(apass_mfma_batched_kernel<16>, grid, dim3(256), 0, st, beams, Sh, s);
-    } else if (s < tu.max_nz) {
-        const int pc = tu.apass_pc;
-        dim3 grid((unsigned)(Sh.NPB * (PBS_PT / pc)), (unsigned)(Sh.ngen * maxG * 2), nbeam);
-#define PBS_AB(N)                                                                                           \
-    do {                                                                                                    \
-        const size_t sh = (size_t)(N - 1) * (N - 1) * pc * sizeof(float);                                   \
-        if (pc == 32) hipLaunchKernelGGL((apass_batched_kernel<N, 32>), grid, dim3(256), sh, st, beams, Sh, s); \
-        else if (pc == 16) hipLaunchKernelGGL((apass_batched_kernel<N, 16>), grid, dim3(256), sh, st, beams, Sh, s); \
-        else hipLaunchKernelGGL((apass_batched_kernel<N, 8>), grid, dim3(256), sh, st, beams, Sh, s);         \
-    } while (0)
-        switch (Sh.nth) {
-        case 16: PBS_AB(16); break;
-        case 20: PBS_AB(20); break;
-        case 24: PBS_AB(24); break;
-        case 32: PBS_AB(32); break;
-        default: return hipErrorInvalidValue;
-        }
-#undef PBS_AB
+    if (!sd && march) {
+        const hipError_t e = tat(-1, st);
+        if (e != hipSuccess) return e;
     }
-    if (s < tu.max_nz) tpass();
     return hipGetLastError();
 }
 
