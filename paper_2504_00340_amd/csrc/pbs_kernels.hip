@@ -1283,6 +1283,49 @@ __global__ __launch_bounds__(256) void qgemm_mfma_f32_kernel(QParams<float> P, i
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
+// a float moved between the lanes of each quad by the DPP quad permutation CTRL
+template <int CTRL>
+__device__ __forceinline__ float dpp_quad(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+// Stores one 32 x 32 accumulator tile of v_mfma_f32_32x32x16 (rows row0 .. row0 + 31 of lateral tile pb)
+// into the source Q [pb][row][32 cells].  Lane l holds column l % 32 of rows (r % 4) + 8 (r / 4) + 4 (l / 32):
+// for each group r / 4 a 4 x 4 transpose inside every quad of lanes (two DPP butterfly stages) leaves
+// lane t of the quad with row t of the group for the quad's 4 columns, written as one 16-byte store, so a
+// wave writes 1 KB contiguous (8 rows of 32 cells) per instruction.  Non-temporal: the source is read
+// once, by the next generation's energy pass, and is kept out of the caches the product streams through.
+__device__ __forceinline__ void store_source_tile(float *__restrict__ C, long NAPT, int pb, int row0,
+                                                  const floatx16 &a, int lane, int NA, int NPB)
+{
+    const int t4 = lane & 3;
+    const bool up1 = (t4 & 1) != 0, up2 = (t4 & 2) != 0;
+    // one butterfly: lanes with `up` send x and take the partner's y into x; the others send y and take
+    // the partner's x into y (quad_perm [1,0,3,2] for the first stage, [2,3,0,1] for the second)
+    auto b1 = [&](float &x, float &y) {
+        const float r = dpp_quad<0xB1>(up1 ? x : y);
+        if (up1) x = r; else y = r;
+    };
+    auto b2 = [&](float &x, float &y) {
+        const float r = dpp_quad<0x4E>(up2 ? x : y);
+        if (up2) x = r; else y = r;
+    };
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float v0 = a[4 * q], v1 = a[4 * q + 1], v2 = a[4 * q + 2], v3 = a[4 * q + 3];
+        b1(v0, v1);
+        b1(v2, v3);
+        b2(v0, v2);
+        b2(v1, v3);
+        const int row = row0 + 8 * q + 4 * (lane >> 5) + t4;
+        if (pb < NPB && row < NA)
+            __builtin_nontemporal_store(
+                floatx4{v0, v1, v2, v3},
+                reinterpret_cast<floatx4 *>(&C[pb * NAPT + (long)row * PBS_PT + ((lane & 31) & ~3)]));
+    }
+}
+
 template <int BN, int NPROD>
 __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const unsigned short *__restrict__ Ahi,
                                                   const unsigned short *__restrict__ Alo, int Kp, int nmt, int nnt,
@@ -1399,15 +1442,8 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int pb = nt * NPBT + wn * 2 + j;
-            if (pb >= P.NPB) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = mt * 128 + wm * 64 + i * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
-                if (row < P.NA) C[pb * NAPT + (long)row * PBS_PT + (lane & 31)] = acc[i][j][r];
-            }
-        }
+        for (int j = 0; j < 2; ++j)
+            store_source_tile(C, NAPT, nt * NPBT + wn * 2 + j, mt * 128 + wm * 64 + i * 32, acc[i][j], lane, P.NA, P.NPB);
 }
 
 // Source product with the energy-scanned fluence read straight from global memory: its split
@@ -1420,8 +1456,7 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
 // with QG_WM = 2 a wave owns 64 rows x 4 lateral tiles.  B fragments of the next QG_PFD 16-node steps
 // are in flight while a step computes.
 // Tuning knobs (compile-time): B prefetch depth in 16-node steps (single-beam and batched kernels),
-// minimum waves per SIMD for the one-product kernels, waves along rows, and non-temporal stores of
-// the source (it is read once, by the next generation's energy pass).
+// minimum waves per SIMD for the one-product kernels, and waves along rows.
 #ifndef QG_PFD
 #define QG_PFD 3
 #endif
@@ -1434,9 +1469,7 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
 #ifndef QG_WM
 #define QG_WM 1
 #endif
-#ifndef QG_NT
-#define QG_NT 1
-#endif
+
 template <int NPROD, int PFD_ = QG_PFD>
 __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const unsigned short *__restrict__ Ahi,
                                                  const unsigned short *__restrict__ Alo, int Kp, int nmt, int nnt,
@@ -1565,19 +1598,9 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) {
-            const int pb = nt * 8 + wn * TJ + j;
-            if (pb >= P.NPB) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = mt * 128 + wm * (32 * TI) + i * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
-#if QG_NT
-                if (row < P.NA) __builtin_nontemporal_store(acc[i][j][r], &C[pb * NAPT + (long)row * PBS_PT + (lane & 31)]);
-#else
-                if (row < P.NA) C[pb * NAPT + (long)row * PBS_PT + (lane & 31)] = acc[i][j][r];
-#endif
-            }
-        }
+        for (int j = 0; j < TJ; ++j)
+            store_source_tile(C, NAPT, nt * 8 + wn * TJ + j, mt * 128 + wm * (32 * TI) + i * 32, acc[i][j], lane, P.NA,
+                              P.NPB);
 }
 
 template <int NPROD>
