@@ -40,8 +40,11 @@ def algorithmic(grid, tsz=4):
         per = 4 * tsz + (2 * tsz if k > 0 else 0) + (2 * tsz if k + 1 < K1 else 0)
         ep.append(G * lines * per + lines * (2 * 8 + 2 * tsz))
     ep_bytes = sum(ep) / K1
-    tp_bytes = K1 * G * 2 * lines * 2 * tsz          # every plane read and written once
-    ap_bytes = K1 * G * 2 * lines * 2 * tsz + NP * tsz
+    # T and A launch over all generations at once, or per generation (on the side stream) when one
+    # generation has fewer than 1e8 phase-space cells
+    per_launch = 1 if NP * NA * G < 100_000_000 else K1
+    tp_bytes = per_launch * G * 2 * lines * 2 * tsz          # every plane read and written once
+    ap_bytes = per_launch * G * 2 * lines * 2 * tsz + NP * tsz
     qg_flops = 2.0 * NA * NA * 2 * G * NP            # one source product (2 half-step sums) per generation
     qg_bytes = 2 * G * lines * 2 * tsz + NA * NA * tsz
     return dict(epass=("bytes", ep_bytes), tpass=("bytes", tp_bytes), apass=("bytes", ap_bytes),
