@@ -165,6 +165,17 @@ pbs_status pbs_apply(pbs_ctx *ctx, int op, int layer, double h);
 enum { PBS_SRC_FP32 = 0, PBS_SRC_BF16X3 = 1, PBS_SRC_BF16X2 = 2, PBS_SRC_BF16X1 = 3 };
 pbs_status pbs_set_source_precision(pbs_ctx *ctx, int mode);
 
+/* Schedule of the depth march (no effect on the results, which are bitwise the same either way).
+ * Generation k's transport, angular and transport sub-steps touch only its own fluence, so they may
+ * run on a second stream beside the energy passes and source products of the later generations
+ * (section 3.3's Strang sequence is kept per generation; the next step's energy pass of k waits for
+ * them).  mode PBS_SCHED_AUTO (the default) uses the second stream when one generation has fewer than
+ * 1e8 phase-space cells, PBS_SCHED_ONE_STREAM never, PBS_SCHED_TWO_STREAMS always.  The stream is
+ * created by pbs_bind and joined back into the bound stream at the end of every pbs_step_depth /
+ * pbs_run_beam call.  Returns PBS_EINVAL for another mode. */
+enum { PBS_SCHED_AUTO = 0, PBS_SCHED_ONE_STREAM = 1, PBS_SCHED_TWO_STREAMS = 2 };
+pbs_status pbs_set_schedule(pbs_ctx *ctx, int mode);
+
 /* Diagnostics: kernel timing.  pbs_profile(ctx, 1) starts recording a HIP event pair on the
  * bound stream around every kernel launch, grouped by kind; pbs_profile(ctx, 0) stops and
  * clears.  pbs_profile_read synchronises the stream and returns, for kind = 0..n-1 (at most

@@ -639,7 +639,8 @@ pbs_status one_step(pbs_ctx *c)
 {
     const int s = c->step;
     const double dz = c->g.dz;
-    const bool ovl = (long)c->NP * c->NA * c->G() < PBS_OVERLAP_CELLS;
+    const bool ovl = c->sched == PBS_SCHED_TWO_STREAMS ||
+                     (c->sched == PBS_SCHED_AUTO && (long)c->NP * c->NA * c->G() < PBS_OVERLAP_CELLS);
     const int tat = ovl ? s : -1;
     pbs_status r = (s == 0) ? energy_chain<T>(c, MODE_OPEN, -1, 0, 0.5 * dz, tat)
                             : energy_chain<T>(c, MODE_PAIR, s - 1, s, 0.5 * dz, tat);
@@ -1160,6 +1161,15 @@ pbs_status pbs_set_source_precision(pbs_ctx *c, int mode)
     if (mode != PBS_SRC_FP32 && c->Kpb == 0)
         return fail(c, PBS_EUNSUPPORTED, "split-BF16 source product needs an FP32 context with >= 128 angular unknowns");
     c->src_mode = mode;
+    return PBS_OK;
+}
+
+pbs_status pbs_set_schedule(pbs_ctx *c, int mode)
+{
+    if (!c) return PBS_EINVAL;
+    if (mode != PBS_SCHED_AUTO && mode != PBS_SCHED_ONE_STREAM && mode != PBS_SCHED_TWO_STREAMS)
+        return fail(c, PBS_EINVAL, "schedule must be PBS_SCHED_AUTO, PBS_SCHED_ONE_STREAM or PBS_SCHED_TWO_STREAMS");
+    c->sched = mode;
     return PBS_OK;
 }
 

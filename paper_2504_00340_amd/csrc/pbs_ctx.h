@@ -39,6 +39,7 @@ struct pbs_ctx {
     hipStream_t side = nullptr;
     std::vector<hipEvent_t> ev_e, ev_tat;   // per generation: energy pass done / T A T done
     std::vector<char> tat_pend;             // T A T issued and not yet waited for by the main stream
+    int sched = 0;                          // PBS_SCHED_*
     size_t o_psi = 0, o_W = 0, o_Q = 0, o_dep = 0, o_edep = 0, o_dout = 0, o_rhoT = 0, o_rhoD = 0, o_tabT = 0,
            o_tabD = 0, total = 0;
     // table offsets (elements) inside the T and double table blocks

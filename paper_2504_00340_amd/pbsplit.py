@@ -18,12 +18,13 @@ PBS_OK, PBS_EINVAL, PBS_ESTATE, PBS_ENOMEM, PBS_EDEVICE, PBS_EUNSUPPORTED = 0, -
 PBS_FP32, PBS_FP64 = 0, 1
 PBS_OP_E, PBS_OP_T, PBS_OP_A = 1, 2, 3
 PBS_SRC_FP32, PBS_SRC_BF16X3, PBS_SRC_BF16X2, PBS_SRC_BF16X1 = 0, 1, 2, 3
+PBS_SCHED_AUTO, PBS_SCHED_ONE_STREAM, PBS_SCHED_TWO_STREAMS = 0, 1, 2
 _NAMES = {0: "PBS_OK", -1: "PBS_EINVAL", -2: "PBS_ESTATE", -3: "PBS_ENOMEM", -4: "PBS_EDEVICE",
           -5: "PBS_EUNSUPPORTED"}
 
 EXPORTS = ["pbs_create", "pbs_workspace_bytes", "pbs_bind", "pbs_set_phantom", "pbs_set_beam", "pbs_step_depth",
            "pbs_run_beam", "pbs_get_dose", "pbs_get_state", "pbs_set_state", "pbs_apply", "pbs_set_source_precision",
-           "pbs_profile",
+           "pbs_profile", "pbs_set_schedule",
            "pbs_profile_read", "pbs_last_error", "pbs_destroy", "pbs_batch_create", "pbs_batch_workspace_bytes",
            "pbs_batch_bind", "pbs_batch_set_phantom", "pbs_batch_run", "pbs_batch_get_dose", "pbs_batch_tuning",
            "pbs_batch_last_error", "pbs_batch_destroy", "pbs_set_surrogate", "pbs_surrogate_sample",
@@ -86,6 +87,7 @@ def lib():
         L.pbs_apply.argtypes = [vp, C.c_int, C.c_int, C.c_double]
         L.pbs_set_source_precision.argtypes = [vp, C.c_int]
         L.pbs_profile.argtypes = [vp, C.c_int]
+        L.pbs_set_schedule.argtypes = [vp, C.c_int]
         L.pbs_profile_read.argtypes = [vp, D, C.POINTER(C.c_long), C.c_int]
         L.pbs_last_error.argtypes = [vp]
         L.pbs_last_error.restype = C.c_char_p
@@ -257,6 +259,11 @@ class Solver:
 
     def set_source_precision(self, mode: int):
         self._check(self.L.pbs_set_source_precision(self.ctx, int(mode)))
+
+    def set_schedule(self, mode: int):
+        """PBS_SCHED_AUTO / ONE_STREAM / TWO_STREAMS: which streams the depth march uses (bitwise the same
+        result)."""
+        self._check(self.L.pbs_set_schedule(self.ctx, int(mode)))
 
     def profile(self, enable: bool):
         self._check(self.L.pbs_profile(self.ctx, 1 if enable else 0))

@@ -47,6 +47,10 @@ def test_create_validates_grid_and_physics():
     assert L.pbs_bind(ctx, C.c_void_p(256 * 1024), nb.value - 1, None) == B.PBS_EINVAL
     assert L.pbs_bind(ctx, C.c_void_p(256 * 1024 + 8), nb.value, None) == B.PBS_EINVAL
     assert b"workspace" in L.pbs_last_error(ctx)
+    # the schedule switch is host state: valid modes anytime, others EINVAL
+    for mode in (B.PBS_SCHED_ONE_STREAM, B.PBS_SCHED_TWO_STREAMS, B.PBS_SCHED_AUTO):
+        assert L.pbs_set_schedule(ctx, mode) == B.PBS_OK
+    assert L.pbs_set_schedule(ctx, 3) == B.PBS_EINVAL and L.pbs_set_schedule(ctx, -1) == B.PBS_EINVAL
     L.pbs_destroy(ctx)
     for bad in [dict(g, nth=7), dict(g, nth=2), dict(g, ng=1), dict(g, nz=0), dict(g, ngen=0), dict(g, ngen=9),
                 dict(g, dz=-0.1), dict(g, x_half=float("nan")), dict(g, e_hi=g["e_lo"]), dict(g, ny=300)]:

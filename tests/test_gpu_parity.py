@@ -126,6 +126,27 @@ def test_march_with_mfma_source_product(O, prec, tol):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_schedules_are_bitwise_equal(prec):
+    """The two-stream march (each generation's T A T beside the energy chain) gives bitwise the one-stream
+    march, chunked or not, on the MFMA source-product path with three generations."""
+    from paper_2504_00340_amd.pbsplit import PBS_SCHED_ONE_STREAM, PBS_SCHED_TWO_STREAMS
+
+    c = I.small(nx=6, ny=7, nth=16, ng=10, nz=5, ngen=3, e0=32.0, e_hi=40.0, depth=1.2, seed=6)
+    out = []
+    for mode, chunks in ((PBS_SCHED_ONE_STREAM, (5,)), (PBS_SCHED_TWO_STREAMS, (5,)), (PBS_SCHED_TWO_STREAMS, (2, 0, 3))):
+        s = _solver(c, prec)
+        s.set_schedule(mode)
+        for n in chunks:
+            s.step(n)
+        s.run()
+        out.append((s.dose(), s.state()))
+        s.close()
+    for d, st in out[1:]:
+        assert np.array_equal(d, out[0][0])
+        assert np.array_equal(st, out[0][1])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_chunked_stepping_is_bitwise_equal(prec):
     c = I.config1()
     a = _solver(c, prec)
