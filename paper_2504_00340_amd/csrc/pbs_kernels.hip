@@ -1882,8 +1882,9 @@ __device__ __forceinline__ int beam_mode(int s, int nz)
     return MODE_PAIR;
 }
 
-__global__ __launch_bounds__(256) void epass_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int k,
-                                                            int s)
+template <bool LO>
+__global__ __launch_bounds__(256) void epass_batched_kernel(
+    const BeamDev *__restrict__ beams, BatchShape Sh, int k, int s)
 {
     const BeamDev &B = beams[blockIdx.y];
     const int mode = beam_mode(s, B.nz);
@@ -1918,11 +1919,11 @@ __global__ __launch_bounds__(256) void epass_batched_kernel(const BeamDev *__res
     P.NAPT = (long)Sh.NA * PBS_PT;
     const long gid = (long)blockIdx.x * 256 + threadIdx.x;
     if (mode == MODE_PAIR)
-        epass8_body<MODE_PAIR, false>(P, gid);
+        epass8_body<MODE_PAIR, false, LO>(P, gid);
     else if (mode == MODE_OPEN)
-        epass8_body<MODE_OPEN, false>(P, gid);
+        epass8_body<MODE_OPEN, false, LO>(P, gid);
     else
-        epass8_body<MODE_CLOSE, false>(P, gid);
+        epass8_body<MODE_CLOSE, false, LO>(P, gid);
 }
 
 // BN = 128 / 256: LDS-staged kernel with BN-column blocks; BN = 0: global-B kernel (256 columns)
@@ -2132,7 +2133,10 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
             sd->pend[k] = 0;
         }
         const unsigned nbe = (unsigned)(((long)Sh.NPB * Sh.NOCT * (8 / PBS_EPASS_LPT) * PBS_PT + 255) / 256);
-        hipLaunchKernelGGL(epass_batched_kernel, dim3(nbe, nbeam), dim3(256), 0, st, beams, Sh, k, s);
+        if (Sh.nprod == 3)
+            hipLaunchKernelGGL(epass_batched_kernel<true>, dim3(nbe, nbeam), dim3(256), 0, st, beams, Sh, k, s);
+        else
+            hipLaunchKernelGGL(epass_batched_kernel<false>, dim3(nbe, nbeam), dim3(256), 0, st, beams, Sh, k, s);
         if (sd && march) {
             // generation k's T A T beside the source product and the later generations' energy passes
             hipError_t e = hipEventRecord(sd->ev_e[k], st);
