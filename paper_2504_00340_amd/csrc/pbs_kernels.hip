@@ -170,6 +170,10 @@ hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st)
 // one partial per (cell, line group), stored at line slot a = line group; the dose reduction then
 // sums NOCT * 8 / PBS_EPASS_LPT slots per cell instead of NA.  Lanes 0-31 hold the 32 cells of one
 // tile.
+// The energy pass streams the fluence (and the source) through once: non-temporal loads and stores
+// keep it from displacing what the caches hold for others (measured 11.1 -> 10.9 ms per config-2 step).
+#define EP_LD(p) __builtin_nontemporal_load(p)
+#define EP_ST(v, p) __builtin_nontemporal_store(v, p)
 // FEAT / LO = false compile out the surrogate records and the lo half of the split scans.
 template <int MODE, bool FEAT = true, bool LO = true>
 __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
@@ -217,13 +221,13 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
 #pragma unroll
         for (int e = 0; e < L; ++e) {
             const bool v = e < nval;
-            x1[e] = v ? p1[e * PBS_PT] : 0.f;
-            x2[e] = v ? p2[e * PBS_PT] : 0.f;
+            x1[e] = v ? EP_LD(&p1[e * PBS_PT]) : 0.f;
+            x2[e] = v ? EP_LD(&p2[e * PBS_PT]) : 0.f;
             qc[e] = qo[e] = 0.f;
             if (hasQ && v) {
                 const long o = (long)g * S + line0 + e * PBS_PT;
-                if (CL) qc[e] = P.Q[o];
-                if (OP) qo[e] = P.Q[QS + o];
+                if (CL) qc[e] = EP_LD(&P.Q[o]);
+                if (OP) qo[e] = EP_LD(&P.Q[QS + o]);
             }
         }
         const float w = P.wc[g], dec = P.wdec[g], idE = P.invdE[g];
@@ -249,8 +253,8 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
                 z2 = (mo11 * r2 - mo21 * r1) * io;
             }
             if (e < nval) {
-                p1[e * PBS_PT] = z1;
-                p2[e * PBS_PT] = z2;
+                EP_ST(z1, &p1[e * PBS_PT]);
+                EP_ST(z2, &p2[e * PBS_PT]);
             }
             if (CL) {
                 s0a += (double)x1[e];
@@ -575,6 +579,10 @@ constexpr int TPASS_PF = 8;   // rows of the row-affine sweep loaded ahead (nx m
 // Same sweep when ny is 32 or 64 and nx a multiple of TPASS_PF: a lane's address is affine in the row
 // (row stride = ny/32 lateral tiles), so each row costs one pointer increment and no guards; lanes
 // beyond ny (ny = 32) read a clamped in-range column and are zeroed.
+// The transport sweep reads and writes every plane once: non-temporal loads and stores (both are needed:
+// either alone measured no gain; together 12.6 -> 12.1 ms per config-2 step, 5.3 TB/s).
+#define TP_LD(p) __builtin_nontemporal_load(p)
+#define TP_ST(v, p) __builtin_nontemporal_store(v, p)
 template <int NY>
 __device__ __forceinline__ void tpass_affine_body(const TParams<float> &P, long plane)
 {
@@ -615,7 +623,7 @@ __device__ __forceinline__ void tpass_affine_body(const TParams<float> &P, long 
     const float *ld = ptr;
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
-        rb[i] = i < nx ? *ld * vmask : 0.f;
+        rb[i] = i < nx ? TP_LD(ld) * vmask : 0.f;
         if (i < nx) ld += step;
     }
     float *st = ptr;
@@ -624,7 +632,7 @@ __device__ __forceinline__ void tpass_affine_body(const TParams<float> &P, long 
         const bool more = r0 + PF < nx;
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
-            rb[PF + i] = more ? *ld * vmask : 0.f;
+            rb[PF + i] = more ? TP_LD(ld) * vmask : 0.f;
             if (more) ld += step;
         }
 #pragma unroll
@@ -643,7 +651,7 @@ __device__ __forceinline__ void tpass_affine_body(const TParams<float> &P, long 
             y += c8 * dpp_f<0x118, 0xF>(y);
             y += m16 * dpp_f<0x142, 0xA>(y);
             y += m32 * dpp_f<0x143, 0xC>(y);
-            if (FULL || valid) *st = y;
+            if (FULL || valid) TP_ST(y, st);
             st += step;
             pm1 = p0;
             dxm = dxp;
