@@ -136,6 +136,8 @@ pbs_status setup_wave(pbs_batch *b, const std::vector<int> &w, std::vector<BeamD
         d.tabd = reinterpret_cast<const double *>(W + s.tabd);
         d.dBot = c->dBot;
         d.dz = (float)b->grids[beam].dz;
+        d.thx = (float)(0.5 * (0.5 * c->g.dz) / c->dx);
+        d.thy = (float)(0.5 * (0.5 * c->g.dz) / c->dy);
         d.G = G;
         d.nz = nz;
         // tables

@@ -100,6 +100,8 @@ struct BeamDev {
     const double *tabd;       // deposit weights dA, dB, dInj: 3 arrays of G
     double dBot;
     float dz;
+    float thx, thy;           // transport factors (dz/4)/dx, (dz/4)/dy, rounded once from FP64 as in the
+                              // single-beam path so a batched beam is bitwise the single-beam run
     int G, nz;
 };
 

@@ -378,6 +378,10 @@ __device__ __forceinline__ T superbee_slope(T dup, T dface)
     return same ? copysign(v, dface) : T(0);
 }
 
+// The transport sweep reads and writes every plane once: non-temporal loads and stores (both are needed:
+// either alone measured no gain; together 12.6 -> 12.1 ms per config-2 step, 5.3 TB/s).
+#define TP_LD(p) __builtin_nontemporal_load(p)
+#define TP_ST(v, p) __builtin_nontemporal_store(v, p)
 template <typename T, int NSEG>
 __device__ __forceinline__ void tpass_body(const TParams<T> &P, long plane)
 {
@@ -419,7 +423,7 @@ __device__ __forceinline__ void tpass_body(const TParams<T> &P, long plane)
             T x = T(0);
             if (r < nx && valid[s]) {
                 const long pq = (long)p * ny + qcol[s];
-                x = base[(pq / PBS_PT) * NAPT + (pq % PBS_PT)];
+                x = TP_LD(&base[(pq / PBS_PT) * NAPT + (pq % PBS_PT)]);
             }
             v[s] = x;
         }
@@ -471,7 +475,7 @@ __device__ __forceinline__ void tpass_body(const TParams<T> &P, long plane)
             ym1[s] = y;
             if (valid[s]) {
                 const long pq = (long)p * ny + qcol[s];
-                base[(pq / PBS_PT) * NAPT + (pq % PBS_PT)] = y;
+                TP_ST(y, &base[(pq / PBS_PT) * NAPT + (pq % PBS_PT)]);
             }
         }
 #pragma unroll
@@ -579,10 +583,6 @@ constexpr int TPASS_PF = 8;   // rows of the row-affine sweep loaded ahead (nx m
 // Same sweep when ny is 32 or 64 and nx a multiple of TPASS_PF: a lane's address is affine in the row
 // (row stride = ny/32 lateral tiles), so each row costs one pointer increment and no guards; lanes
 // beyond ny (ny = 32) read a clamped in-range column and are zeroed.
-// The transport sweep reads and writes every plane once: non-temporal loads and stores (both are needed:
-// either alone measured no gain; together 12.6 -> 12.1 ms per config-2 step, 5.3 TB/s).
-#define TP_LD(p) __builtin_nontemporal_load(p)
-#define TP_ST(v, p) __builtin_nontemporal_store(v, p)
 template <int NY>
 __device__ __forceinline__ void tpass_affine_body(const TParams<float> &P, long plane)
 {
@@ -668,6 +668,129 @@ __global__ __launch_bounds__(256) void tpass_affine_kernel(TParams<float> P)
     tpass_affine_body<NY>(P, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
+// Same sweep for ny = 96 or 128 (two 64-lane segments per row, ny a multiple of the 32-column lateral
+// tile, so every segment's address stays affine in the row): neighbours at a segment seam and the carry of
+// the implicit row recurrence cross it by readlane; lanes beyond ny read a clamped column and are zeroed.
+template <int NY>
+__device__ __forceinline__ void tpass_wide_body(const TParams<float> &P, long plane)
+{
+    static_assert(NY % 32 == 0 && NY > 64 && NY <= 128, "two segments of whole lateral tiles");
+    constexpr int NS = 2;
+    if (plane >= P.nplanes) return;   // uniform per wave
+    const int lane = threadIdx.x & 63;
+    const int a = (int)(plane % P.NA);
+    const long slab = plane / P.NA;
+    const float cx = P.theta[a / P.m], cy = P.theta[a % P.m];
+    const bool mx = cx < 0.f, my = cy < 0.f;
+    const float ax = fabsf(cx) * P.h_half_over_dx, ay = fabsf(cy) * P.h_half_over_dy;
+    const float idiag = 1.f / (1.f + ax + ay);
+    const float cq = ay * idiag;
+    const long NAPT = (long)P.NA * PBS_PT;
+    const int nx = P.nx;
+    const long RS = (long)(NY / 32) * NAPT;   // elements from row p to row p+1
+    const long step = mx ? -RS : RS;
+    float vmask[NS];
+    bool valid[NS];
+    const float *ld[NS];
+    float *st[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int q = s * 64 + lane;
+        valid[s] = q < NY;
+        const int ql = valid[s] ? q : NY - 1;
+        const int qc = my ? NY - 1 - ql : ql;
+        float *row0 = P.psi + slab * P.NLINE + (long)a * PBS_PT + (long)(qc >> 5) * NAPT + (qc & 31);
+        st[s] = mx ? row0 + (long)(nx - 1) * RS : row0;
+        ld[s] = st[s];
+        vmask[s] = valid[s] ? 1.f : 0.f;
+    }
+    // scan multipliers: cq^(2^i) for the row shifts, cq^((lane&15)+1), cq^((lane&31)+1) for the row
+    // broadcasts and cq^(lane+1) for the carry from the previous segment
+    const float c1 = cq, c2 = c1 * c1, c4 = c2 * c2, c8 = c4 * c4;
+    float m16 = 1.f, m32 = 1.f, m64 = 1.f;
+    {
+        const int e16 = (lane & 15) + 1, e32 = (lane & 31) + 1, e64 = lane + 1;
+        float pw = cq;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            if ((e16 >> i) & 1) m16 *= pw;
+            if ((e32 >> i) & 1) m32 *= pw;
+            if ((e64 >> i) & 1) m64 *= pw;
+            pw *= pw;
+        }
+    }
+    auto lane_of = [](float v, int l) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    };
+    constexpr int PF = TPASS_PF;   // rows loaded ahead of the sweep
+    float rb[2 * PF][NS];
+#pragma unroll
+    for (int i = 0; i < PF; ++i)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            rb[i][s] = i < nx ? TP_LD(ld[s]) * vmask[s] : 0.f;
+            if (i < nx) ld[s] += step;
+        }
+    float pm1[NS], dxm[NS], ym1[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) pm1[s] = dxm[s] = ym1[s] = 0.f;
+    for (int r0 = 0; r0 < nx; r0 += PF) {
+        const bool more = r0 + PF < nx;
+#pragma unroll
+        for (int i = 0; i < PF; ++i)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                rb[PF + i][s] = more ? TP_LD(ld[s]) * vmask[s] : 0.f;
+                if (more) ld[s] += step;
+            }
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            float left[NS], dyp[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const float p0 = rb[i][s];
+                const float up = dpp_f<0x138, 0xF>(p0), dn = dpp_f<0x130, 0xF>(p0);
+                left[s] = (s > 0 && lane == 0) ? lane_of(rb[i][s > 0 ? s - 1 : 0], 63) : up;
+                const float right = (s + 1 < NS && lane == 63) ? lane_of(rb[i][s + 1 < NS ? s + 1 : 0], 0) : dn;
+                dyp[s] = superbee_slope(p0 - left[s], right - p0);
+            }
+            float carry = 0.f;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const float p0 = rb[i][s], p1 = rb[i + 1][s];
+                const float up = dpp_f<0x138, 0xF>(dyp[s]);
+                const float dym = (s > 0 && lane == 0) ? lane_of(dyp[s > 0 ? s - 1 : 0], 63) : up;
+                const float dxp = superbee_slope(p0 - pm1[s], p1 - p0);
+                const float R = p0 - ax * ((p0 - pm1[s]) + (dxp - dxm[s])) - ay * ((p0 - left[s]) + (dyp[s] - dym));
+                float y = (R + ax * ym1[s]) * idiag;
+                y += c1 * dpp_f<0x111, 0xF>(y);
+                y += c2 * dpp_f<0x112, 0xF>(y);
+                y += c4 * dpp_f<0x114, 0xF>(y);
+                y += c8 * dpp_f<0x118, 0xF>(y);
+                y += m16 * dpp_f<0x142, 0xA>(y);
+                y += m32 * dpp_f<0x143, 0xC>(y);
+                if (s > 0) y += m64 * carry;
+                carry = lane_of(y, 63);
+                if (valid[s]) TP_ST(y, st[s]);
+                st[s] += step;
+                pm1[s] = p0;
+                dxm[s] = dxp;
+                ym1[s] = y;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PF; ++i)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) rb[i][s] = rb[PF + i][s];
+    }
+}
+
+template <int NY>
+__global__ __launch_bounds__(256) void tpass_wide_kernel(TParams<float> P)
+{
+    tpass_wide_body<NY>(P, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
+}
+
 template <typename T>
 hipError_t launch_tpass(const TParams<T> &P, hipStream_t st)
 {
@@ -679,6 +802,14 @@ hipError_t launch_tpass(const TParams<T> &P, hipStream_t st)
         }
         if (P.nx % TPASS_PF == 0 && P.ny == 32) {
             hipLaunchKernelGGL(tpass_affine_kernel<32>, grid, dim3(256), 0, st, P);
+            return hipGetLastError();
+        }
+        if (P.nx % TPASS_PF == 0 && P.ny == 96) {
+            hipLaunchKernelGGL(tpass_wide_kernel<96>, grid, dim3(256), 0, st, P);
+            return hipGetLastError();
+        }
+        if (P.nx % TPASS_PF == 0 && P.ny == 128) {
+            hipLaunchKernelGGL(tpass_wide_kernel<128>, grid, dim3(256), 0, st, P);
             return hipGetLastError();
         }
         if (P.ny <= 64) {
@@ -1979,8 +2110,8 @@ __global__ __launch_bounds__(64 * WPB) void tpass_batched_kernel(const BeamDev *
     TParams<float> P;
     P.psi = k < 0 ? B.psi : B.psi + (long)k * B.G * 2 * Sh.NLINE;
     P.theta = Sh.theta;
-    P.h_half_over_dx = 0.25f * B.dz / Sh.dx;
-    P.h_half_over_dy = 0.25f * B.dz / Sh.dy;
+    P.h_half_over_dx = B.thx;
+    P.h_half_over_dy = B.thy;
     P.nx = Sh.nx;
     P.ny = Sh.ny;
     P.m = Sh.m;
@@ -1999,8 +2130,8 @@ __global__ __launch_bounds__(64 * WPB) void tpass_batched_affine_kernel(const Be
     TParams<float> P;
     P.psi = k < 0 ? B.psi : B.psi + (long)k * B.G * 2 * Sh.NLINE;
     P.theta = Sh.theta;
-    P.h_half_over_dx = 0.25f * B.dz / Sh.dx;
-    P.h_half_over_dy = 0.25f * B.dz / Sh.dy;
+    P.h_half_over_dx = B.thx;
+    P.h_half_over_dy = B.thy;
     P.nx = Sh.nx;
     P.ny = Sh.ny;
     P.m = Sh.m;
@@ -2008,6 +2139,26 @@ __global__ __launch_bounds__(64 * WPB) void tpass_batched_affine_kernel(const Be
     P.NLINE = Sh.NLINE;
     P.nplanes = (long)(k < 0 ? Sh.ngen : 1) * B.G * 2 * Sh.NA;
     tpass_affine_body<NY>(P, (long)blockIdx.x * WPB + (threadIdx.x >> 6));
+}
+
+template <int NY, int WPB>
+__global__ __launch_bounds__(64 * WPB) void tpass_batched_wide_kernel(const BeamDev *__restrict__ beams,
+                                                                      BatchShape Sh, int s, int k)
+{
+    const BeamDev &B = beams[blockIdx.y];
+    if (s >= B.nz) return;
+    TParams<float> P;
+    P.psi = k < 0 ? B.psi : B.psi + (long)k * B.G * 2 * Sh.NLINE;
+    P.theta = Sh.theta;
+    P.h_half_over_dx = B.thx;
+    P.h_half_over_dy = B.thy;
+    P.nx = Sh.nx;
+    P.ny = Sh.ny;
+    P.m = Sh.m;
+    P.NA = Sh.NA;
+    P.NLINE = Sh.NLINE;
+    P.nplanes = (long)(k < 0 ? Sh.ngen : 1) * B.G * 2 * Sh.NA;
+    tpass_wide_body<NY>(P, (long)blockIdx.x * WPB + (threadIdx.x >> 6));
 }
 
 template <int N, int PC>
@@ -2085,12 +2236,22 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
 #define PBS_TW(NS) do { if (w == 1) PBS_TB(NS, 1); else if (w == 2) PBS_TB(NS, 2); else PBS_TB(NS, 4); } while (0)
 #define PBS_TA(NY, W) hipLaunchKernelGGL((tpass_batched_affine_kernel<NY, W>), dim3(nb, nbeam), dim3(64 * W), 0, q, beams, Sh, s, k)
 #define PBS_TAW(NY) do { if (w == 1) PBS_TA(NY, 1); else if (w == 2) PBS_TA(NY, 2); else PBS_TA(NY, 4); } while (0)
+#define PBS_TD(NY, W) hipLaunchKernelGGL((tpass_batched_wide_kernel<NY, W>), dim3(nb, nbeam), dim3(64 * W), 0, q, beams, Sh, s, k)
+#define PBS_TWW(NY) do { if (w == 1) PBS_TD(NY, 1); else if (w == 2) PBS_TD(NY, 2); else PBS_TD(NY, 4); } while (0)
             if (Sh.nx % TPASS_PF == 0 && Sh.ny == 64) {
                 PBS_TAW(64);
                 return;
             }
             if (Sh.nx % TPASS_PF == 0 && Sh.ny == 32) {
                 PBS_TAW(32);
+                return;
+            }
+            if (Sh.nx % TPASS_PF == 0 && Sh.ny == 96) {
+                PBS_TWW(96);
+                return;
+            }
+            if (Sh.nx % TPASS_PF == 0 && Sh.ny == 128) {
+                PBS_TWW(128);
                 return;
             }
             switch (nseg) {
@@ -2103,6 +2264,8 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
 #undef PBS_TB
 #undef PBS_TAW
 #undef PBS_TA
+#undef PBS_TWW
+#undef PBS_TD
         };
         tpass();
         if (Sh.nth == 16 || Sh.nth == 32) {

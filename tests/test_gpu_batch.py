@@ -8,25 +8,26 @@ from paper_2504_00340_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 
-def _beams(n=5, seed=11):
+def _beams(n=5, seed=11, nx=10, ny=10):
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
         G = int(rng.integers(16, 40))
         nz = int(rng.integers(3, 9))
         e0 = float(rng.uniform(25.0, 38.0))
-        g = I.grid(10, 10, 16, G, nz, 2, 1.0, 1.0, 0.15, 0.0, e0 + 6.0, 0.15 * nz)
+        g = I.grid(nx, ny, 16, G, nz, 2, 1.0, 1.0, 0.15, 0.0, e0 + 6.0, 0.15 * nz)
         b = I.beam(e0, x0=float(rng.uniform(-0.2, 0.2)), y0=float(rng.uniform(-0.2, 0.2)), sigma_x=0.25, sigma_y=0.3)
-        rho = rng.uniform(0.7, 1.6, size=(nz, 10, 10))
+        rho = rng.uniform(0.7, 1.6, size=(nz, nx, ny))
         out.append(dict(grid=g, beam=b, rho=rho))
     return out
 
 
-@pytest.mark.parametrize("wave", [0, 2])
-def test_batch_equals_single_beam_runs(wave):
+@pytest.mark.parametrize("wave,nx,ny", [(0, 10, 10), (2, 10, 10), (0, 8, 96)])
+def test_batch_equals_single_beam_runs(wave, nx, ny):
+    """The 8 x 96 case runs the two-segment row sweep (ny = 96, nx a multiple of 8)."""
     from paper_2504_00340_amd.pbsplit import Batch, Solver
 
-    beams = _beams()
+    beams = _beams(3, nx=nx, ny=ny) if ny > 64 else _beams()
     bt = Batch(beams, I.PHYS, wave=wave)
     bt.run()
     tu = bt.tuning()
