@@ -369,13 +369,18 @@ hipError_t launch_epass8(const EParams<float> &P, int mode, hipStream_t st)
 
 // ---------------------------------------------------------------------------- transport pass
 // Superbee-limited face slope without division: delta = Dface * eta(Dup / Dface).
+// max(min(2|u|, |f|), min(|u|, 2|f|)) is the median of |u|, |f| and 2 min(|u|, |f|) (exact: doubling, min and
+// max do not round); it is 0 when either difference is, so the sign test needs only the two sign bits.
 template <typename T>
 __device__ __forceinline__ T superbee_slope(T dup, T dface)
 {
     const T au = fabs(dup), af = fabs(dface);
-    const T v = fmax(fmin(T(2) * au, af), fmin(au, T(2) * af));
-    const bool same = (dup > T(0) && dface > T(0)) || (dup < T(0) && dface < T(0));
-    return same ? copysign(v, dface) : T(0);
+    T v;
+    if constexpr (sizeof(T) == 4)
+        v = __builtin_amdgcn_fmed3f(au, af, 2.f * fminf(au, af));
+    else
+        v = fmin(fmax(au, af), T(2) * fmin(au, af));
+    return signbit(dup) == signbit(dface) ? copysign(v, dface) : T(0);
 }
 
 // The transport sweep reads and writes every plane once: non-temporal loads and stores (both are needed:
@@ -501,6 +506,14 @@ __device__ __forceinline__ float dpp_f(float x)
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROWMASK, 0xF,
                                                                  false));
 }
+
+// All lanes written, lanes without a source read 0: the form the compiler folds into the DPP operand of the
+// consuming VALU op (a row-scan step becomes one v_fmac_f32_dpp).
+template <int CTRL>
+__device__ __forceinline__ float dpp_z(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, true));
+}
 // DPP controls (GFX9): row_shr:n = 0x110 + n, wave_shl:1 = 0x130, wave_shr:1 = 0x138,
 // row_bcast:15 = 0x142, row_bcast:31 = 0x143.  Lanes without a source receive 0 (the ghost value).
 
@@ -616,6 +629,9 @@ __device__ __forceinline__ void tpass_affine_body(const TParams<float> &P, long 
             if ((e32 >> i) & 1) m32 *= pw;
             pw *= pw;
         }
+        // the broadcasts write every row: rows 0 and 2 (row_bcast15) and lanes 0-31 (row_bcast31) add nothing
+        if (!((lane >> 4) & 1)) m16 = 0.f;
+        if (lane < 32) m32 = 0.f;
     }
     const float vmask = valid ? 1.f : 0.f;
     constexpr int PF = TPASS_PF;   // rows loaded ahead of the sweep
@@ -638,19 +654,19 @@ __device__ __forceinline__ void tpass_affine_body(const TParams<float> &P, long 
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
             const float p0 = rb[i], p1 = rb[i + 1];
-            const float left = dpp_f<0x138, 0xF>(p0);
-            const float right = dpp_f<0x130, 0xF>(p0);
+            const float left = dpp_z<0x138>(p0);
+            const float right = dpp_z<0x130>(p0);
             const float dyp = superbee_slope(p0 - left, right - p0);
-            const float dym = dpp_f<0x138, 0xF>(dyp);
+            const float dym = dpp_z<0x138>(dyp);
             const float dxp = superbee_slope(p0 - pm1, p1 - p0);
             const float R = p0 - ax * ((p0 - pm1) + (dxp - dxm)) - ay * ((p0 - left) + (dyp - dym));
             float y = (R + ax * ym1) * idiag;
-            y += c1 * dpp_f<0x111, 0xF>(y);
-            y += c2 * dpp_f<0x112, 0xF>(y);
-            y += c4 * dpp_f<0x114, 0xF>(y);
-            y += c8 * dpp_f<0x118, 0xF>(y);
-            y += m16 * dpp_f<0x142, 0xA>(y);
-            y += m32 * dpp_f<0x143, 0xC>(y);
+            y += c1 * dpp_z<0x111>(y);
+            y += c2 * dpp_z<0x112>(y);
+            y += c4 * dpp_z<0x114>(y);
+            y += c8 * dpp_z<0x118>(y);
+            y += m16 * dpp_z<0x142>(y);
+            y += m32 * dpp_z<0x143>(y);
             if (FULL || valid) TP_ST(y, st);
             st += step;
             pm1 = p0;
@@ -667,6 +683,8 @@ __global__ __launch_bounds__(256) void tpass_affine_kernel(TParams<float> P)
 {
     tpass_affine_body<NY>(P, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
+
+constexpr int TPASS_WIDE_PF = 4;   // rows loaded ahead per segment (4 measured faster than 8 or 2 at ny = 96)
 
 // Same sweep for ny = 96 or 128 (two 64-lane segments per row, ny a multiple of the 32-column lateral
 // tile, so every segment's address stays affine in the row): neighbours at a segment seam and the carry of
@@ -718,11 +736,14 @@ __device__ __forceinline__ void tpass_wide_body(const TParams<float> &P, long pl
             if ((e64 >> i) & 1) m64 *= pw;
             pw *= pw;
         }
+        // the broadcasts write every row: rows 0 and 2 (row_bcast15) and lanes 0-31 (row_bcast31) add nothing
+        if (!((lane >> 4) & 1)) m16 = 0.f;
+        if (lane < 32) m32 = 0.f;
     }
     auto lane_of = [](float v, int l) {
         return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
     };
-    constexpr int PF = TPASS_PF;   // rows loaded ahead of the sweep
+    constexpr int PF = TPASS_WIDE_PF;   // rows loaded ahead of the sweep
     float rb[2 * PF][NS];
 #pragma unroll
     for (int i = 0; i < PF; ++i)
@@ -749,7 +770,7 @@ __device__ __forceinline__ void tpass_wide_body(const TParams<float> &P, long pl
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 const float p0 = rb[i][s];
-                const float up = dpp_f<0x138, 0xF>(p0), dn = dpp_f<0x130, 0xF>(p0);
+                const float up = dpp_z<0x138>(p0), dn = dpp_z<0x130>(p0);
                 left[s] = (s > 0 && lane == 0) ? lane_of(rb[i][s > 0 ? s - 1 : 0], 63) : up;
                 const float right = (s + 1 < NS && lane == 63) ? lane_of(rb[i][s + 1 < NS ? s + 1 : 0], 0) : dn;
                 dyp[s] = superbee_slope(p0 - left[s], right - p0);
@@ -758,17 +779,17 @@ __device__ __forceinline__ void tpass_wide_body(const TParams<float> &P, long pl
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 const float p0 = rb[i][s], p1 = rb[i + 1][s];
-                const float up = dpp_f<0x138, 0xF>(dyp[s]);
+                const float up = dpp_z<0x138>(dyp[s]);
                 const float dym = (s > 0 && lane == 0) ? lane_of(dyp[s > 0 ? s - 1 : 0], 63) : up;
                 const float dxp = superbee_slope(p0 - pm1[s], p1 - p0);
                 const float R = p0 - ax * ((p0 - pm1[s]) + (dxp - dxm[s])) - ay * ((p0 - left[s]) + (dyp[s] - dym));
                 float y = (R + ax * ym1[s]) * idiag;
-                y += c1 * dpp_f<0x111, 0xF>(y);
-                y += c2 * dpp_f<0x112, 0xF>(y);
-                y += c4 * dpp_f<0x114, 0xF>(y);
-                y += c8 * dpp_f<0x118, 0xF>(y);
-                y += m16 * dpp_f<0x142, 0xA>(y);
-                y += m32 * dpp_f<0x143, 0xC>(y);
+                y += c1 * dpp_z<0x111>(y);
+                y += c2 * dpp_z<0x112>(y);
+                y += c4 * dpp_z<0x114>(y);
+                y += c8 * dpp_z<0x118>(y);
+                y += m16 * dpp_z<0x142>(y);
+                y += m32 * dpp_z<0x143>(y);
                 if (s > 0) y += m64 * carry;
                 carry = lane_of(y, 63);
                 if (valid[s]) TP_ST(y, st[s]);
