@@ -46,11 +46,12 @@ class Phys(C.Structure):
     _fields_ = [("bk_alpha", C.c_double), ("bk_p", C.c_double), ("e_floor", C.c_double),
                 ("highland_es", C.c_double), ("x0_water", C.c_double), ("mp", C.c_double),
                 ("kappa0", C.c_double), ("e_c", C.c_double), ("lambda_nuc", C.c_double),
-                ("gamma_a", C.c_double), ("gamma_b", C.c_double)]
+                ("gamma_a", C.c_double), ("gamma_b", C.c_double), ("stopping", C.c_int)]
 
 
 def _mk(cls, d):
-    return cls(**{k: d[k] for k, _ in cls._fields_})
+    # the stopping-power model defaults to the range fit (0) when a physics dict does not name it
+    return cls(**{k: (d.get(k, 0) if k == "stopping" else d[k]) for k, _ in cls._fields_})
 
 
 _lib = None
@@ -65,6 +66,7 @@ def lib():
         L = C.CDLL(_LIB)
         L.og_gen_elems.restype = C.c_long
         L.og_stopping.restype = C.c_double
+        L.og_bethe_water.restype = C.c_double
         L.og_scatpower.restype = C.c_double
         L.og_superbee.restype = C.c_double
         L.og_defl_angle.restype = C.c_double
@@ -214,6 +216,11 @@ class Oracle:
 
 def stopping(phys: dict, E: float) -> float:
     return lib().og_stopping(C.byref(_mk(Phys, phys)), C.c_double(E))
+
+
+def bethe_water(E: float, mp: float = 938.272) -> float:
+    """Bethe-Bloch mass stopping power of water (App. A.1), MeV cm^2/g."""
+    return lib().og_bethe_water(C.c_double(E), C.c_double(mp))
 
 
 def scatpower(phys: dict, E: float) -> float:

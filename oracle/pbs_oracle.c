@@ -40,6 +40,7 @@ typedef struct {
 typedef struct {
     double bk_alpha, bk_p, e_floor, highland_es, x0_water, mp;
     double kappa0, e_c, lambda_nuc, gamma_a, gamma_b;
+    int stopping; /* 0: Bragg-Kleeman range fit; 1: Bethe-Bloch for water (App. A.1) */
 } og_phys;
 
 /* ---------------------------------------------------------------- sizes */
@@ -61,11 +62,46 @@ static long IDX(const og_grid *g, long gg, long l, long a, long pq)
 }
 
 /* ------------------------------------------------------------- physics */
-/* Bragg-Kleeman range R = alpha E^p (cm of water) gives the mass stopping
- * power S = dE/dR = 1/(alpha p E^(p-1)); clamped at e_floor (R15).        */
+/* Mean excitation energy of element Z, eV: the appendix's piecewise fit (App. A.1). */
+static double og_ivalue(int Z)
+{
+    if (Z == 1) return 19.0;
+    if (Z <= 13) return 11.2 + 11.7 * Z;
+    return 52.8 + 8.71 * Z;
+}
+
+/* Bethe-Bloch mass stopping power of water, MeV cm^2/g (App. A.1).  Readings:
+ * the printed prefactor kappa Z is taken per gram, kappa Z/A with kappa =
+ * 0.307075 MeV cm^2/mol; the logarithm is the heavy-projectile form as
+ * printed (maximum energy transfer 2 m_e c^2 beta^2 gamma^2); the density
+ * term delta is 0 (the appendix does not give it; below 250 MeV in water it
+ * is well under 0.1 %); the compound weights N_k are the mass fractions of
+ * H and O in H2O (Bragg additivity per unit mass).                          */
+double og_bethe_water(double E, double mp)
+{
+    const double kappa = 0.307075, me_c2 = 0.51099895;
+    const int Z[2] = {1, 8};
+    const double A[2] = {1.008, 15.999}, atoms[2] = {2.0, 1.0};
+    const double molar = atoms[0] * A[0] + atoms[1] * A[1];
+    const double pc = sqrt(E * (E + 2.0 * mp)), etot = E + mp;
+    const double beta = pc / etot, betagamma = pc / mp;
+    const double tmax_ev = 2.0 * me_c2 * betagamma * betagamma * 1e6;
+    double S = 0.0;
+    for (int k = 0; k < 2; k++) {
+        double frac = atoms[k] * A[k] / molar;
+        double Sk = kappa * Z[k] / A[k] / (beta * beta) * (log(tmax_ev / og_ivalue(Z[k])) - beta * beta);
+        S += frac * Sk;
+    }
+    return S;
+}
+
+/* Stopping power used by the tables, clamped at e_floor (R15): the
+ * Bragg-Kleeman range R = alpha E^p (cm of water) gives S = dE/dR =
+ * 1/(alpha p E^(p-1)); or the Bethe-Bloch form above.                      */
 double og_stopping(const og_phys *ph, double E)
 {
     double e = E > ph->e_floor ? E : ph->e_floor;
+    if (ph->stopping == 1) return og_bethe_water(e, ph->mp);
     return 1.0 / (ph->bk_alpha * ph->bk_p * pow(e, ph->bk_p - 1.0));
 }
 

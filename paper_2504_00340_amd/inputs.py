@@ -23,7 +23,8 @@ import numpy as np
 # down-scatter rate lambda (1/MeV); Gamma-law shape/rate of the nuclear
 # deflection angle (App. A.4 forms, synthetic parameters).
 PHYS = dict(bk_alpha=0.0022, bk_p=1.77, e_floor=1.0, highland_es=14.1, x0_water=36.08, mp=938.272,
-            kappa0=0.012, e_c=20.0, lambda_nuc=0.05, gamma_a=2.0, gamma_b=40.0)
+            kappa0=0.012, e_c=20.0, lambda_nuc=0.05, gamma_a=2.0, gamma_b=40.0, stopping=0)
+STOP_BRAGG_KLEEMAN, STOP_BETHE = 0, 1   # stopping-power model: range fit, or Bethe-Bloch (App. A.1)
 
 RHO_WATER, RHO_BONE, RHO_LUNG = 1.0, 1.85, 0.26
 

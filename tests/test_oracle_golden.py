@@ -68,19 +68,24 @@ def test_idd_positions_helper_on_a_triangle():
 
 # (E0, depth, steps, groups, upper energy): dz = 0.025 / 0.04 cm, 1 MeV groups
 CASES = [(50, 2.6, 104, 60, 60.0), (100, 8.4, 210, 110, 110.0)]
+TOL_BETHE = 0.015   # measured: within 1.25 % (50 MeV, dz = 0.025 cm) and 0.6 % (100 MeV)
 
 
+@pytest.mark.parametrize("stopping", [I.STOP_BRAGG_KLEEMAN, I.STOP_BETHE], ids=["bragg_kleeman", "bethe"])
 @pytest.mark.parametrize("e0,depth,nz,ng,ehi", CASES, ids=["50MeV", "100MeV"])
-def test_idd_positions_match_the_paper(e0, depth, nz, ng, ehi):
+def test_idd_positions_match_the_paper(e0, depth, nz, ng, ehi, stopping):
+    """Both stopping-power models: the range fit of the benchmark configurations, and the paper's own
+    Bethe-Bloch form (App. A.1), which places the peak within TOL_BETHE of the printed positions."""
     ref = _table()[e0]
     g = I.grid(4, 4, 12, ng, nz, 2, 2.0, 2.0, 0.3, 0.0, ehi, depth)
-    dose, _ = Oracle(g, dict(I.PHYS)).run(I.beam(float(e0)), I.water(g))
+    dose, _ = Oracle(g, dict(I.PHYS, stopping=stopping)).run(I.beam(float(e0)), I.water(g))
     idd = dose.sum(axis=(1, 2))
     z = (np.arange(nz) + 0.5) * g["dz"]
     got = idd_positions(z, idd)
-    print(e0, {k: round(v, 3) for k, v in got.items()}, ref)
+    print(e0, stopping, {k: round(v, 3) for k, v in got.items()}, ref)
+    tol = 0.02 if stopping == I.STOP_BRAGG_KLEEMAN else TOL_BETHE
     for key in ("BP", "P90", "D90", "D20"):
-        assert abs(got[key] - ref[key]) <= 0.02 * ref[key], (key, got[key], ref[key])
+        assert abs(got[key] - ref[key]) <= tol * ref[key], (key, got[key], ref[key])
 
 
 def _sigma_table():

@@ -25,6 +25,32 @@ def test_stopping_power_integrates_to_bragg_kleeman_range(oracle_mod, inputs):
     assert oracle_mod.stopping(ph, 0.3) == oracle_mod.stopping(ph, ph["e_floor"])
 
 
+def test_bethe_water_matches_icru49(oracle_mod, inputs):
+    """The Bethe-Bloch stopping power of water (App. A.1) against the ICRU 49 tabulation
+    (tests/golden/stopping_water_icru49.txt); through the model switch it is the tables' S."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "stopping_water_icru49.txt")
+    ph = dict(inputs.PHYS, stopping=inputs.STOP_BETHE)
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 5
+    for e, ref, tol in ((float(a), float(b), float(c)) for a, b, c in rows):
+        got = oracle_mod.bethe_water(e, ph["mp"])
+        assert abs(got - ref) <= tol * ref, (e, got, ref)
+        assert oracle_mod.stopping(ph, e) == got
+    # the floor applies to either model
+    assert oracle_mod.stopping(ph, 0.2) == oracle_mod.bethe_water(ph["e_floor"], ph["mp"])
+
+
+def test_bethe_range_against_bragg_kleeman_fit(oracle_mod, inputs):
+    """The CSDA range from 1 MeV of the Bethe-Bloch form stays within 1.5 % of the empirical range fit
+    alpha E^p (an independent model) between 50 and 230 MeV."""
+    ph = dict(inputs.PHYS, stopping=inputs.STOP_BETHE)
+    for e in (50.0, 100.0, 150.0, 200.0, 230.0):
+        r, _ = integrate.quad(lambda x: 1.0 / oracle_mod.stopping(ph, x), 1.0, e, epsabs=0, epsrel=1e-10)
+        fit = ph["bk_alpha"] * (e ** ph["bk_p"] - 1.0)
+        assert abs(r / fit - 1.0) < 0.015, (e, r, fit)   # measured: -0.8 % to +1.0 %, -1.2 % at 230 MeV
+
+
 def test_scattering_power_matches_highland_from_momentum(oracle_mod, inputs):
     ph = inputs.PHYS
     for T in [1.5, 10.0, 100.0, 230.0]:
