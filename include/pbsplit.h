@@ -83,6 +83,12 @@ typedef struct pbs_beam {
 
 /* Physics record.  Materials enter through the density only (water-
  * equivalent per unit mass).
+ *   stopping        PBS_STOP_BRAGG_KLEEMAN: S from the range fit below;
+ *                   PBS_STOP_BETHE: the Bethe-Bloch mass stopping power of App. A.1 for water,
+ *                   heavy-projectile form kappa Z/A / beta^2 [ln(2 m_e c^2 beta^2 gamma^2 / I) - beta^2]
+ *                   with kappa = 0.307075 MeV cm^2/mol, no density correction, I(Z) from the
+ *                   appendix's piecewise fit (H 19 eV, O 104.8 eV), summed over H and O with their
+ *                   mass fractions (Bragg additivity); needs e_floor >= 0.5 MeV (else PBS_EINVAL)
  *   bk_alpha, bk_p  Bragg-Kleeman range R = alpha E^p (cm water): S = 1/(alpha p E^(p-1))
  *   e_floor         coefficients are evaluated at max(E, e_floor) (MeV)
  *   highland_es, x0_water, mp   scattering power sigma_tr = (E_s/pv)^2 / X0 (Highland form),
@@ -90,9 +96,11 @@ typedef struct pbs_beam {
  *   kappa0, e_c     nuclear removal per unit mass kappa(E) = kappa0 (1 - exp(-E/e_c)) (cm^2/g)
  *   lambda_nuc      energy transfer of re-emission  ~ exp(-lambda (E_g' - E_g)) (App. A.4)
  *   gamma_a, gamma_b  angular transfer ~ theta^(a-1) exp(-b theta) of the deflection angle */
+enum { PBS_STOP_BRAGG_KLEEMAN = 0, PBS_STOP_BETHE = 1 };
 typedef struct pbs_physics {
     double bk_alpha, bk_p, e_floor, highland_es, x0_water, mp;
     double kappa0, e_c, lambda_nuc, gamma_a, gamma_b;
+    int stopping;
 } pbs_physics;
 
 typedef struct pbs_ctx pbs_ctx; /* opaque; host-side metadata only */

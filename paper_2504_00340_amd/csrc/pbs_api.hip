@@ -156,9 +156,29 @@ pbs_status hip_fail(pbs_ctx *c, hipError_t e, const char *what)
 bool finite_pos(double x) { return std::isfinite(x) && x > 0; }
 
 // ------------------------------------------------------------------------------ host tables
+// Bethe-Bloch mass stopping power of water (App. A.1), MeV cm^2/g: per element the heavy-projectile form
+// K (Z/A) / beta^2 [ln(2 m_e c^2 beta^2 gamma^2 / I) - beta^2] without the density term, I(Z) from the
+// appendix's fit, and the compound as the mass-fraction sum over H and O.
+double bethe_water(double e, double mp)
+{
+    constexpr double K = 0.307075;      // 4 pi N_A r_e^2 m_e c^2, MeV cm^2 / mol
+    constexpr double MEC2 = 0.51099895; // MeV
+    constexpr double A_H = 1.008, A_O = 15.999;
+    const double m_h2o = 2.0 * A_H + A_O;
+    const double gamma = 1.0 + e / mp;
+    const double beta2 = 1.0 - 1.0 / (gamma * gamma);
+    const double wmax_ev = 2.0 * MEC2 * beta2 * gamma * gamma * 1.0e6;
+    auto element = [&](double Z, double A, double I_ev) {
+        return K * (Z / A) / beta2 * (std::log(wmax_ev / I_ev) - beta2);
+    };
+    const double I_h = 19.0, I_o = 11.2 + 11.7 * 8.0;
+    return (2.0 * A_H / m_h2o) * element(1.0, A_H, I_h) + (A_O / m_h2o) * element(8.0, A_O, I_o);
+}
+
 double stopping_power(const pbs_physics &ph, double E)
 {
     const double e = std::max(E, ph.e_floor);
+    if (ph.stopping == PBS_STOP_BETHE) return bethe_water(e, ph.mp);
     return 1.0 / (ph.bk_alpha * ph.bk_p * std::pow(e, ph.bk_p - 1.0));
 }
 
@@ -878,6 +898,8 @@ pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precisi
         !finite_pos(ph.mp) || ph.kappa0 < 0 || !finite_pos(ph.e_c) || ph.lambda_nuc < 0 || !(ph.gamma_a >= 1.0) ||
         !finite_pos(ph.gamma_b))
         return PBS_EINVAL;
+    if (ph.stopping != PBS_STOP_BRAGG_KLEEMAN && ph.stopping != PBS_STOP_BETHE) return PBS_EINVAL;
+    if (ph.stopping == PBS_STOP_BETHE && !(ph.e_floor >= 0.5)) return PBS_EINVAL;
     if (!apass_supported(g.nth)) return PBS_EUNSUPPORTED;
     pbs_ctx *c = new (std::nothrow) pbs_ctx();
     if (!c) return PBS_ENOMEM;

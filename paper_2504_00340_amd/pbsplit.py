@@ -19,6 +19,7 @@ PBS_FP32, PBS_FP64 = 0, 1
 PBS_OP_E, PBS_OP_T, PBS_OP_A = 1, 2, 3
 PBS_SRC_FP32, PBS_SRC_BF16X3, PBS_SRC_BF16X2, PBS_SRC_BF16X1 = 0, 1, 2, 3
 PBS_SCHED_AUTO, PBS_SCHED_ONE_STREAM, PBS_SCHED_TWO_STREAMS = 0, 1, 2
+PBS_STOP_BRAGG_KLEEMAN, PBS_STOP_BETHE = 0, 1
 _NAMES = {0: "PBS_OK", -1: "PBS_EINVAL", -2: "PBS_ESTATE", -3: "PBS_ENOMEM", -4: "PBS_EDEVICE",
           -5: "PBS_EUNSUPPORTED"}
 
@@ -54,7 +55,7 @@ class Physics(C.Structure):
     _fields_ = [("bk_alpha", C.c_double), ("bk_p", C.c_double), ("e_floor", C.c_double),
                 ("highland_es", C.c_double), ("x0_water", C.c_double), ("mp", C.c_double),
                 ("kappa0", C.c_double), ("e_c", C.c_double), ("lambda_nuc", C.c_double),
-                ("gamma_a", C.c_double), ("gamma_b", C.c_double)]
+                ("gamma_a", C.c_double), ("gamma_b", C.c_double), ("stopping", C.c_int)]
 
 
 class PbsError(RuntimeError):
@@ -131,7 +132,8 @@ def lib():
 
 
 def _mk(cls, d):
-    return cls(**{k: d[k] for k, _ in cls._fields_})
+    # the stopping-power model defaults to the range fit (0) when a physics dict does not name it
+    return cls(**{k: (d.get(k, 0) if k == "stopping" else d[k]) for k, _ in cls._fields_})
 
 
 SURROGATE_WEIGHTS = os.path.join(_HERE, "data", "surrogate_c5.pbsn")

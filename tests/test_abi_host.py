@@ -60,6 +60,15 @@ def test_create_validates_grid_and_physics():
     assert rc == B.PBS_EUNSUPPORTED
     rc, _ = _create(g, dict(I.PHYS, bk_alpha=0.0))
     assert rc == B.PBS_EINVAL
+    # stopping-power model: the two known values; the Bethe-Bloch form needs a floor >= 0.5 MeV
+    for phys, want in ((dict(I.PHYS, stopping=B.PBS_STOP_BETHE), B.PBS_OK), (dict(I.PHYS, stopping=2), B.PBS_EINVAL),
+                       (dict(I.PHYS, stopping=-1), B.PBS_EINVAL),
+                       (dict(I.PHYS, stopping=B.PBS_STOP_BETHE, e_floor=0.4), B.PBS_EINVAL),
+                       (dict(I.PHYS, stopping=B.PBS_STOP_BRAGG_KLEEMAN, e_floor=0.4), B.PBS_OK)):
+        rc, ctx = _create(g, phys)
+        assert rc == want, phys
+        if ctx.value:
+            B.lib().pbs_destroy(ctx)
     rc, _ = _create(g, prec=7)
     assert rc == B.PBS_EINVAL
 

@@ -195,3 +195,21 @@ def test_error_paths():
     with pytest.raises(PbsError):
         s.apply(9, 0, 0.1)
     s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_bethe_stopping_march_matches_oracle(O, prec, tol):
+    """The Bethe-Bloch stopping power of App. A.1 (host tables of the library against the oracle's own);
+    the model switch must change the result (here by about 3 % of the dose)."""
+    c = I.small(nx=6, ny=7, nth=16, ng=10, nz=5, ngen=3, e0=32.0, e_hi=40.0, depth=1.2, seed=6)
+    c["phys"] = dict(c["phys"], stopping=I.STOP_BETHE)
+    print("case", prec, "Bethe-Bloch stopping", flush=True)
+    dref, fref = O.Oracle(c["grid"], c["phys"]).run(c["beam"], c["rho"])
+    dbk, _ = O.Oracle(c["grid"], dict(c["phys"], stopping=I.STOP_BRAGG_KLEEMAN)).run(c["beam"], c["rho"])
+    assert _rel(dbk, dref) > 1e-3
+    s = _solver(c, prec)
+    s.run()
+    print(prec, _rel(s.dose(), dref), _rel(s.state(), fref), flush=True)
+    assert _rel(s.dose(), dref) < tol
+    assert _rel(s.state(), fref) < 10 * tol
+    s.close()
