@@ -684,6 +684,99 @@ __global__ __launch_bounds__(256) void tpass_affine_kernel(TParams<float> P)
     tpass_affine_body<NY>(P, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
+// Same sweep for ny = 32 with two planes per wave: lanes 0-31 sweep plane 2w, lanes 32-63 plane 2w+1, each
+// half with its own angle, mirroring and pointer. Neighbour moves that would cross the halves are zeroed,
+// the row scan stops at the 16-lane broadcast (it never crosses lane 31/32), and a half without a plane
+// (odd plane count) repeats its neighbour's loads and stores nothing. Every lane carries a cell, where the
+// one-plane sweep left half of them idle.
+__device__ __forceinline__ void tpass_pair_body(const TParams<float> &P, long pair)
+{
+    if (pair * 2 >= P.nplanes) return;   // uniform per wave
+    const int lane = threadIdx.x & 63;
+    const int ql = lane & 31;
+    const long plane = pair * 2 + (lane >> 5);
+    const bool live = plane < P.nplanes;
+    const long pl = live ? plane : plane - 1;
+    const int a = (int)(pl % P.NA);
+    const long slab = pl / P.NA;
+    const float cx = P.theta[a / P.m], cy = P.theta[a % P.m];
+    const bool mx = cx < 0.f, my = cy < 0.f;
+    const float ax = fabsf(cx) * P.h_half_over_dx, ay = fabsf(cy) * P.h_half_over_dy;
+    const float idiag = 1.f / (1.f + ax + ay);
+    const float cq = ay * idiag;
+    const long NAPT = (long)P.NA * PBS_PT;
+    const int nx = P.nx;
+    const int qc = my ? 31 - ql : ql;
+    const long RS = NAPT;   // one lateral tile per row
+    float *row0 = P.psi + slab * P.NLINE + (long)a * PBS_PT + qc;
+    const long step = mx ? -RS : RS;
+    float *ptr = mx ? row0 + (long)(nx - 1) * RS : row0;
+    const float c1 = cq, c2 = c1 * c1, c4 = c2 * c2, c8 = c4 * c4;
+    float m16 = 1.f;
+    {
+        const int e16 = (lane & 15) + 1;
+        float pw = cq;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            if ((e16 >> i) & 1) m16 *= pw;
+            pw *= pw;
+        }
+        // row_bcast15 writes every row: rows 0 and 2 of the wave (the first 16 lanes of each half) add nothing
+        if (!((lane >> 4) & 1)) m16 = 0.f;
+    }
+    // 0 on the lanes whose neighbour move would cross into the other half, else 1.  Kept opaque so that
+    // the compiler does not turn "move, then zero some lanes" into a move under a partial exec mask, where
+    // the lanes switched off would also stop serving as move sources.
+    float keep_l = ql == 0 ? 0.f : 1.f, keep_r = ql == 31 ? 0.f : 1.f;
+    asm volatile("" : "+v"(keep_l), "+v"(keep_r));
+    constexpr int PF = TPASS_PF;   // rows loaded ahead of the sweep
+    float rb[2 * PF];
+    const float *ld = ptr;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+        rb[i] = i < nx ? TP_LD(ld) : 0.f;
+        if (i < nx) ld += step;
+    }
+    float *st = ptr;
+    float pm1 = 0.f, dxm = 0.f, ym1 = 0.f;
+    for (int r0 = 0; r0 < nx; r0 += PF) {
+        const bool more = r0 + PF < nx;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            rb[PF + i] = more ? TP_LD(ld) : 0.f;
+            if (more) ld += step;
+        }
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const float p0 = rb[i], p1 = rb[i + 1];
+            const float left = keep_l * dpp_z<0x138>(p0);
+            const float right = keep_r * dpp_z<0x130>(p0);
+            const float dyp = superbee_slope(p0 - left, right - p0);
+            const float dym = keep_l * dpp_z<0x138>(dyp);
+            const float dxp = superbee_slope(p0 - pm1, p1 - p0);
+            const float R = p0 - ax * ((p0 - pm1) + (dxp - dxm)) - ay * ((p0 - left) + (dyp - dym));
+            float y = (R + ax * ym1) * idiag;
+            y += c1 * dpp_z<0x111>(y);
+            y += c2 * dpp_z<0x112>(y);
+            y += c4 * dpp_z<0x114>(y);
+            y += c8 * dpp_z<0x118>(y);
+            y += m16 * dpp_z<0x142>(y);
+            if (live) TP_ST(y, st);
+            st += step;
+            pm1 = p0;
+            dxm = dxp;
+            ym1 = y;
+        }
+#pragma unroll
+        for (int i = 0; i < PF; ++i) rb[i] = rb[PF + i];
+    }
+}
+
+__global__ __launch_bounds__(256) void tpass_pair_kernel(TParams<float> P)
+{
+    tpass_pair_body(P, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
+}
+
 constexpr int TPASS_WIDE_PF = 4;   // rows loaded ahead per segment (4 measured faster than 8 or 2 at ny = 96)
 
 // Same sweep for ny = 96 or 128 (two 64-lane segments per row, ny a multiple of the 32-column lateral
@@ -822,7 +915,8 @@ hipError_t launch_tpass(const TParams<T> &P, hipStream_t st)
             return hipGetLastError();
         }
         if (P.nx % TPASS_PF == 0 && P.ny == 32) {
-            hipLaunchKernelGGL(tpass_affine_kernel<32>, grid, dim3(256), 0, st, P);
+            const long pairs = (P.nplanes + 1) / 2;
+            hipLaunchKernelGGL(tpass_pair_kernel, dim3((unsigned)((pairs + 3) / 4)), dim3(256), 0, st, P);
             return hipGetLastError();
         }
         if (P.nx % TPASS_PF == 0 && P.ny == 96) {
@@ -2182,6 +2276,26 @@ __global__ __launch_bounds__(64 * WPB) void tpass_batched_wide_kernel(const Beam
     tpass_wide_body<NY>(P, (long)blockIdx.x * WPB + (threadIdx.x >> 6));
 }
 
+template <int WPB>
+__global__ __launch_bounds__(64 * WPB) void tpass_batched_pair_kernel(const BeamDev *__restrict__ beams,
+                                                                      BatchShape Sh, int s, int k)
+{
+    const BeamDev &B = beams[blockIdx.y];
+    if (s >= B.nz) return;
+    TParams<float> P;
+    P.psi = k < 0 ? B.psi : B.psi + (long)k * B.G * 2 * Sh.NLINE;
+    P.theta = Sh.theta;
+    P.h_half_over_dx = B.thx;
+    P.h_half_over_dy = B.thy;
+    P.nx = Sh.nx;
+    P.ny = Sh.ny;
+    P.m = Sh.m;
+    P.NA = Sh.NA;
+    P.NLINE = Sh.NLINE;
+    P.nplanes = (long)(k < 0 ? Sh.ngen : 1) * B.G * 2 * Sh.NA;
+    tpass_pair_body(P, (long)blockIdx.x * WPB + (threadIdx.x >> 6));
+}
+
 template <int N, int PC>
 __global__ __launch_bounds__(256) void apass_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s, int k)
 {
@@ -2264,7 +2378,14 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
                 return;
             }
             if (Sh.nx % TPASS_PF == 0 && Sh.ny == 32) {
-                PBS_TAW(32);
+                // two planes per wave
+                const unsigned nbp = (unsigned)(((planes + 1) / 2 + w - 1) / w);
+                if (w == 1)
+                    hipLaunchKernelGGL((tpass_batched_pair_kernel<1>), dim3(nbp, nbeam), dim3(64), 0, q, beams, Sh, s, k);
+                else if (w == 2)
+                    hipLaunchKernelGGL((tpass_batched_pair_kernel<2>), dim3(nbp, nbeam), dim3(128), 0, q, beams, Sh, s, k);
+                else
+                    hipLaunchKernelGGL((tpass_batched_pair_kernel<4>), dim3(nbp, nbeam), dim3(256), 0, q, beams, Sh, s, k);
                 return;
             }
             if (Sh.nx % TPASS_PF == 0 && Sh.ny == 96) {

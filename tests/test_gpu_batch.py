@@ -22,12 +22,12 @@ def _beams(n=5, seed=11, nx=10, ny=10):
     return out
 
 
-@pytest.mark.parametrize("wave,nx,ny", [(0, 10, 10), (2, 10, 10), (0, 8, 96)])
+@pytest.mark.parametrize("wave,nx,ny", [(0, 10, 10), (2, 10, 10), (0, 8, 96), (0, 16, 32)])
 def test_batch_equals_single_beam_runs(wave, nx, ny):
-    """The 8 x 96 case runs the two-segment row sweep (ny = 96, nx a multiple of 8)."""
+    """The 8 x 96 case runs the two-segment row sweep, the 16 x 32 case the two-plane one."""
     from paper_2504_00340_amd.pbsplit import Batch, Solver
 
-    beams = _beams(3, nx=nx, ny=ny) if ny > 64 else _beams()
+    beams = _beams(3, nx=nx, ny=ny) if (nx, ny) != (10, 10) else _beams()
     bt = Batch(beams, I.PHYS, wave=wave)
     bt.run()
     tu = bt.tuning()
