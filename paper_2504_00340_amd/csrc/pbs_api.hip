@@ -14,9 +14,10 @@
 
 // The depth march runs on two streams (a generation's T A T beside the energy chain) when one
 // generation holds fewer phase-space cells than this: such kernels leave most of the GPU idle (a 32 x 32
-// beam with 15 x 15 angles and 128 groups: +11 % beams/s), while at config-2 size every kernel already
-// saturates HBM and the concurrent ones mostly slow each other (1 % per step gained, every kernel 1.4-2.6x
-// longer), so there the sub-steps stay in order on one stream and each kernel's own rate stays measurable.
+// beam with 15 x 15 angles and 128 groups: +11 % beams/s), while at 64 x 64 cells, 31 x 31 angles, 128
+// groups and 4 generations every kernel already saturates HBM and the concurrent ones mostly slow each other
+// (1 % per step gained, every kernel 1.4-2.6x longer), so there the sub-steps stay in order on one stream
+// and each kernel's own rate stays measurable.
 #ifndef PBS_OVERLAP_CELLS
 #define PBS_OVERLAP_CELLS 100000000L
 #endif

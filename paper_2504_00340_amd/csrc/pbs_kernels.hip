@@ -171,7 +171,8 @@ hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st)
 // sums NOCT * 8 / PBS_EPASS_LPT slots per cell instead of NA.  Lanes 0-31 hold the 32 cells of one
 // tile.
 // The energy pass streams the fluence (and the source) through once: non-temporal loads and stores
-// keep it from displacing what the caches hold for others (measured 11.1 -> 10.9 ms per config-2 step).
+// keep it from displacing what the caches hold for others (measured 11.1 -> 10.9 ms per depth step of a
+// 64 x 64-cell, 31 x 31-angle, 128-group, 4-generation beam).
 #define EP_LD(p) __builtin_nontemporal_load(p)
 #define EP_ST(v, p) __builtin_nontemporal_store(v, p)
 // FEAT / LO = false compile out the surrogate records and the lo half of the split scans.
@@ -384,7 +385,8 @@ __device__ __forceinline__ T superbee_slope(T dup, T dface)
 }
 
 // The transport sweep reads and writes every plane once: non-temporal loads and stores (both are needed:
-// either alone measured no gain; together 12.6 -> 12.1 ms per config-2 step, 5.3 TB/s).
+// either alone measured no gain; together 12.6 -> 12.1 ms per depth step of a 64 x 64-cell, 31 x 31-angle,
+// 128-group, 4-generation beam, 5.3 TB/s).
 #define TP_LD(p) __builtin_nontemporal_load(p)
 #define TP_ST(v, p) __builtin_nontemporal_store(v, p)
 template <typename T, int NSEG>
