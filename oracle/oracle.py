@@ -46,12 +46,34 @@ class Phys(C.Structure):
     _fields_ = [("bk_alpha", C.c_double), ("bk_p", C.c_double), ("e_floor", C.c_double),
                 ("highland_es", C.c_double), ("x0_water", C.c_double), ("mp", C.c_double),
                 ("kappa0", C.c_double), ("e_c", C.c_double), ("lambda_nuc", C.c_double),
-                ("gamma_a", C.c_double), ("gamma_b", C.c_double), ("stopping", C.c_int)]
+                ("gamma_a", C.c_double), ("gamma_b", C.c_double), ("stopping", C.c_int),
+                ("straggling", C.c_int), ("scattering", C.c_int), ("material", C.c_int), ("nuc_bands", C.c_int),
+                ("nuc_e", C.c_double * 4), ("nuc_lambda", C.c_double * 4), ("nuc_alpha", C.c_double * 4),
+                ("nuc_beta", C.c_double * 4)]
+
+
+# switches of the physics record that default to 0 (off / water / single nuclear parameters)
+_OPT_INT = ("stopping", "straggling", "scattering", "material", "nuc_bands")
+_OPT_ARR = ("nuc_e", "nuc_lambda", "nuc_alpha", "nuc_beta")
 
 
 def _mk(cls, d):
-    # the stopping-power model defaults to the range fit (0) when a physics dict does not name it
-    return cls(**{k: (d.get(k, 0) if k == "stopping" else d[k]) for k, _ in cls._fields_})
+    kw = {}
+    for k, t in cls._fields_:
+        if k in _OPT_INT:
+            kw[k] = int(d.get(k, 0))
+        elif k in _OPT_ARR:
+            v = list(d.get(k, [0.0] * 4)) + [0.0] * 4
+            kw[k] = (C.c_double * 4)(*v[:4])
+        else:
+            kw[k] = d[k]
+    return cls(**kw)
+
+
+class Tab(C.Structure):
+    _fields_ = [(n, C.POINTER(C.c_double)) for n in ("E_face", "E_mid", "dE", "S_face", "sig_tr", "kappa",
+                                                      "T_face", "Tp_face")] + \
+               [("band", C.POINTER(C.c_int)), ("P1", C.POINTER(C.c_double)), ("P2", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -70,6 +92,10 @@ def lib():
         L.og_scatpower.restype = C.c_double
         L.og_superbee.restype = C.c_double
         L.og_defl_angle.restype = C.c_double
+        for f in ("og_bethe", "og_williams", "og_williams_deriv", "og_rutherford", "og_straggle",
+                  "og_straggle_deriv"):
+            getattr(L, f).restype = C.c_double
+        L.og_max_threads.restype = C.c_int
         L.og_initial.restype = C.c_int
         _lib = L
     return _lib
@@ -101,10 +127,20 @@ class Oracle:
         self.S_face = np.zeros(G + 1)
         self.sig_tr = np.zeros(G)
         self.kappa = np.zeros(G)
+        self.T_face = np.zeros(G + 1)
+        self.Tp_face = np.zeros(G + 1)
+        self.band = np.zeros(G, dtype=np.int32)
+        self.NB = max(1, int(phys.get("nuc_bands", 0)))
         self.P1 = np.zeros((G, G))
-        self.P2 = np.zeros((NA, NA))
+        self.P2 = np.zeros((self.NB, NA, NA)) if self.NB > 1 else np.zeros((NA, NA))
         lib().og_tables(C.byref(g), C.byref(self.p), _p(self.E_face), _p(self.E_mid), _p(self.dE),
-                        _p(self.S_face), _p(self.sig_tr), _p(self.kappa), _p(self.P1), _p(self.P2))
+                        _p(self.S_face), _p(self.sig_tr), _p(self.kappa), _p(self.T_face), _p(self.Tp_face),
+                        self.band.ctypes.data_as(C.POINTER(C.c_int)), _p(self.P1), _p(self.P2))
+        self.straggling = bool(phys.get("straggling", 0))
+        self._tab = Tab(_p(self.E_face), _p(self.E_mid), _p(self.dE), _p(self.S_face), _p(self.sig_tr),
+                        _p(self.kappa), _p(self.T_face) if self.straggling else None,
+                        _p(self.Tp_face) if self.straggling else None,
+                        self.band.ctypes.data_as(C.POINTER(C.c_int)), _p(self.P1), _p(self.P2))
 
     # geometry helpers (plain restatements of the grid definition)
     @property
@@ -134,9 +170,13 @@ class Oracle:
         return st
 
     # sub-operators -------------------------------------------------------
+    def _strag(self):
+        return (_p(self.T_face), _p(self.Tp_face)) if self.straggling else (None, None)
+
     def energy_rhs_line(self, rho, x1, x2, Q=None):
         o1, o2 = np.zeros(self.G), np.zeros(self.G)
-        lib().og_energy_rhs(C.byref(self.g), _p(self.S_face), _p(self.dE), _p(self.kappa), C.c_double(rho),
+        lib().og_energy_rhs(C.byref(self.g), _p(self.S_face), _p(self.dE), _p(self.kappa), *self._strag(),
+                            C.c_double(rho),
                             _p(np.ascontiguousarray(x1, dtype=np.float64)),
                             _p(np.ascontiguousarray(x2, dtype=np.float64)),
                             _opt(None if Q is None else np.ascontiguousarray(Q, dtype=np.float64)), _p(o1), _p(o2))
@@ -144,20 +184,18 @@ class Oracle:
 
     def energy_cn(self, gen_state, rho, h, Qn=None, Qs=None):
         """In place CN step of one generation ([G,2,NA,NP])."""
-        lib().og_energy_cn(C.byref(self.g), _p(self.S_face), _p(self.dE), _p(self.kappa), _p(rho),
-                           C.c_double(h), _p(gen_state), _opt(Qn), _opt(Qs))
+        lib().og_energy_cn(C.byref(self.g), _p(self.S_face), _p(self.dE), _p(self.kappa), *self._strag(),
+                           _p(rho), C.c_double(h), _p(gen_state), _opt(Qn), _opt(Qs))
 
     def energy_all(self, state, rho, h):
         dep = np.zeros(self.NP)
-        lib().og_energy_all_api(C.byref(self.g), _p(self.E_face), _p(self.E_mid), _p(self.dE), _p(self.S_face),
-                                _p(self.sig_tr), _p(self.kappa), _p(self.P1), _p(self.P2), _p(rho), C.c_double(h),
-                                _p(state), _p(dep))
+        lib().og_energy_all_api(C.byref(self.g), C.byref(self._tab), _p(rho), C.c_double(h), _p(state), _p(dep))
         return dep
 
     def source(self, prev_gen, rho):
         Q = np.zeros((self.G, self.NA, self.NP))
-        lib().og_source(C.byref(self.g), _p(self.dE), _p(self.kappa), _p(self.P1), _p(self.P2), _p(rho),
-                        _p(prev_gen), _p(Q))
+        lib().og_source(C.byref(self.g), _p(self.dE), _p(self.kappa), _p(self.P1), _p(self.P2),
+                        self.band.ctypes.data_as(C.POINTER(C.c_int)), _p(rho), _p(prev_gen), _p(Q))
         return Q
 
     def transport_cn(self, gen_state, h):
@@ -191,8 +229,7 @@ class Oracle:
         if state is None:
             state = self.initial(beam)
         dose = np.zeros((g.nz, g.nx * g.ny))
-        lib().og_run(C.byref(g), _p(self.E_face), _p(self.E_mid), _p(self.dE), _p(self.S_face), _p(self.sig_tr),
-                     _p(self.kappa), _p(self.P1), _p(self.P2), _p(rho), _p(state), _p(dose))
+        lib().og_run(C.byref(g), C.byref(self._tab), _p(rho), _p(state), _p(dose))
         return dose.reshape(g.nz, g.nx, g.ny), state
 
     def run_records(self, beam: dict, rho, state=None):
@@ -208,10 +245,17 @@ class Oracle:
             state = self.initial(beam)
         dose = np.zeros((g.nz, g.nx * g.ny))
         rec = np.zeros((4, g.nz, g.nx * g.ny))
-        lib().og_run_records(C.byref(g), _p(self.E_face), _p(self.E_mid), _p(self.dE), _p(self.S_face),
-                             _p(self.sig_tr), _p(self.kappa), _p(self.P1), _p(self.P2), _p(rho), _p(state),
-                             _p(dose), _p(rec))
+        lib().og_run_records(C.byref(g), C.byref(self._tab), _p(rho), _p(state), _p(dose), _p(rec))
         return dose.reshape(g.nz, g.nx, g.ny), state, rec.reshape(4, g.nz, g.nx, g.ny)
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().og_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return lib().og_max_threads()
 
 
 def stopping(phys: dict, E: float) -> float:
@@ -221,6 +265,28 @@ def stopping(phys: dict, E: float) -> float:
 def bethe_water(E: float, mp: float = 938.272) -> float:
     """Bethe-Bloch mass stopping power of water (App. A.1), MeV cm^2/g."""
     return lib().og_bethe_water(C.c_double(E), C.c_double(mp))
+
+
+MEDIA = {"water": 0, "bone": 1, "air": 2}
+
+
+def bethe(material: int, E: float, mp: float = 938.272) -> float:
+    """Bethe-Bloch mass stopping power of a medium (0 water, 1 bone, 2 air), MeV cm^2/g (App. A.1)."""
+    return lib().og_bethe(int(material), C.c_double(E), C.c_double(mp))
+
+
+def williams(material: int, E: float, mp: float = 938.272) -> float:
+    """Williams straggling coefficient of a medium, MeV^2 cm^2/g (App. A.2)."""
+    return lib().og_williams(int(material), C.c_double(E), C.c_double(mp))
+
+
+def williams_deriv(material: int, E: float, mp: float = 938.272) -> float:
+    return lib().og_williams_deriv(int(material), C.c_double(E), C.c_double(mp))
+
+
+def rutherford(material: int, E: float, mp: float = 938.272) -> float:
+    """Screened-Rutherford momentum-transfer cross section of a medium, cm^2/g (App. A.3)."""
+    return lib().og_rutherford(int(material), C.c_double(E), C.c_double(mp))
 
 
 def scatpower(phys: dict, E: float) -> float:

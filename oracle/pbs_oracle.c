@@ -25,6 +25,7 @@
  * (dense solves, closed forms, conservation, convergence, symmetry).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -40,8 +41,18 @@ typedef struct {
 typedef struct {
     double bk_alpha, bk_p, e_floor, highland_es, x0_water, mp;
     double kappa0, e_c, lambda_nuc, gamma_a, gamma_b;
-    int stopping; /* 0: Bragg-Kleeman range fit; 1: Bethe-Bloch for water (App. A.1) */
+    int stopping;   /* 0: Bragg-Kleeman range fit (water); 1: Bethe-Bloch of the medium (App. A.1) */
+    int straggling; /* 0: none; 1: Williams straggling coefficient of the medium (App. A.2) */
+    int scattering; /* 0: Highland scattering power; 1: screened Rutherford sigma_tr (App. A.3) */
+    int material;   /* medium: 0 water, 1 bone, 2 air (the compositions of section 4's material table) */
+    int nuc_bands;  /* 0: lambda_nuc, gamma_a, gamma_b for every group; 1..4: per energy band below */
+    double nuc_e[4], nuc_lambda[4], nuc_alpha[4], nuc_beta[4];
 } og_phys;
+
+/* Worker threads of the parallel loops over independent lines (timing of the oracle only; the
+ * results do not depend on it).                                            */
+void og_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int og_max_threads(void) { return omp_get_max_threads(); }
 
 /* ---------------------------------------------------------------- sizes */
 static long og_m(const og_grid *g) { return g->nth - 1; }
@@ -70,29 +81,137 @@ static double og_ivalue(int Z)
     return 52.8 + 8.71 * Z;
 }
 
-/* Bethe-Bloch mass stopping power of water, MeV cm^2/g (App. A.1).  Readings:
- * the printed prefactor kappa Z is taken per gram, kappa Z/A with kappa =
- * 0.307075 MeV cm^2/mol; the logarithm is the heavy-projectile form as
- * printed (maximum energy transfer 2 m_e c^2 beta^2 gamma^2); the density
+/* ------------------------------------------------------------- media
+ * Elements by atomic number Z and standard atomic weight A (g/mol), and the
+ * media by weight fraction: water as H2O; bone and air as section 4's table
+ * of material targets prints them.                                          */
+#define OG_MAXEL 9
+typedef struct {
+    int n;
+    int Z[OG_MAXEL];
+    double A[OG_MAXEL], w[OG_MAXEL];
+} og_medium;
+
+static og_medium og_get_medium(int material)
+{
+    og_medium m;
+    memset(&m, 0, sizeof(m));
+    if (material == 1) { /* bone, rho 1.757 in the table */
+        const int Z[9] = {1, 6, 7, 8, 11, 12, 15, 16, 20};
+        const double A[9] = {1.008, 12.011, 14.007, 15.999, 22.990, 24.305, 30.974, 32.06, 40.078};
+        const double w[9] = {0.042, 0.194, 0.040, 0.425, 0.001, 0.002, 0.092, 0.003, 0.201};
+        m.n = 9;
+        for (int k = 0; k < 9; k++) { m.Z[k] = Z[k]; m.A[k] = A[k]; m.w[k] = w[k]; }
+    } else if (material == 2) { /* air, rho 0.001205 */
+        const int Z[4] = {6, 7, 8, 18};
+        const double A[4] = {12.011, 14.007, 15.999, 39.948};
+        const double w[4] = {0.0001248, 0.7553, 0.2318, 0.01283};
+        m.n = 4;
+        for (int k = 0; k < 4; k++) { m.Z[k] = Z[k]; m.A[k] = A[k]; m.w[k] = w[k]; }
+    } else { /* water: H2O */
+        const double molar = 2.0 * 1.008 + 15.999;
+        m.n = 2;
+        m.Z[0] = 1; m.A[0] = 1.008; m.w[0] = 2.0 * 1.008 / molar;
+        m.Z[1] = 8; m.A[1] = 15.999; m.w[1] = 15.999 / molar;
+    }
+    return m;
+}
+
+/* Kinematics of a proton of kinetic energy E (MeV): beta^2, gamma, pc (MeV). */
+static void og_kin(double E, double mp, double *beta2, double *gamma, double *pc)
+{
+    double g = 1.0 + E / mp;
+    *gamma = g;
+    *beta2 = 1.0 - 1.0 / (g * g);
+    *pc = sqrt(E * (E + 2.0 * mp));
+}
+
+#define OG_KAPPA 0.307075        /* 4 pi N_A r_e^2 m_e c^2, MeV cm^2/mol */
+#define OG_MEC2 0.51099895       /* electron rest energy, MeV */
+#define OG_NA 6.02214076e23      /* Avogadro, 1/mol */
+#define OG_RE 2.8179403262e-13   /* classical electron radius, cm */
+#define OG_ALPHA (1.0 / 137.035999084)
+
+/* Bethe-Bloch mass stopping power of the medium, MeV cm^2/g (App. A.1).
+ * Readings: the printed prefactor kappa Z is taken per gram, kappa Z/A with
+ * kappa = 0.307075 MeV cm^2/mol; the logarithm is the heavy-projectile form
+ * as printed (maximum energy transfer 2 m_e c^2 beta^2 gamma^2); the density
  * term delta is 0 (the appendix does not give it; below 250 MeV in water it
  * is well under 0.1 %); the compound weights N_k are the mass fractions of
- * H and O in H2O (Bragg additivity per unit mass).                          */
-double og_bethe_water(double E, double mp)
+ * the elements (Bragg additivity per unit mass); I(Z) from the appendix's
+ * piecewise fit.                                                            */
+double og_bethe(int material, double E, double mp)
 {
-    const double kappa = 0.307075, me_c2 = 0.51099895;
-    const int Z[2] = {1, 8};
-    const double A[2] = {1.008, 15.999}, atoms[2] = {2.0, 1.0};
-    const double molar = atoms[0] * A[0] + atoms[1] * A[1];
-    const double pc = sqrt(E * (E + 2.0 * mp)), etot = E + mp;
-    const double beta = pc / etot, betagamma = pc / mp;
-    const double tmax_ev = 2.0 * me_c2 * betagamma * betagamma * 1e6;
+    og_medium m = og_get_medium(material);
+    double b2, gam, pc;
+    og_kin(E, mp, &b2, &gam, &pc);
+    const double tmax_ev = 2.0 * OG_MEC2 * b2 * gam * gam * 1e6;
     double S = 0.0;
-    for (int k = 0; k < 2; k++) {
-        double frac = atoms[k] * A[k] / molar;
-        double Sk = kappa * Z[k] / A[k] / (beta * beta) * (log(tmax_ev / og_ivalue(Z[k])) - beta * beta);
-        S += frac * Sk;
-    }
+    for (int k = 0; k < m.n; k++)
+        S += m.w[k] * OG_KAPPA * m.Z[k] / m.A[k] / b2 * (log(tmax_ev / og_ivalue(m.Z[k])) - b2);
     return S;
+}
+
+double og_bethe_water(double E, double mp) { return og_bethe(0, E, mp); }
+
+/* Williams' straggling coefficient of the medium, MeV^2 cm^2/g (App. A.2).
+ * Readings: the printed 4 pi e^4 is per target electron; times the electrons
+ * per gram, N_A Z/A, it is kappa m_e c^2 Z/A (kappa as above); m_e v^2 is
+ * the non-relativistic m_e c^2 beta^2; I per element as for the stopping
+ * power; compounds by mass fraction.                                        */
+double og_williams(int material, double E, double mp)
+{
+    og_medium m = og_get_medium(material);
+    double b2, gam, pc;
+    og_kin(E, mp, &b2, &gam, &pc);
+    const double x = OG_MEC2 * b2; /* m_e v^2, MeV */
+    double T = 0.0;
+    for (int k = 0; k < m.n; k++) {
+        double I = og_ivalue(m.Z[k]) * 1e-6;
+        T += m.w[k] * OG_KAPPA * OG_MEC2 * m.Z[k] / m.A[k] * (1.0 + 4.0 * I / (3.0 * x) * log(2.0 * x / I));
+    }
+    return T;
+}
+
+/* dT/dE of og_williams: with x = m_e c^2 beta^2, d/dx [ln(2x/I)/x] = (1 - ln(2x/I))/x^2 and
+ * dx/dE = m_e c^2 * 2 / (gamma^3 m_p).                                      */
+double og_williams_deriv(int material, double E, double mp)
+{
+    og_medium m = og_get_medium(material);
+    double b2, gam, pc;
+    og_kin(E, mp, &b2, &gam, &pc);
+    const double x = OG_MEC2 * b2;
+    const double dxdE = OG_MEC2 * 2.0 / (gam * gam * gam * mp);
+    double d = 0.0;
+    for (int k = 0; k < m.n; k++) {
+        double I = og_ivalue(m.Z[k]) * 1e-6;
+        d += m.w[k] * OG_KAPPA * OG_MEC2 * m.Z[k] / m.A[k] * (4.0 * I / 3.0) * (1.0 - log(2.0 * x / I)) / (x * x) * dxdE;
+    }
+    return d;
+}
+
+/* Screened-Rutherford momentum-transfer cross section per unit mass of the medium,
+ * cm^2/g (App. A.3): per atom 2 pi (z Z e^2/(4 pi eps0 m0 v^2))^2 [ln((eta+1)/eta) - 1/(eta+1)],
+ * eta = (Z^(1/3) alpha m_e c / p)^2, times N_A/A atoms per gram, summed by mass fraction.
+ * Readings: e^2/(4 pi eps0) = r_e m_e c^2; m0 v^2 is read as p v of the proton in the laboratory
+ * frame (relativistic, no reduced-mass factor): the cross section must be per deflection of the
+ * proton's own direction, and at small angles the Rutherford law in those variables depends on
+ * the momentum transfer and the velocity only, whatever the target mass (the reduced mass belongs
+ * to the centre-of-mass angle; for hydrogen it would multiply sigma_tr by 4).                  */
+double og_rutherford(int material, double E, double mp)
+{
+    og_medium m = og_get_medium(material);
+    double b2, gam, pc;
+    og_kin(E, mp, &b2, &gam, &pc);
+    const double pv = pc * pc / (E + mp);
+    double s = 0.0;
+    for (int k = 0; k < m.n; k++) {
+        double r = m.Z[k] * OG_RE * OG_MEC2 / pv;
+        double t = cbrt((double)m.Z[k]) * OG_ALPHA * OG_MEC2 / pc;
+        double eta = t * t;
+        s += m.w[k] * OG_NA / m.A[k] * 2.0 * M_PI * r * r * (log((eta + 1.0) / eta) - 1.0 / (eta + 1.0));
+    }
+    return s;
 }
 
 /* Stopping power used by the tables, clamped at e_floor (R15): the
@@ -101,17 +220,34 @@ double og_bethe_water(double E, double mp)
 double og_stopping(const og_phys *ph, double E)
 {
     double e = E > ph->e_floor ? E : ph->e_floor;
-    if (ph->stopping == 1) return og_bethe_water(e, ph->mp);
+    if (ph->stopping == 1) return og_bethe(ph->material, e, ph->mp);
     return 1.0 / (ph->bk_alpha * ph->bk_p * pow(e, ph->bk_p - 1.0));
 }
 
-/* Highland scattering power (E_s/pv)^2/X0 used as sigma_tr, clamped. */
+/* Scattering power used as sigma_tr, clamped: Highland (E_s/pv)^2/X0, or the
+ * screened Rutherford form above.                                          */
 double og_scatpower(const og_phys *ph, double E)
 {
     double e = E > ph->e_floor ? E : ph->e_floor;
+    if (ph->scattering == 1) return og_rutherford(ph->material, e, ph->mp);
     double pv = (e * e + 2.0 * e * ph->mp) / (e + ph->mp);
     double r = ph->highland_es / pv;
     return r * r / ph->x0_water;
+}
+
+/* Straggling coefficient T (clamped like the other coefficients) and its
+ * derivative (zero below the floor, where T is held constant); both 0
+ * without straggling.                                                      */
+double og_straggle(const og_phys *ph, double E)
+{
+    if (!ph->straggling) return 0.0;
+    return og_williams(ph->material, E > ph->e_floor ? E : ph->e_floor, ph->mp);
+}
+
+double og_straggle_deriv(const og_phys *ph, double E)
+{
+    if (!ph->straggling || E < ph->e_floor) return 0.0;
+    return og_williams_deriv(ph->material, E, ph->mp);
 }
 
 /* Gauss-Legendre nodes/weights on [-1,1], computed by Newton iteration on
@@ -158,15 +294,33 @@ double og_defl_angle(double u, double v, double up, double vp)
     return atan2(cr, dt);
 }
 
+/* Energy band of every group for the nuclear kernel: with nuc_bands = 0 all groups use the single
+ * parameters (band 0); otherwise each group takes the parameters fitted at the nearest anchor
+ * energy (App. A.4 fits them group by group; the anchors stand for its fitting groups).          */
+static int og_band(const og_phys *ph, double E)
+{
+    int b = 0;
+    for (int k = 1; k < ph->nuc_bands; k++)
+        if (fabs(E - ph->nuc_e[k]) < fabs(E - ph->nuc_e[b])) b = k;
+    return b;
+}
+static double og_band_lambda(const og_phys *ph, int b) { return ph->nuc_bands ? ph->nuc_lambda[b] : ph->lambda_nuc; }
+static double og_band_alpha(const og_phys *ph, int b) { return ph->nuc_bands ? ph->nuc_alpha[b] : ph->gamma_a; }
+static double og_band_beta(const og_phys *ph, int b) { return ph->nuc_bands ? ph->nuc_beta[b] : ph->gamma_b; }
+
 /*
  * Tables (section 3.2 eq:(appSE) and the definition of sigma_tr,g below
- * eq:(0041-d); App. A.4 for P1, P2).  Arrays are caller-allocated:
+ * eq:(0041-d); App. A.2 for T; App. A.4 for P1, P2).  Arrays are caller-allocated:
  *   E_face[G+1], E_mid[G], dE[G], S_face[G+1], sig_tr[G], kappa[G],
+ *   T_face[G+1], Tp_face[G+1]  straggling coefficient and its derivative at the faces,
+ *   band[G]  energy band of the nuclear kernel of every group,
  *   P1[G*G]  (P1[gs*G+gd], source group gs -> destination gd <= gs),
- *   P2[NA*NA] (P2[as*NA+ad], source node as -> destination node ad).
+ *   P2[NB*NA*NA] (P2[(b*NA+as)*NA+ad], source node as -> destination node ad, band b),
+ *            NB = max(1, nuc_bands).
  */
 void og_tables(const og_grid *g, const og_phys *ph, double *E_face, double *E_mid, double *dE,
-               double *S_face, double *sig_tr, double *kappa, double *P1, double *P2)
+               double *S_face, double *sig_tr, double *kappa, double *T_face, double *Tp_face, int *band,
+               double *P1, double *P2)
 {
     int G = g->ng;
     double de = (g->e_hi - g->e_lo) / G;
@@ -176,6 +330,10 @@ void og_tables(const og_grid *g, const og_phys *ph, double *E_face, double *E_mi
         dE[k] = E_face[k + 1] - E_face[k];
     }
     for (int f = 0; f <= G; f++) S_face[f] = og_stopping(ph, E_face[f]);
+    for (int f = 0; f <= G; f++) {
+        T_face[f] = og_straggle(ph, E_face[f]);
+        Tp_face[f] = og_straggle_deriv(ph, E_face[f]);
+    }
 
     /* group mean of the scattering power: 8-point Gauss-Legendre */
     double gx[8], gw[8];
@@ -193,30 +351,36 @@ void og_tables(const og_grid *g, const og_phys *ph, double *E_face, double *E_mi
         double a = E_face[k], b = E_face[k + 1];
         kappa[k] = ph->kappa0 * (1.0 - ph->e_c / (b - a) * (exp(-a / ph->e_c) - exp(-b / ph->e_c)));
     }
-    /* P1 (App. A.4): lambda exp(-lambda (E_g' - E_g)), g <= g', normalised
-     * over destinations for every source group.                          */
+    for (int k = 0; k < G; k++) band[k] = og_band(ph, E_mid[k]);
+    /* P1 (App. A.4): lambda exp(-lambda (E_g' - E_g)), g <= g', with lambda of the source group's
+     * band, normalised over destinations for every source group.                              */
     for (int gs = 0; gs < G; gs++) {
+        double lam = og_band_lambda(ph, band[gs]);
         double Z = 0.0;
-        for (int gd = 0; gd <= gs; gd++) Z += ph->lambda_nuc * exp(-ph->lambda_nuc * (E_mid[gs] - E_mid[gd]));
+        for (int gd = 0; gd <= gs; gd++) Z += lam * exp(-lam * (E_mid[gs] - E_mid[gd]));
         for (int gd = 0; gd < G; gd++)
-            P1[(long)gs * G + gd] =
-                gd <= gs ? ph->lambda_nuc * exp(-ph->lambda_nuc * (E_mid[gs] - E_mid[gd])) / Z : 0.0;
+            P1[(long)gs * G + gd] = gd <= gs ? lam * exp(-lam * (E_mid[gs] - E_mid[gd])) / Z : 0.0;
     }
-    /* P2 (App. A.4): Gamma law beta^a/Gamma(a) theta^(a-1) exp(-beta theta)
-     * of the deflection angle, normalised over destination nodes.        */
+    /* P2_b (App. A.4): Gamma law beta^a/Gamma(a) theta^(a-1) exp(-beta theta) of the deflection
+     * angle with band b's parameters, normalised over destination nodes.                        */
     long m = og_m(g), NA = og_na(g);
-    double cst = pow(ph->gamma_b, ph->gamma_a) / tgamma(ph->gamma_a);
-    for (long as = 0; as < NA; as++) {
-        double up = og_theta(g, as / m), vp = og_theta(g, as % m);
-        double K = 0.0;
-        for (long ad = 0; ad < NA; ad++) {
-            double u = og_theta(g, ad / m), v = og_theta(g, ad % m);
-            double th = og_defl_angle(u, v, up, vp);
-            double f = cst * pow(th, ph->gamma_a - 1.0) * exp(-ph->gamma_b * th);
-            P2[as * NA + ad] = f;
-            K += f;
+    int NB = ph->nuc_bands > 0 ? ph->nuc_bands : 1;
+    for (int b = 0; b < NB; b++) {
+        double al = og_band_alpha(ph, b), be = og_band_beta(ph, b);
+        double cst = pow(be, al) / tgamma(al);
+        double *P = P2 + (long)b * NA * NA;
+        for (long as = 0; as < NA; as++) {
+            double up = og_theta(g, as / m), vp = og_theta(g, as % m);
+            double K = 0.0;
+            for (long ad = 0; ad < NA; ad++) {
+                double u = og_theta(g, ad / m), v = og_theta(g, ad % m);
+                double th = og_defl_angle(u, v, up, vp);
+                double f = cst * pow(th, al - 1.0) * exp(-be * th);
+                P[as * NA + ad] = f;
+                K += f;
+            }
+            for (long ad = 0; ad < NA; ad++) P[as * NA + ad] /= K;
         }
-        for (long ad = 0; ad < NA; ad++) P2[as * NA + ad] /= K;
     }
 }
 
@@ -290,11 +454,15 @@ int og_initial(const og_grid *g, const og_beam *b, const double *E_face, double 
  * x1,x2 are strided lines (stride st); out1/out2 likewise.
  */
 static void og_energy_rhs_line(long G, const double *S_face, const double *dE, const double *kappa,
-                               double rho, const double *x1, const double *x2, long st, const double *Q,
-                               double *o1, double *o2)
+                               const double *T_face, const double *Tp_face, double rho, const double *x1,
+                               const double *x2, long st, const double *Q, double *o1, double *o2)
 {
     for (long k = 0; k < G; k++) {
         double Sp = S_face[k + 1], Sm = S_face[k];
+        if (T_face) { /* straggling, first-order part: S + T'/2 (R22) */
+            Sp += 0.5 * Tp_face[k + 1];
+            Sm += 0.5 * Tp_face[k];
+        }
         double fup = (k == G - 1) ? 0.0 : x1[(k + 1) * st] - x2[(k + 1) * st];
         double flo = x1[k * st] - x2[k * st];
         double sct = rho * kappa[k];
@@ -302,17 +470,148 @@ static void og_energy_rhs_line(long G, const double *S_face, const double *dE, c
         double r2 = 3.0 * rho * Sp / dE[k] * fup + 3.0 * rho * Sm / dE[k] * flo
                     - 3.0 * rho * (Sp + Sm) / dE[k] * x1[k * st] - rho * (Sp - Sm) / dE[k] * x2[k * st]
                     - sct * x2[k * st];
+        if (T_face) {
+            /* straggling, second-order part (1/2) d/dE (T d psi/dE) by the symmetric interior
+             * penalty method (section 3.2, the Q1 / Q2 terms; R22): T linear in the group from its
+             * face values, penalty alpha T_f / h_f on every interior face with alpha = (1+1)^2/2 = 2,
+             * h_f the mean width of the two groups; no diffusive flux through the end faces.
+             * Rows are the test functions phi^1/dE and 3 phi^2/dE; jump [psi] = psi(below) - psi(above). */
+            double Tbar = 0.5 * (T_face[k] + T_face[k + 1]);
+            r2 += rho * 0.5 * 3.0 / dE[k] * (-4.0 * Tbar * x2[k * st] / dE[k]);
+            if (k + 1 < G) { /* upper face: this group is below it */
+                double Tf = T_face[k + 1], hf = 0.5 * (dE[k] + dE[k + 1]), pen = 2.0 * Tf / hf;
+                double J = (x1[k * st] + x2[k * st]) - (x1[(k + 1) * st] - x2[(k + 1) * st]);
+                double Av = Tf * (x2[k * st] / dE[k] + x2[(k + 1) * st] / dE[k + 1]);
+                r1 += rho * 0.5 / dE[k] * (Av - pen * J);
+                r2 += rho * 0.5 * 3.0 / dE[k] * (Av + J * Tf / dE[k] - pen * J);
+            }
+            if (k > 0) { /* lower face: this group is above it */
+                double Tf = T_face[k], hf = 0.5 * (dE[k - 1] + dE[k]), pen = 2.0 * Tf / hf;
+                double J = (x1[(k - 1) * st] + x2[(k - 1) * st]) - (x1[k * st] - x2[k * st]);
+                double Av = Tf * (x2[(k - 1) * st] / dE[k - 1] + x2[k * st] / dE[k]);
+                r1 += rho * 0.5 / dE[k] * (-Av + pen * J);
+                r2 += rho * 0.5 * 3.0 / dE[k] * (Av + J * Tf / dE[k] - pen * J);
+            }
+        }
         if (Q) r1 += Q[k * st];
         o1[k * st] = r1;
         o2[k * st] = r2;
     }
 }
 
-/* Exposed for tests: RHS of the energy operator on one contiguous line. */
-void og_energy_rhs(const og_grid *g, const double *S_face, const double *dE, const double *kappa, double rho,
-                   const double *x1, const double *x2, const double *Q, double *o1, double *o2)
+/* Exposed for tests: RHS of the energy operator on one contiguous line (T_face, Tp_face NULL:
+ * no straggling). */
+void og_energy_rhs(const og_grid *g, const double *S_face, const double *dE, const double *kappa,
+                   const double *T_face, const double *Tp_face, double rho, const double *x1, const double *x2,
+                   const double *Q, double *o1, double *o2)
 {
-    og_energy_rhs_line(g->ng, S_face, dE, kappa, rho, x1, x2, 1, Q, o1, o2);
+    og_energy_rhs_line(g->ng, S_face, dE, kappa, T_face, Tp_face, rho, x1, x2, 1, Q, o1, o2);
+}
+
+/* Inverse of a 2x2 matrix (row-major). */
+static void og_inv2(const double a[4], double r[4])
+{
+    double det = a[0] * a[3] - a[1] * a[2];
+    r[0] = a[3] / det;
+    r[1] = -a[1] / det;
+    r[2] = -a[2] / det;
+    r[3] = a[0] / det;
+}
+
+static void og_mul2(const double a[4], const double b[4], double r[4])
+{
+    double t[4] = {a[0] * b[0] + a[1] * b[2], a[0] * b[1] + a[1] * b[3], a[2] * b[0] + a[3] * b[2],
+                   a[2] * b[1] + a[3] * b[3]};
+    memcpy(r, t, sizeof(t));
+}
+
+/*
+ * Crank-Nicolson energy step with straggling (section 3.3 with the full operator of eq:(0041-d)):
+ * the operator couples group k to k-1 and k+1, so every line is a block-tridiagonal system
+ * (I - h/2 rho D0) X* = X^n + h/2 L(X^n) + h/2 (Q^n + Q*), with D0 the operator at rho = 1 (every
+ * term of it is proportional to rho).  The 2x2 blocks of D0 are read off the line operator itself,
+ * applied to unit vectors; the system is solved by block elimination from the top group down and
+ * back-substitution upwards.
+ */
+static void og_energy_cn_strag(const og_grid *g, const double *S_face, const double *dE, const double *kappa,
+                               const double *T_face, const double *Tp_face, const double *rho, double h,
+                               double *psi, const double *Qn, const double *Qs)
+{
+    long G = g->ng, NA = og_na(g), NP = og_np(g);
+    long st = 2 * NA * NP, qst = NA * NP;
+    /* blocks of D0: Lo[k] (coupling to k-1), Di[k], Up[k] (coupling to k+1), row-major [row][col] */
+    double *Lo = calloc(4 * G, sizeof(double)), *Di = calloc(4 * G, sizeof(double)),
+           *Up = calloc(4 * G, sizeof(double));
+    double *u1 = calloc(G, sizeof(double)), *u2 = calloc(G, sizeof(double));
+    double *o1 = malloc(G * sizeof(double)), *o2 = malloc(G * sizeof(double));
+    for (long j = 0; j < G; j++)
+        for (int l = 0; l < 2; l++) {
+            memset(u1, 0, G * sizeof(double));
+            memset(u2, 0, G * sizeof(double));
+            (l == 0 ? u1 : u2)[j] = 1.0;
+            og_energy_rhs_line(G, S_face, dE, kappa, T_face, Tp_face, 1.0, u1, u2, 1, NULL, o1, o2);
+            for (long k = 0; k < G; k++) {
+                double *B = (j == k) ? Di + 4 * k : (j == k - 1) ? Lo + 4 * k : (j == k + 1) ? Up + 4 * k : NULL;
+                if (!B) continue; /* the operator reaches one group each way only */
+                B[0 * 2 + l] = o1[k];
+                B[1 * 2 + l] = o2[k];
+            }
+        }
+    free(u1); free(u2); free(o1); free(o2);
+#pragma omp parallel
+    {
+        double *e1 = malloc(G * sizeof(double)), *e2 = malloc(G * sizeof(double));
+        double *bt = malloc(2 * G * sizeof(double)), *Dt = malloc(4 * G * sizeof(double));
+#pragma omp for schedule(static)
+        for (long line = 0; line < NA * NP; line++) {
+            long a = line / NP, pq = line % NP;
+            double r = rho[pq], c = 0.5 * h * r;
+            double *x1 = psi + IDX(g, 0, 0, a, pq);
+            double *x2 = psi + IDX(g, 0, 1, a, pq);
+            og_energy_rhs_line(G, S_face, dE, kappa, T_face, Tp_face, r, x1, x2, st, NULL, e1, e2);
+            /* elimination from the top: Dt_k = M_k - U_k Dt_{k+1}^-1 L_{k+1}, bt_k = b_k - U_k Dt_{k+1}^-1 bt_{k+1},
+             * with M = I - c D0_kk, U = -c Up, L = -c Lo                                                    */
+            for (long k = G - 1; k >= 0; k--) {
+                double b1 = x1[k * st] + 0.5 * h * e1[k], b2 = x2[k * st] + 0.5 * h * e2[k];
+                if (Qn) b1 += 0.5 * h * Qn[a * NP + pq + k * qst];
+                if (Qs) b1 += 0.5 * h * Qs[a * NP + pq + k * qst];
+                double M[4] = {1.0 - c * Di[4 * k], -c * Di[4 * k + 1], -c * Di[4 * k + 2], 1.0 - c * Di[4 * k + 3]};
+                if (k + 1 < G) {
+                    double U[4] = {-c * Up[4 * k], -c * Up[4 * k + 1], -c * Up[4 * k + 2], -c * Up[4 * k + 3]};
+                    double L1[4] = {-c * Lo[4 * (k + 1)], -c * Lo[4 * (k + 1) + 1], -c * Lo[4 * (k + 1) + 2],
+                                    -c * Lo[4 * (k + 1) + 3]};
+                    double Di1[4], UDi[4], UDL[4];
+                    og_inv2(Dt + 4 * (k + 1), Di1);
+                    og_mul2(U, Di1, UDi);
+                    og_mul2(UDi, L1, UDL);
+                    for (int q = 0; q < 4; q++) M[q] -= UDL[q];
+                    b1 -= UDi[0] * bt[2 * (k + 1)] + UDi[1] * bt[2 * (k + 1) + 1];
+                    b2 -= UDi[2] * bt[2 * (k + 1)] + UDi[3] * bt[2 * (k + 1) + 1];
+                }
+                memcpy(Dt + 4 * k, M, sizeof(M));
+                bt[2 * k] = b1;
+                bt[2 * k + 1] = b2;
+            }
+            /* back-substitution upwards: X_k = Dt_k^-1 (bt_k - L_k X_{k-1}) */
+            double y1p = 0.0, y2p = 0.0;
+            for (long k = 0; k < G; k++) {
+                double b1 = bt[2 * k], b2 = bt[2 * k + 1];
+                if (k > 0) {
+                    b1 += c * (Lo[4 * k] * y1p + Lo[4 * k + 1] * y2p);
+                    b2 += c * (Lo[4 * k + 2] * y1p + Lo[4 * k + 3] * y2p);
+                }
+                double Dinv[4];
+                og_inv2(Dt + 4 * k, Dinv);
+                double y1 = Dinv[0] * b1 + Dinv[1] * b2, y2 = Dinv[2] * b1 + Dinv[3] * b2;
+                x1[k * st] = y1;
+                x2[k * st] = y2;
+                y1p = y1;
+                y2p = y2;
+            }
+        }
+        free(e1); free(e2); free(bt); free(Dt);
+    }
+    free(Lo); free(Di); free(Up);
 }
 
 /*
@@ -325,11 +624,17 @@ void og_energy_rhs(const og_grid *g, const double *S_face, const double *dE, con
  * system (I - h/2 D_g) X*_g = X^n_g + h/2 L(X^n)_g + h/2 (coupling to the
  * already known X*_{g+1}) + h/2 (Q^n_g + Q*_g) is solved by Cramer's rule.
  * Qn, Qs: sources of the psi1 row [g][a][pq] (already multiplied by rho),
- * or NULL.  rho: [pq].
+ * or NULL.  rho: [pq].  With straggling (T_face non-NULL) the system is
+ * block-tridiagonal and og_energy_cn_strag solves it.
  */
 void og_energy_cn(const og_grid *g, const double *S_face, const double *dE, const double *kappa,
-                  const double *rho, double h, double *psi, const double *Qn, const double *Qs)
+                  const double *T_face, const double *Tp_face, const double *rho, double h, double *psi,
+                  const double *Qn, const double *Qs)
 {
+    if (T_face) {
+        og_energy_cn_strag(g, S_face, dE, kappa, T_face, Tp_face, rho, h, psi, Qn, Qs);
+        return;
+    }
     long G = g->ng, NA = og_na(g), NP = og_np(g);
     long st = 2 * NA * NP; /* stride between groups along a line */
 #pragma omp parallel for schedule(static)
@@ -422,36 +727,49 @@ void og_number_content(const og_grid *g, const double *dE, const double *psi, do
 /*
  * Source of generation k from generation k-1 (Remark after the Strang
  * scheme, eqn:(pri-se2), and the factorised kernel of section 4 / App. A.4):
- *   Q_g(a) = rho * sum_{a'} P2[a' -> a] sum_{g' >= g} P1[g' -> g] kappa_{g'} psi1_{g'}(a') dE_{g'}/dE_g
- * sigma_{c,s} uses the removal cross section of the source group (R10) and
- * P2 is a discrete probability over destination nodes, which absorbs the
- * du dv factor of the paper's quadrature.  The psi2 row gets no source.
- * prev: generation k-1 state; Q: [g][a][pq].
+ *   Q_g(a) = rho * sum_{a'} P2_g[a' -> a] sum_{g' >= g} P1[g' -> g] kappa_{g'} psi1_{g'}(a') dE_{g'}/dE_g
+ * sigma_{c,s} uses the removal cross section of the source group (R10), P2_g
+ * is the angular law of the destination group g's band (App. A.4: "in the
+ * energy group g"), a discrete probability over destination nodes, which
+ * absorbs the du dv factor of the paper's quadrature.  The psi2 row gets no
+ * source.  prev: generation k-1 state; Q: [g][a][pq]; P2: [band][a'][a];
+ * band: [G] (NULL: every group band 0).
  */
 void og_source(const og_grid *g, const double *dE, const double *kappa, const double *P1, const double *P2,
-               const double *rho, const double *prev, double *Q)
+               const int *band, const double *rho, const double *prev, double *Q)
 {
     long G = g->ng, NA = og_na(g), NP = og_np(g);
     double *V = malloc((size_t)G * NA * NP * sizeof(double));
-    /* energy sum (for every source node a' and voxel) */
+    /* energy sum (for every source node a' and voxel); every voxel's terms are added in the order
+     * g' = g, g+1, ..., the voxels of one (a', g) run side by side */
 #pragma omp parallel for schedule(static)
-    for (long ap = 0; ap < NA; ap++)
-        for (long k = 0; k < G; k++)
-            for (long pq = 0; pq < NP; pq++) {
-                double s = 0.0;
-                for (long ks = k; ks < G; ks++)
-                    s += P1[ks * G + k] * kappa[ks] * prev[IDX(g, ks, 0, ap, pq)] * dE[ks] / dE[k];
-                V[(k * NA + ap) * NP + pq] = s;
-            }
-    /* angular sum */
-#pragma omp parallel for schedule(static)
-    for (long ka = 0; ka < G * NA; ka++) {
-        long k = ka / NA, a = ka % NA;
-        for (long pq = 0; pq < NP; pq++) {
-            double s = 0.0;
-            for (long ap = 0; ap < NA; ap++) s += P2[ap * NA + a] * V[(k * NA + ap) * NP + pq];
-            Q[(k * NA + a) * NP + pq] = rho[pq] * s;
+    for (long apk = 0; apk < NA * G; apk++) {
+        long ap = apk / G, k = apk % G;
+        double *s = V + (k * NA + ap) * NP;
+        for (long pq = 0; pq < NP; pq++) s[pq] = 0.0;
+        for (long ks = k; ks < G; ks++) {
+            double c = P1[ks * G + k] * kappa[ks];
+            const double *x = prev + IDX(g, ks, 0, ap, 0);
+            for (long pq = 0; pq < NP; pq++) s[pq] += c * x[pq] * dE[ks] / dE[k];
         }
+    }
+    /* angular sum: terms added in the order a' = 0, 1, ... for every voxel */
+#pragma omp parallel
+    {
+        double *s = malloc(NP * sizeof(double));
+#pragma omp for schedule(static)
+        for (long ka = 0; ka < G * NA; ka++) {
+            long k = ka / NA, a = ka % NA;
+            const double *P = P2 + (long)(band ? band[k] : 0) * NA * NA;
+            for (long pq = 0; pq < NP; pq++) s[pq] = 0.0;
+            for (long ap = 0; ap < NA; ap++) {
+                double c = P[ap * NA + a];
+                const double *v = V + (k * NA + ap) * NP;
+                for (long pq = 0; pq < NP; pq++) s[pq] += c * v[pq];
+            }
+            for (long pq = 0; pq < NP; pq++) Q[(k * NA + a) * NP + pq] = rho[pq] * s[pq];
+        }
+        free(s);
     }
     free(V);
 }
@@ -632,8 +950,12 @@ void og_angular_cn(const og_grid *g, const double *sig_tr, const double *rho, do
 }
 
 /* ------------------------------------------------------------ the march */
+/* Every table of one configuration (as og_tables fills them); T_face and Tp_face are NULL
+ * without straggling. */
 typedef struct {
-    const double *E_face, *E_mid, *dE, *S_face, *sig_tr, *kappa, *P1, *P2;
+    const double *E_face, *E_mid, *dE, *S_face, *sig_tr, *kappa, *T_face, *Tp_face;
+    const int *band;
+    const double *P1, *P2;
 } og_tab;
 
 /*
@@ -673,12 +995,13 @@ static void og_energy_all_rec(const og_grid *g, const og_tab *t, const double *r
         double *cur = state + (long)k * E;
         if (k >= 1) {
             /* before = gen k-1 at entry (saved below), cur-1 = gen k-1 after */
-            og_source(g, t->dE, t->kappa, t->P1, t->P2, rho, before, Qn);
-            og_source(g, t->dE, t->kappa, t->P1, t->P2, rho, state + (long)(k - 1) * E, Qs);
+            og_source(g, t->dE, t->kappa, t->P1, t->P2, t->band, rho, before, Qn);
+            og_source(g, t->dE, t->kappa, t->P1, t->P2, t->band, rho, state + (long)(k - 1) * E, Qs);
         }
         og_energy_content(g, t->E_mid, t->dE, cur, e0);
         memcpy(before, cur, sizeof(double) * E);
-        og_energy_cn(g, t->S_face, t->dE, t->kappa, rho, h, cur, k >= 1 ? Qn : NULL, k >= 1 ? Qs : NULL);
+        og_energy_cn(g, t->S_face, t->dE, t->kappa, t->T_face, t->Tp_face, rho, h, cur, k >= 1 ? Qn : NULL,
+                     k >= 1 ? Qs : NULL);
         og_energy_content(g, t->E_mid, t->dE, cur, e1);
         for (long pq = 0; pq < NP; pq++) dep[pq] += e0[pq] - e1[pq];
         if (dep0 && k == 0)
@@ -708,11 +1031,10 @@ static void og_energy_all_rec(const og_grid *g, const og_tab *t, const double *r
  * state: ngen generations; on entry generation 0 holds the initial state,
  * the others zero; on exit the state after the last step.
  */
-void og_run(const og_grid *g, const double *E_face, const double *E_mid, const double *dE, const double *S_face,
-            const double *sig_tr, const double *kappa, const double *P1, const double *P2, const double *rho,
-            double *state, double *dose)
+void og_run(const og_grid *g, const og_tab *tp, const double *rho, double *state, double *dose)
 {
-    og_tab t = {E_face, E_mid, dE, S_face, sig_tr, kappa, P1, P2};
+    og_tab t = *tp;
+    const double *sig_tr = t.sig_tr;
     long E = og_gen_elems(g), NP = og_np(g);
     double dz = g->dz, vol = og_dx(g) * og_dy(g) * g->dz;
     double *dep = malloc(sizeof(double) * NP);
@@ -735,11 +1057,11 @@ void og_run(const og_grid *g, const double *E_face, const double *E_mid, const d
  *   1, 2: energy and number content of generation 0 after the first E half-step of layer s,
  *   3: deposit of generation 0 alone in layer s (MeV).
  */
-void og_run_records(const og_grid *g, const double *E_face, const double *E_mid, const double *dE,
-                    const double *S_face, const double *sig_tr, const double *kappa, const double *P1,
-                    const double *P2, const double *rho, double *state, double *dose, double *rec)
+void og_run_records(const og_grid *g, const og_tab *tp, const double *rho, double *state, double *dose,
+                    double *rec)
 {
-    og_tab t = {E_face, E_mid, dE, S_face, sig_tr, kappa, P1, P2};
+    og_tab t = *tp;
+    const double *sig_tr = t.sig_tr, *E_mid = t.E_mid, *dE = t.dE;
     long E = og_gen_elems(g), NP = og_np(g), L = (long)g->nz * NP;
     double dz = g->dz, vol = og_dx(g) * og_dy(g) * g->dz;
     double *dep = malloc(sizeof(double) * NP);
@@ -762,10 +1084,7 @@ void og_run_records(const og_grid *g, const double *E_face, const double *E_mid,
 }
 
 /* Exposed for tests: one E half-step over all generations with deposit. */
-void og_energy_all_api(const og_grid *g, const double *E_face, const double *E_mid, const double *dE,
-                       const double *S_face, const double *sig_tr, const double *kappa, const double *P1,
-                       const double *P2, const double *rho, double h, double *state, double *dep)
+void og_energy_all_api(const og_grid *g, const og_tab *t, const double *rho, double h, double *state, double *dep)
 {
-    og_tab t = {E_face, E_mid, dE, S_face, sig_tr, kappa, P1, P2};
-    og_energy_all(g, &t, rho, h, state, dep);
+    og_energy_all(g, t, rho, h, state, dep);
 }

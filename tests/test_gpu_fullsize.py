@@ -1,0 +1,175 @@
+"""Parity of the full-size kernel paths with the FP64 oracle, element by element and per generation.
+
+The lateral grid is a window of configuration 2 (8 x 64 cells of 0.125 cm, so the transport sweep is
+the 64-lane row-affine kernel), with configuration 2's full angular and energy grids (32 x 32 nodes over
++-0.15 rad: the MFMA angular pass and the full-tile source product; 128 groups on [0, 160] MeV), four
+generations (K = 3) and its depth step (0.06 cm).  Densities are seeded per cell between lung (0.26) and
+bone (1.85).
+
+Checked against the oracle (section 3.3's Strang sequence, section 3.2's energy operator eq:(0041-d) with
+the source of the Remark after the scheme, section 3.4's transport and angular operators):
+  * the E, T and A sub-steps on a random state of all generations, in FP64 and in FP32 with each
+    arithmetic of the source product;
+  * a two-step march from the beam of eq:(bdy), with the dose.
+Bound per generation k: max |got - ref| <= tol * max |ref_k|.  FP64: 1e-12.  FP32 with the FP32 source
+product, and every generation whose update carries no low-precision source: 1e-5 (a few hundred FP32
+roundings along a line).  The scattered generations of the split-BF16 source modes in the march are
+made of the source alone, so their bound is the source's own rounding (derived in the test below).
+"""
+import numpy as np
+import pytest
+
+from paper_2504_00340_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+NX, NY, NTH, NG, NGEN = 8, 64, 32, 128, 4
+DZ = 0.06
+
+
+def _cfg(nz, seed):
+    g = I.grid(NX, NY, NTH, NG, nz, NGEN, NX * 0.0625, NY * 0.0625, 0.15, 0.0, 160.0, nz * DZ)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho = rng.uniform(I.RHO_LUNG, I.RHO_BONE, size=(nz, NX, NY))
+    return dict(grid=g, beam=I.beam(150.0), phys=dict(I.PHYS), rho=rho)
+
+
+SRC_MODES = ["fp32", "bf16x3", "bf16x1"]
+
+
+def _solver(c, prec, src=None):
+    from paper_2504_00340_amd import pbsplit as P
+
+    s = P.Solver(c["grid"], c["phys"], precision=prec)
+    if src is not None:
+        s.set_source_precision({"fp32": P.PBS_SRC_FP32, "bf16x3": P.PBS_SRC_BF16X3,
+                                "bf16x1": P.PBS_SRC_BF16X1}[src])
+    s.set_phantom(c["rho"])
+    s.set_beam(c["beam"])
+    return s
+
+
+def _gen_err(got, ref):
+    """Per generation: max |got - ref| / max |ref_k| and the worst index."""
+    out = []
+    for k in range(ref.shape[0]):
+        d = np.abs(got[k] - ref[k])
+        i = int(np.argmax(d))
+        out.append((float(d.flat[i] / max(np.abs(ref[k]).max(), 1e-300)), np.unravel_index(i, ref[k].shape)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def substep_refs(O):
+    """Oracle results of the three sub-steps on one random state (computed once)."""
+    c = _cfg(3, 11)
+    o = O.Oracle(c["grid"], c["phys"])
+    shape = (NGEN,) + o.gen_shape
+    st = I.random_state(shape, 1234)
+    st[:, :, 1] *= 0.3
+    rho = np.ascontiguousarray(c["rho"][1].reshape(-1))
+    refs = {}
+    for op, h in (("T", 0.5 * DZ), ("A", DZ), ("E", 0.5 * DZ)):
+        ref = st.copy()
+        print("oracle sub-step", op, flush=True)
+        if op == "T":
+            for k in range(NGEN):
+                o.transport_cn(ref[k], h)
+            refs[op] = (h, ref, None)
+        elif op == "A":
+            for k in range(NGEN):
+                o.angular_cn(ref[k], rho, h)
+            refs[op] = (h, ref, None)
+        else:
+            dep = o.energy_all(ref, rho, h)
+            refs[op] = (h, ref, dep / (rho * o.dx * o.dy * c["grid"]["dz"]))
+    return c, st, refs
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("prec,src", [("fp64", None)] + [("fp32", m) for m in SRC_MODES])
+def test_fullsize_substeps_match_oracle(substep_refs, prec, src):
+    c, st, refs = substep_refs
+    print("case full-size window sub-steps", prec, src, flush=True)
+    s = _solver(c, prec, src)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    for op, code in (("T", 2), ("A", 3), ("E", 1)):
+        h, ref, dose_ref = refs[op]
+        if op == "E":
+            s.set_beam(c["beam"])          # zero the dose
+        s.set_state(st)
+        s.apply(code, 1, h)
+        got = s.state()
+        errs = _gen_err(got, ref)
+        print(op, prec, src, "per-generation max error / max|ref|:",
+              ", ".join(f"k{k} {e:.2e} at {idx}" for k, (e, idx) in enumerate(errs)), flush=True)
+        for k, (e, idx) in enumerate(errs):
+            assert e <= tol, (op, k, e, idx)
+        if dose_ref is not None:
+            d = s.dose()[1].reshape(-1)
+            de = float(np.abs(d - dose_ref).max() / np.abs(dose_ref).max())
+            print(op, prec, src, f"dose max error / max dose {de:.2e}", flush=True)
+            assert de <= tol
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def march_ref(O):
+    # the oracle applies every step unfused (E/2 T A T E/2), so two one-step runs on the same state are the
+    # two-step march; one call per step keeps the progress output flowing
+    c = _cfg(2, 12)
+    o1 = O.Oracle(dict(c["grid"], nz=1), c["phys"])
+    fin = o1.initial(c["beam"])
+    dose = []
+    for s in range(2):
+        print("oracle march of the full-size window, step", s, flush=True)
+        d, fin = o1.run(c["beam"], c["rho"][s:s + 1], state=fin)
+        dose.append(d[0])
+    return c, np.stack(dose), fin
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("prec,src", [("fp64", None)] + [("fp32", m) for m in SRC_MODES])
+def test_fullsize_march_matches_oracle(march_ref, prec, src):
+    """Two depth steps from the beam: every kernel of a step (fused energy pass with the source of three
+    scattered generations, source products, transport, angular pass, dose reduction).
+
+    Bounds.  FP64: 1e-12 per generation.  FP32: the primaries carry no source, 1e-5; with the FP32 source
+    product every generation 1e-5.  In the split-BF16 modes a scattered generation that starts at zero is
+    made of the source alone.  With the scanned fluence W rounded once to BF16 (relative error <= 2^-9)
+    and the transfer matrix P2 either split hi + lo (error <= 2^-16, three products) or rounded with
+    compensated columns (a moved entry is at most 1.5 BF16 ulp from its value: <= 1.5 * 2^-8), every
+    product sum_a' P2[a, a'] W[a'] of non-negative terms is off by at most (2^-9 + eps_P) of its value.
+    The bound used is that sum (1e-4 for three products, 8e-3 for one) relative to max |ref_k|; the dose,
+    which the scattered generations enter with a small weight, must stay within 1e-4 (rel-L2) in every
+    mode, the bar the FP32 path is held to."""
+    c, dref, fref = march_ref
+    print("case full-size window march", prec, src, flush=True)
+    s = _solver(c, prec, src)
+    s.run()
+    dose = s.dose()
+    got = s.state()
+    s.close()
+    errs = _gen_err(got, fref)
+    drel = float(np.linalg.norm(dose - dref) / np.linalg.norm(dref))
+    dmax = float(np.abs(dose - dref).max() / np.abs(dref).max())
+    print("march", prec, src, "per-generation max error / max|ref|:",
+          ", ".join(f"k{k} {e:.2e} at {idx}" for k, (e, idx) in enumerate(errs)),
+          f"; dose rel-L2 {drel:.2e}, max {dmax:.2e}", flush=True)
+    if prec == "fp64":
+        tols = [1e-12] * NGEN
+        dtol = 1e-12
+    else:
+        scat = {"fp32": 1e-5, "bf16x3": 1e-4, "bf16x1": 8e-3}[src]
+        tols = [1e-5] + [scat] * (NGEN - 1)
+        dtol = 1e-4
+    for k, (e, idx) in enumerate(errs):
+        assert e <= tols[k], (k, e, idx)
+    assert drel <= dtol and dmax <= dtol
