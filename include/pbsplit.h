@@ -117,6 +117,21 @@ pbs_status pbs_workspace_bytes(const pbs_ctx *ctx, size_t *bytes);
  * bind; rebinding invalidates phantom, beam and dose. */
 pbs_status pbs_bind(pbs_ctx *ctx, void *dev_workspace, size_t bytes, void *hip_stream);
 
+/* Allocation-free variant of pbs_bind, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): binds the context to a scratch
+ * array that the library holds in device memory, PBS_STATIC_SCRATCH_BYTES (64 MiB) per GPU, kept until
+ * the process ends, and to hip_stream (hipStream_t on the current device, NULL = the null stream).  It
+ * calls no hipMalloc, hipFree or other allocating routine and creates no stream or event, so the
+ * context always marches on its one stream (pbs_set_schedule has no effect on it).  Returns PBS_EINVAL
+ * (with the sizes in pbs_last_error) when pbs_workspace_bytes exceeds the scratch, PBS_EDEVICE when
+ * the scratch's address cannot be obtained.
+ * Every context bound this way on one GPU shares that GPU's scratch, which keeps the last call's
+ * contents (pbs_set_beam clears what must start at zero).  Binding another context to it invalidates
+ * the previous one: its later calls return PBS_ESTATE.  Calls of two such contexts that overlap in time
+ * on one GPU race.  Results are bitwise those of a context bound with pbs_bind. */
+#define PBS_STATIC_SCRATCH_BYTES (64u << 20)
+pbs_status pbs_bind_static(pbs_ctx *ctx, void *hip_stream);
+
 /* Densities rho[s][p][q] (g/cm^3) on the computational grid, host array of
  * nz*nx*ny doubles, C order.  Every value must be finite and > 0 (else
  * PBS_EINVAL).  Copied; the caller keeps ownership. */

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpbsplit.so")
-SOURCES = ["pbs_api.hip", "pbs_batch.hip", "pbs_kernels.hip", "pbs_net.hip"]
+SOURCES = ["pbs_api.hip", "pbs_batch.hip", "pbs_kernels.hip", "pbs_net.hip", "pbs_static.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -660,8 +660,9 @@ pbs_status one_step(pbs_ctx *c)
 {
     const int s = c->step;
     const double dz = c->g.dz;
-    const bool ovl = c->sched == PBS_SCHED_TWO_STREAMS ||
-                     (c->sched == PBS_SCHED_AUTO && (long)c->NP * c->NA * c->G() < PBS_OVERLAP_CELLS);
+    // a context without the side stream (bound to the static scratch) always marches on one stream
+    const bool ovl = c->side && (c->sched == PBS_SCHED_TWO_STREAMS ||
+                                 (c->sched == PBS_SCHED_AUTO && (long)c->NP * c->NA * c->G() < PBS_OVERLAP_CELLS));
     const int tat = ovl ? s : -1;
     pbs_status r = (s == 0) ? energy_chain<T>(c, MODE_OPEN, -1, 0, 0.5 * dz, tat)
                             : energy_chain<T>(c, MODE_PAIR, s - 1, s, 0.5 * dz, tat);
@@ -874,6 +875,46 @@ pbs_status run_surrogate(pbs_ctx *c)
 
 }  // namespace
 
+namespace pbs {
+// Bind a workspace (caller memory or the static scratch) and a stream: uploads the tables (and the packed
+// surrogate weights).  with_side: create the side stream and events of the two-stream march; without it
+// the context always marches on its one stream and creates no HIP objects here.
+pbs_status bind_workspace(pbs_ctx *c, char *ws, size_t bytes, hipStream_t stream, bool with_side)
+{
+    c->ws = ws;
+    c->ws_bytes = bytes;
+    c->stream = stream;
+    if (with_side && !c->side) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        const int ng = c->g.ngen;
+        c->ev_e.assign(ng, nullptr);
+        c->ev_tat.assign(ng, nullptr);
+        for (int k = 0; k < ng; ++k) {
+            HIPCHK(c, hipEventCreateWithFlags(&c->ev_e[k], hipEventDisableTiming));
+            HIPCHK(c, hipEventCreateWithFlags(&c->ev_tat[k], hipEventDisableTiming));
+        }
+    }
+    c->tat_pend.assign(c->g.ngen, 0);
+    c->state = ST_CREATED;
+    pbs_status r = DISPATCH(c, upload_tables, c);
+    if (r != PBS_OK) return r;
+    if (c->sur == 2) {
+        float *m = reinterpret_cast<float *>(c->ws + c->o_smaster);
+        NetPacked P;
+        net_carve(c->ws + c->o_spk, P);
+        HIPCHK(c, hipMemcpyAsync(m, c->sur_params.data(), c->sur_params.size() * sizeof(float), hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, net_pack(m, P, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->state = ST_BOUND;
+    return PBS_OK;
+}
+
+pbs_status ctx_fail(pbs_ctx *c, pbs_status st, const char *msg) { return fail(c, st, msg); }
+}  // namespace pbs
+
+
 // =================================================================================== C ABI
 extern "C" {
 
@@ -950,39 +991,15 @@ pbs_status pbs_bind(pbs_ctx *c, void *ws, size_t bytes, void *stream)
     if (!c) return PBS_EINVAL;
     if (!ws || ((uintptr_t)ws & 255)) return fail(c, PBS_EINVAL, "workspace is NULL or not 256-byte aligned");
     if (bytes < c->total) return fail(c, PBS_EINVAL, "workspace too small");
-    c->ws = (char *)ws;
-    c->ws_bytes = bytes;
-    c->stream = (hipStream_t)stream;
-    if (!c->side) {
-        HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-        const int ng = c->g.ngen;
-        c->ev_e.assign(ng, nullptr);
-        c->ev_tat.assign(ng, nullptr);
-        c->tat_pend.assign(ng, 0);
-        for (int k = 0; k < ng; ++k) {
-            HIPCHK(c, hipEventCreateWithFlags(&c->ev_e[k], hipEventDisableTiming));
-            HIPCHK(c, hipEventCreateWithFlags(&c->ev_tat[k], hipEventDisableTiming));
-        }
-    }
-    c->state = ST_CREATED;
-    pbs_status r = DISPATCH(c, upload_tables, c);
-    if (r != PBS_OK) return r;
-    if (c->sur == 2) {
-        float *m = reinterpret_cast<float *>(c->ws + c->o_smaster);
-        NetPacked P;
-        net_carve(c->ws + c->o_spk, P);
-        HIPCHK(c, hipMemcpyAsync(m, c->sur_params.data(), c->sur_params.size() * sizeof(float), hipMemcpyHostToDevice,
-                                 c->stream));
-        HIPCHK(c, net_pack(m, P, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-    }
-    c->state = ST_BOUND;
-    return PBS_OK;
+    c->static_dev = -1;
+    return pbs::bind_workspace(c, (char *)ws, bytes, (hipStream_t)stream, true);
 }
 
 pbs_status pbs_set_phantom(pbs_ctx *c, const double *rho, size_t n)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (c->state < ST_BOUND) return fail(c, PBS_ESTATE, "set_phantom before bind");
     if (!rho || n != (size_t)c->g.nz * c->NP) return fail(c, PBS_EINVAL, "phantom size must be nz*nx*ny");
     for (size_t i = 0; i < n; ++i)
@@ -997,6 +1014,8 @@ pbs_status pbs_set_phantom(pbs_ctx *c, const double *rho, size_t n)
 pbs_status pbs_set_beam(pbs_ctx *c, const pbs_beam *b)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (c->state < ST_PHANTOM) return fail(c, PBS_ESTATE, "set_beam before set_phantom");
     if (!b) return fail(c, PBS_EINVAL, "beam is NULL");
     if (!std::isfinite(b->e0) || !finite_pos(b->sigma_e) || !std::isfinite(b->x0) || !std::isfinite(b->y0) ||
@@ -1017,6 +1036,8 @@ pbs_status pbs_set_beam(pbs_ctx *c, const pbs_beam *b)
 pbs_status pbs_step_depth(pbs_ctx *c, int n, int *step_out)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "step_depth before set_beam");
     if (c->closed) return fail(c, PBS_ESTATE, "beam already finished by run_beam");
     if (c->sur == 2) return fail(c, PBS_ESTATE, "a surrogate context marches whole beams (pbs_run_beam)");
@@ -1031,6 +1052,8 @@ pbs_status pbs_step_depth(pbs_ctx *c, int n, int *step_out)
 pbs_status pbs_run_beam(pbs_ctx *c)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "run_beam before set_beam");
     if (c->closed) return fail(c, PBS_ESTATE, "beam already finished by run_beam");
     pbs_status r;
@@ -1089,6 +1112,8 @@ pbs_status pbs_set_surrogate(pbs_ctx *c, const void *weights, size_t bytes, doub
 pbs_status pbs_surrogate_sample(pbs_ctx *c, void *dev_x, float *dev_t, size_t n_slices)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (c->sur != 1) return fail(c, PBS_ESTATE, "sample needs a context in recording mode");
     if (c->state < ST_BEAM || !c->closed) return fail(c, PBS_ESTATE, "sample before run_beam");
     if (!dev_x || !dev_t || ((uintptr_t)dev_x & 15) || ((uintptr_t)dev_t & 15))
@@ -1101,6 +1126,8 @@ pbs_status pbs_surrogate_sample(pbs_ctx *c, void *dev_x, float *dev_t, size_t n_
 pbs_status pbs_surrogate_records(pbs_ctx *c, double *out, size_t n)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (!c->sur) return fail(c, PBS_ESTATE, "no surrogate records without pbs_set_surrogate");
     if (c->state < ST_BEAM || !c->closed) return fail(c, PBS_ESTATE, "records before run_beam");
     if (!out || n != (size_t)4 * c->g.nz * c->NP) return fail(c, PBS_EINVAL, "records buffer must hold 4*nz*nx*ny");
@@ -1112,6 +1139,8 @@ pbs_status pbs_surrogate_records(pbs_ctx *c, double *out, size_t n)
 pbs_status pbs_surrogate_report(pbs_ctx *c, double *out, int n)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (!c->sur) return fail(c, PBS_ESTATE, "no surrogate report without pbs_set_surrogate");
     if (c->state < ST_BEAM || !c->closed) return fail(c, PBS_ESTATE, "report before run_beam");
     if (!out || n < 0 || n > 10) return fail(c, PBS_EINVAL, "report holds at most 10 values");
@@ -1132,6 +1161,8 @@ pbs_status pbs_surrogate_report(pbs_ctx *c, double *out, int n)
 pbs_status pbs_get_dose(pbs_ctx *c, double *out, size_t n, int out_is_device)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "get_dose before set_beam");
     const size_t tot = (size_t)c->g.nz * c->NP;
     if (!out || n != tot) return fail(c, PBS_EINVAL, "dose buffer must hold nz*nx*ny doubles");
@@ -1148,6 +1179,8 @@ pbs_status pbs_get_dose(pbs_ctx *c, double *out, size_t n, int out_is_device)
 pbs_status pbs_get_state(pbs_ctx *c, double *out, size_t n)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "get_state before set_beam");
     if (!out || n != (size_t)c->g.ngen * c->G() * 2 * c->NA * c->NP) return fail(c, PBS_EINVAL, "bad state size");
     return DISPATCH(c, get_state, c, out);
@@ -1156,6 +1189,8 @@ pbs_status pbs_get_state(pbs_ctx *c, double *out, size_t n)
 pbs_status pbs_set_state(pbs_ctx *c, const double *in, size_t n)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "set_state before set_beam");
     if (!in || n != (size_t)c->g.ngen * c->G() * 2 * c->NA * c->NP) return fail(c, PBS_EINVAL, "bad state size");
     for (size_t i = 0; i < n; ++i)
@@ -1166,6 +1201,8 @@ pbs_status pbs_set_state(pbs_ctx *c, const double *in, size_t n)
 pbs_status pbs_apply(pbs_ctx *c, int op, int layer, double h)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (c->state < ST_BEAM) return fail(c, PBS_ESTATE, "apply before set_beam");
     if (layer < 0 || layer >= c->g.nz || !std::isfinite(h) || h < 0) return fail(c, PBS_EINVAL, "bad layer or h");
     switch (op) {
@@ -1199,6 +1236,8 @@ pbs_status pbs_set_schedule(pbs_ctx *c, int mode)
 pbs_status pbs_profile(pbs_ctx *c, int enable)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (c->state < ST_BOUND) return fail(c, PBS_ESTATE, "profile before bind");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->ev_pairs.clear();
@@ -1210,6 +1249,8 @@ pbs_status pbs_profile(pbs_ctx *c, int enable)
 pbs_status pbs_profile_read(pbs_ctx *c, double *ms, long *launches, int n)
 {
     if (!c) return PBS_EINVAL;
+    if (c->static_dev >= 0 && pbs::static_lost(c))
+        return fail(c, PBS_ESTATE, "another context has been bound to this device's static scratch since");
     if (!ms || !launches || n < 0) return fail(c, PBS_EINVAL, "bad profile buffers");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int k = 0; k < n; ++k) {

@@ -13,7 +13,14 @@ enum { ST_CREATED = 0, ST_BOUND = 1, ST_PHANTOM = 2, ST_BEAM = 3 };
 constexpr int PBS_DEFAULT_SRC = PBS_SRC_BF16X1;
 inline int src_nprod(int mode) { return mode == PBS_SRC_BF16X1 ? 1 : mode == PBS_SRC_BF16X2 ? 2 : 3; }
 
+struct pbs_ctx;
 namespace pbs {
+// bind a workspace and a stream (uploads the tables); with_side creates the two-stream march's stream and events
+pbs_status bind_workspace(pbs_ctx *c, char *ws, size_t bytes, hipStream_t stream, bool with_side);
+// record an error on the context and return st
+pbs_status ctx_fail(pbs_ctx *c, pbs_status st, const char *msg);
+// true when another context has been bound to the static scratch of c's device since c was
+bool static_lost(const pbs_ctx *c);
 // split-BF16 transfer matrix [3][Mp][Kpb]: hi, lo, and a column-compensated single-BF16 copy
 void transfer_table_bf16(const std::vector<double> &P2T, int NA, int Mp, int Kpb, std::vector<unsigned short> &out);
 }  // namespace pbs
@@ -53,6 +60,10 @@ struct pbs_ctx {
     size_t d_A, d_B, d_Inj, d_E1, d_E2, d_lat, d_count;
     int state = ST_CREATED;
     int step = 0;
+    // bound to the static scratch of device static_dev (-1: caller workspace) when the scratch's owner
+    // count of that device was static_epoch
+    int static_dev = -1;
+    unsigned long long static_epoch = 0;
     bool closed = false;
     std::vector<double> rho_host;
     std::string err;

@@ -31,7 +31,8 @@ EXPORTS = ["pbs_create", "pbs_workspace_bytes", "pbs_bind", "pbs_set_phantom", "
            "pbs_batch_last_error", "pbs_batch_destroy", "pbs_set_surrogate", "pbs_surrogate_sample",
            "pbs_surrogate_records", "pbs_surrogate_report", "pbs_net_param_count", "pbs_net_create",
            "pbs_net_workspace_bytes", "pbs_net_bind", "pbs_net_set_params", "pbs_net_get_params", "pbs_net_forward",
-           "pbs_net_gradient", "pbs_net_train_step", "pbs_net_last_error", "pbs_net_destroy"]
+           "pbs_net_gradient", "pbs_net_train_step", "pbs_net_last_error", "pbs_net_destroy", "pbs_bind_static"]
+PBS_STATIC_SCRATCH_BYTES = 64 << 20
 _NORET = ("pbs_last_error", "pbs_destroy", "pbs_batch_last_error", "pbs_batch_destroy", "pbs_net_last_error",
           "pbs_net_destroy")
 PBS_NET_MAGIC, PBS_NET_VERSION, PBS_NET_CIN, SUR_NFEAT = 0x4E534250, 1, 8, 8
@@ -78,6 +79,7 @@ def lib():
         L.pbs_create.argtypes = [C.POINTER(Grid), C.POINTER(Physics), C.c_int, C.POINTER(vp)]
         L.pbs_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
         L.pbs_bind.argtypes = [vp, vp, sz, vp]
+        L.pbs_bind_static.argtypes = [vp, vp]
         L.pbs_set_phantom.argtypes = [vp, D, sz]
         L.pbs_set_beam.argtypes = [vp, C.POINTER(Beam)]
         L.pbs_step_depth.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
@@ -178,10 +180,13 @@ class Solver:
     """One libpbsplit context bound to a torch-allocated workspace on `device`.
 
     surrogate: None, "record" (plain march that keeps the per-slice surrogate records) or a weights
-    blob (bytes) for the surrogate of generation 1 with fallback at residual_tol."""
+    blob (bytes) for the surrogate of generation 1 with fallback at residual_tol.
+    static_scratch: bind to the library's own device scratch (pbs_bind_static) instead of a torch
+    workspace; nothing is allocated on the device."""
 
     def __init__(self, grid: dict, phys: dict, precision: str = "fp32", device="cuda:0", stream=None,
-                 surrogate=None, residual_tol: float = 1e-2):
+                 surrogate=None, residual_tol: float = 1e-2, static_scratch: bool = False):
+
         import torch
 
         self.torch = torch
@@ -206,12 +211,18 @@ class Solver:
         self._check(self.L.pbs_workspace_bytes(self.ctx, C.byref(nb)))
         self.ws_bytes = nb.value
         self.device = torch.device(device)
-        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self._ws.data_ptr()
-        self.ws_ptr = base + ((256 - base % 256) % 256)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self._check(self.L.pbs_bind(self.ctx, C.c_void_p(self.ws_ptr), self.ws_bytes,
-                                    C.c_void_p(self.stream.cuda_stream)))
+        if static_scratch:
+            self._ws = None
+            self.ws_ptr = None
+            with torch.cuda.device(self.device):
+                self._check(self.L.pbs_bind_static(self.ctx, C.c_void_p(self.stream.cuda_stream)))
+        else:
+            self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            base = self._ws.data_ptr()
+            self.ws_ptr = base + ((256 - base % 256) % 256)
+            self._check(self.L.pbs_bind(self.ctx, C.c_void_p(self.ws_ptr), self.ws_bytes,
+                                        C.c_void_p(self.stream.cuda_stream)))
         m = grid["nth"] - 1
         self.NA = m * m
         self.NP = grid["nx"] * grid["ny"]
