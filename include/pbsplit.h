@@ -223,7 +223,12 @@ pbs_status pbs_batch_workspace_bytes(const pbs_batch *batch, size_t *bytes);
 pbs_status pbs_batch_bind(pbs_batch *batch, void *dev_workspace, size_t bytes, void *hip_stream);
 /* Densities of one beam's grid, [nz][nx][ny] doubles (finite, > 0); copied. */
 pbs_status pbs_batch_set_phantom(pbs_batch *batch, int beam, const double *rho, size_t n);
-/* March every beam to its end (closing energy half-step included); synchronises the stream. */
+/* Choose the launch variants (timing on the first wave) and capture every wave's march into a HIP graph,
+ * once; later runs replay the graphs.  Optional: pbs_batch_run does it on its first call.  Needs every
+ * phantom set; synchronises the stream. */
+pbs_status pbs_batch_prepare(pbs_batch *batch);
+/* March every beam to its end (closing energy half-step included); synchronises the stream.  Per wave:
+ * upload tables, densities and the initial fluence of its beams, replay the wave's graph. */
 pbs_status pbs_batch_run(pbs_batch *batch);
 /* Dose of one beam, [nz][nx][ny] FP64 host array (MeV/g per incident proton). */
 pbs_status pbs_batch_get_dose(pbs_batch *batch, int beam, double *out, size_t n);
@@ -326,7 +331,8 @@ void pbs_net_destroy(pbs_net *net);
 /* Text of the last error of this context (never NULL). */
 const char *pbs_last_error(const pbs_ctx *ctx);
 
-/* Release the context (host memory only; the workspace stays the caller's). */
+/* Release the context: waits for the work it enqueued on its stream, then frees host memory only (the
+ * workspace stays the caller's). */
 void pbs_destroy(pbs_ctx *ctx);
 
 #ifdef __cplusplus

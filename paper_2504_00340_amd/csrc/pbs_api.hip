@@ -55,12 +55,13 @@ double bf16_val(unsigned short h)
 }  // namespace
 
 // The transfer matrix for the split-BF16 source product, [3][Mp][Kpb] zero-padded, row = destination:
-// hi = bf16(P2), lo = bf16(P2 - hi), and a single-BF16 copy whose columns are compensated so that
-// each column (one source node) still sums to its exact total: starting from bf16(P2), entries are
-// moved by one BF16 ulp at a time, each time the entry whose ulp best reduces the residual, until
-// the residual is below 1e-7 of the total (or no step reduces it).  Without the compensation the
-// rounding of this fixed table would bias the number of re-emitted protons the same way in every
-// cell and group.
+// hi = bf16(P2), lo = bf16(P2 - hi), and a single-BF16 copy whose columns keep their exact sums (the
+// number of re-emitted protons of one source node): every entry lies between two neighbouring BF16
+// values and starts at the nearer one; entries are then moved to their other neighbour, each at most
+// once, in the order that costs the least extra rounding error relative to the entry (the ones whose
+// value lies closest to the midpoint first), while each move brings the column sum closer to its exact
+// total.  Every entry stays within one BF16 ulp of its value.  Without the compensation the rounding
+// of this fixed table would bias the number of re-emitted protons the same way in every cell and group.
 void transfer_table_bf16(const std::vector<double> &P2T, int NA, int Mp, int Kpb, std::vector<unsigned short> &out)
 {
     const size_t MK = (size_t)Mp * Kpb;
@@ -73,6 +74,13 @@ void transfer_table_bf16(const std::vector<double> &P2T, int NA, int Mp, int Kpb
             out[MK + (size_t)a * Kpb + k] = bf16_rne((float)(x - bf16_val(hi)));
             out[2 * MK + (size_t)a * Kpb + k] = hi;
         }
+    struct Move {
+        double cost, step;
+        int a;
+        unsigned short to;
+    };
+    std::vector<Move> mv;
+    std::vector<char> used(NA);
     for (int k = 0; k < NA; ++k) {
         double target = 0.0, cur = 0.0;
         for (int a = 0; a < NA; ++a) {
@@ -80,29 +88,34 @@ void transfer_table_bf16(const std::vector<double> &P2T, int NA, int Mp, int Kpb
             cur += bf16_val(out[2 * MK + (size_t)a * Kpb + k]);
         }
         double r = target - cur;
-        for (int it = 0; it < 256 && std::fabs(r) > 1e-7 * std::fabs(target); ++it) {
-            int best = -1;
-            double bestr = std::fabs(r), bstep = 0.0;
+        std::fill(used.begin(), used.end(), 0);
+        // rounds of moves in the direction of the residual; a move that overshoots flips the direction
+        for (int round = 0; round < 64 && std::fabs(r) > 1e-7 * std::fabs(target); ++round) {
+            mv.clear();
+            const bool up = r > 0;
             for (int a = 0; a < NA; ++a) {
+                if (used[a]) continue;
+                const double x = P2T[(size_t)a * NA + k];
                 const unsigned short h = out[2 * MK + (size_t)a * Kpb + k];
                 const double v = bf16_val(h);
-                if (!(v > 0.0)) continue;
-                // the neighbouring BF16 value in the direction of the residual (positive entries only)
-                const unsigned short hn = r > 0 ? (unsigned short)(h + 1) : (unsigned short)(h - 1);
+                if (!(x > 0.0) || !(v > 0.0)) continue;
+                const unsigned short hn = up ? (unsigned short)(h + 1) : (unsigned short)(h - 1);
                 const double vn = bf16_val(hn);
                 if (!(vn > 0.0) || !std::isfinite(vn)) continue;
-                const double step = vn - v;
-                const double nr = std::fabs(r - step);
-                if (nr < bestr) {
-                    bestr = nr;
-                    best = a;
-                    bstep = step;
-                }
+                if (up ? !(vn >= x) : !(vn <= x)) continue;   // x must lie between v and its other neighbour
+                mv.push_back({(std::fabs(vn - x) - std::fabs(v - x)) / x, vn - v, a, hn});
             }
-            if (best < 0) break;
-            unsigned short &h = out[2 * MK + (size_t)best * Kpb + k];
-            h = r > 0 ? (unsigned short)(h + 1) : (unsigned short)(h - 1);
-            r -= bstep;
+            std::sort(mv.begin(), mv.end(), [](const Move &p, const Move &q) { return p.cost < q.cost; });
+            bool moved = false;
+            for (const Move &m : mv) {
+                if (!(std::fabs(r - m.step) < std::fabs(r))) continue;
+                out[2 * MK + (size_t)m.a * Kpb + k] = m.to;
+                used[m.a] = 1;
+                r -= m.step;
+                moved = true;
+                if ((r > 0) != up || !(std::fabs(r) > 1e-7 * std::fabs(target))) break;
+            }
+            if (!moved) break;
         }
     }
 }
@@ -914,7 +927,6 @@ pbs_status bind_workspace(pbs_ctx *c, char *ws, size_t bytes, hipStream_t stream
 pbs_status ctx_fail(pbs_ctx *c, pbs_status st, const char *msg) { return fail(c, st, msg); }
 }  // namespace pbs
 
-
 // =================================================================================== C ABI
 extern "C" {
 
@@ -1276,6 +1288,9 @@ const char *pbs_last_error(const pbs_ctx *c)
 void pbs_destroy(pbs_ctx *c)
 {
     if (!c) return;
+    // work enqueued by step_depth / run_beam may still write the workspace: finish it before the caller
+    // can release that memory
+    if (c->ws) (void)hipStreamSynchronize(c->stream);
     if (c->side) (void)hipStreamSynchronize(c->side);
     for (hipEvent_t e : c->ev_e)
         if (e) (void)hipEventDestroy(e);

@@ -6,7 +6,8 @@
 // launched as one graph launch.  Every kernel of a step covers all beams of the wave; blocks of
 // beams that are done exit at once.  A small autotuner times bitwise-neutral launch variants
 // (source-product tile width, transport waves per block, angular cells per block) on the first
-// wave and keeps the fastest.
+// wave and keeps the fastest.  Tuning and capture happen once (pbs_batch_prepare, or the first run);
+// later runs only set up each wave's state and replay its graph.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -55,6 +56,9 @@ struct pbs_batch {
     std::vector<char> have_rho;
     BatchTuning tune;
     bool tuned = false;
+    // per wave: the whole march captured once (for the tuning chosen) and instantiated; replayed by every run
+    std::vector<hipGraph_t> graphs;
+    std::vector<hipGraphExec_t> execs;
     int state = 0;   // 0 created, 1 bound, 2 done
     std::string err;
 };
@@ -297,6 +301,82 @@ pbs_status autotune(pbs_batch *b, int nw, int maxG)
     return PBS_OK;
 }
 
+int wave_max(const pbs_batch *b, const std::vector<int> &w, bool groups)
+{
+    int v = 0;
+    for (int beam : w) v = std::max(v, groups ? b->grids[beam].ng : b->grids[beam].nz);
+    return v;
+}
+
+// The whole march of wave wi captured into one graph and instantiated.  The kernels read the beam
+// descriptors of the wave region at run time, so the graph serves every run (setup_wave writes them).
+pbs_status capture_wave(pbs_batch *b, size_t wi)
+{
+    const std::vector<int> &w = b->waves[wi];
+    const int maxG = wave_max(b, w, true), maxnz = wave_max(b, w, false);
+    BatchTuning t = b->tune;
+    t.max_nz = maxnz;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+    const BeamDev *bd = reinterpret_cast<const BeamDev *>(b->ws + b->o_beams);
+    const BatchShape Sh = shape(b);
+    hipError_t le = hipSuccess;
+    BatchSide sd{b->side, b->ev_e.data(), b->ev_tat.data(), b->pend.data()};
+    for (int k = 0; k < b->ngen; ++k) b->pend[k] = 0;
+    for (int s = 0; s <= maxnz && le == hipSuccess; ++s)
+        le = launch_batch_step(bd, (int)w.size(), Sh, s, maxG, t, b->stream, &sd);
+    // join the side stream before the capture ends
+    for (int k = 0; k < b->ngen; ++k)
+        if (b->pend[k]) {
+            const hipError_t je = hipStreamWaitEvent(b->stream, b->ev_tat[k], 0);
+            if (le == hipSuccess) le = je;
+            b->pend[k] = 0;
+        }
+    const hipError_t ce = hipStreamEndCapture(b->stream, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return bfail(b, PBS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return bfail(b, PBS_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    }
+    b->graphs[wi] = graph;
+    b->execs[wi] = exec;
+    return PBS_OK;
+}
+
+void drop_graphs(pbs_batch *b)
+{
+    for (hipGraphExec_t e : b->execs)
+        if (e) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t g : b->graphs)
+        if (g) (void)hipGraphDestroy(g);
+    b->execs.assign(b->waves.size(), nullptr);
+    b->graphs.assign(b->waves.size(), nullptr);
+}
+
+// autotune on the first wave (once), then capture every wave not captured yet
+pbs_status prepare(pbs_batch *b)
+{
+    if (b->execs.size() != b->waves.size()) drop_graphs(b);
+    if (!b->tuned) {
+        std::vector<BeamDev> dev;
+        pbs_status r = setup_wave(b, b->waves[0], dev);
+        if (r != PBS_OK) return r;
+        if ((r = autotune(b, (int)b->waves[0].size(), wave_max(b, b->waves[0], true))) != PBS_OK) return r;
+        drop_graphs(b);
+    }
+    for (size_t wi = 0; wi < b->waves.size(); ++wi)
+        if (!b->execs[wi]) {
+            const pbs_status r = capture_wave(b, wi);
+            if (r != PBS_OK) return r;
+        }
+    return PBS_OK;
+}
+
 }  // namespace
 
 // =================================================================================== C ABI
@@ -454,63 +534,34 @@ pbs_status pbs_batch_set_phantom(pbs_batch *b, int beam, const double *rho, size
     return PBS_OK;
 }
 
+pbs_status pbs_batch_prepare(pbs_batch *b)
+{
+    if (!b) return PBS_EINVAL;
+    if (b->state < 1) return bfail(b, PBS_ESTATE, "batch_prepare before bind");
+    for (int i = 0; i < b->nb; ++i)
+        if (!b->have_rho[i]) return bfail(b, PBS_ESTATE, "a beam has no phantom");
+    const pbs_status r = prepare(b);
+    if (r != PBS_OK) return r;
+    BHIP(b, hipStreamSynchronize(b->stream));
+    return PBS_OK;
+}
+
 pbs_status pbs_batch_run(pbs_batch *b)
 {
     if (!b) return PBS_EINVAL;
     if (b->state < 1) return bfail(b, PBS_ESTATE, "batch_run before bind");
     for (int i = 0; i < b->nb; ++i)
         if (!b->have_rho[i]) return bfail(b, PBS_ESTATE, "a beam has no phantom");
+    pbs_status r = prepare(b);
+    if (r != PBS_OK) return r;
     BHIP(b, launch_fill<double>(reinterpret_cast<double *>(b->ws + b->o_dose), 0.0,
                                 (long)((b->o_wave - b->o_dose) / 8), b->stream));
     std::vector<BeamDev> dev;
-    for (auto &w : b->waves) {
-        pbs_status r = setup_wave(b, w, dev);
-        if (r != PBS_OK) return r;
-        int maxG = 0, maxnz = 0;
-        for (int beam : w) {
-            maxG = std::max(maxG, b->grids[beam].ng);
-            maxnz = std::max(maxnz, b->grids[beam].nz);
-        }
-        if (!b->tuned) {
-            if ((r = autotune(b, (int)w.size(), maxG)) != PBS_OK) return r;
-            if ((r = setup_wave(b, w, dev)) != PBS_OK) return r;   // the timing steps changed the state
-        }
-        BatchTuning t = b->tune;
-        t.max_nz = maxnz;
-        // the whole march of the wave as one graph
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
-        const BeamDev *bd = reinterpret_cast<const BeamDev *>(b->ws + b->o_beams);
-        const BatchShape Sh = shape(b);
-        hipError_t le = hipSuccess;
-        BatchSide sd{b->side, b->ev_e.data(), b->ev_tat.data(), b->pend.data()};
-        for (int k = 0; k < b->ngen; ++k) b->pend[k] = 0;
-        for (int s = 0; s <= maxnz && le == hipSuccess; ++s)
-            le = launch_batch_step(bd, (int)w.size(), Sh, s, maxG, t, b->stream, &sd);
-        // join the side stream before the capture ends
-        for (int k = 0; k < b->ngen; ++k)
-            if (b->pend[k]) {
-                const hipError_t je = hipStreamWaitEvent(b->stream, b->ev_tat[k], 0);
-                if (le == hipSuccess) le = je;
-                b->pend[k] = 0;
-            }
-        const hipError_t ce = hipStreamEndCapture(b->stream, &graph);
-        if (le != hipSuccess || ce != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return bfail(b, PBS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(le != hipSuccess ? le : ce));
-        }
-        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (ie != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            return bfail(b, PBS_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
-        }
-        const hipError_t re = hipGraphLaunch(exec, b->stream);
-        const hipError_t se = hipStreamSynchronize(b->stream);
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        if (re != hipSuccess || se != hipSuccess)
-            return bfail(b, PBS_EDEVICE, std::string("graph launch: ") + hipGetErrorString(re != hipSuccess ? re : se));
+    for (size_t wi = 0; wi < b->waves.size(); ++wi) {
+        const std::vector<int> &w = b->waves[wi];
+        if ((r = setup_wave(b, w, dev)) != PBS_OK) return r;
+        const hipError_t re = hipGraphLaunch(b->execs[wi], b->stream);
+        if (re != hipSuccess) return bfail(b, PBS_EDEVICE, std::string("graph launch: ") + hipGetErrorString(re));
         // dose of every beam of the wave
         size_t o = 0;
         for (int beam : w) {
@@ -523,8 +574,9 @@ pbs_status pbs_batch_run(pbs_batch *b)
                                          reinterpret_cast<const double *>(b->ws + b->o_wave + s.rhod), vol,
                                          (long)gr.nz * b->NP, b->stream));
         }
+        // the next wave's set-up rewrites the wave region
+        BHIP(b, hipStreamSynchronize(b->stream));
     }
-    BHIP(b, hipStreamSynchronize(b->stream));
     b->state = 2;
     return PBS_OK;
 }
@@ -555,7 +607,9 @@ const char *pbs_batch_last_error(const pbs_batch *b) { return b ? b->err.c_str()
 void pbs_batch_destroy(pbs_batch *b)
 {
     if (!b) return;
+    if (b->ws) (void)hipStreamSynchronize(b->stream);
     if (b->side) (void)hipStreamSynchronize(b->side);
+    drop_graphs(b);
     for (hipEvent_t e : b->ev_e)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : b->ev_tat)

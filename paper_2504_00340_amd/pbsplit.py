@@ -27,7 +27,7 @@ EXPORTS = ["pbs_create", "pbs_workspace_bytes", "pbs_bind", "pbs_set_phantom", "
            "pbs_run_beam", "pbs_get_dose", "pbs_get_state", "pbs_set_state", "pbs_apply", "pbs_set_source_precision",
            "pbs_profile", "pbs_set_schedule",
            "pbs_profile_read", "pbs_last_error", "pbs_destroy", "pbs_batch_create", "pbs_batch_workspace_bytes",
-           "pbs_batch_bind", "pbs_batch_set_phantom", "pbs_batch_run", "pbs_batch_get_dose", "pbs_batch_tuning",
+           "pbs_batch_bind", "pbs_batch_set_phantom", "pbs_batch_prepare", "pbs_batch_run", "pbs_batch_get_dose", "pbs_batch_tuning",
            "pbs_batch_last_error", "pbs_batch_destroy", "pbs_set_surrogate", "pbs_surrogate_sample",
            "pbs_surrogate_records", "pbs_surrogate_report", "pbs_net_param_count", "pbs_net_create",
            "pbs_net_workspace_bytes", "pbs_net_bind", "pbs_net_set_params", "pbs_net_get_params", "pbs_net_forward",
@@ -101,6 +101,7 @@ def lib():
         L.pbs_batch_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
         L.pbs_batch_bind.argtypes = [vp, vp, sz, vp]
         L.pbs_batch_set_phantom.argtypes = [vp, C.c_int, D, sz]
+        L.pbs_batch_prepare.argtypes = [vp]
         L.pbs_batch_run.argtypes = [vp]
         L.pbs_batch_get_dose.argtypes = [vp, C.c_int, D, sz]
         L.pbs_batch_tuning.argtypes = [vp, C.POINTER(C.c_int)]
@@ -186,7 +187,6 @@ class Solver:
 
     def __init__(self, grid: dict, phys: dict, precision: str = "fp32", device="cuda:0", stream=None,
                  surrogate=None, residual_tol: float = 1e-2, static_scratch: bool = False):
-
         import torch
 
         self.torch = torch
@@ -352,6 +352,10 @@ class Batch:
     def _check(self, rc):
         if rc != PBS_OK:
             raise PbsError(rc, self.L.pbs_batch_last_error(self.h).decode())
+
+    def prepare(self):
+        """Autotune and capture every wave's graph (otherwise done by the first run)."""
+        self._check(self.L.pbs_batch_prepare(self.h))
 
     def run(self):
         self._check(self.L.pbs_batch_run(self.h))

@@ -29,7 +29,11 @@ def test_batch_equals_single_beam_runs(wave, nx, ny):
 
     beams = _beams(3, nx=nx, ny=ny) if (nx, ny) != (10, 10) else _beams()
     bt = Batch(beams, I.PHYS, wave=wave)
+    if wave:
+        bt.prepare()             # tuning and capture ahead of the run; without it the first run does them
     bt.run()
+    first = [bt.dose(i) for i in range(len(beams))]
+    bt.run()                     # replays the graphs captured by the first run
     tu = bt.tuning()
     print("tuning", tu, flush=True)
     assert tu["gemm_kernel"] in ("global", "lds256", "lds128") and tu["tpass_waves_per_block"] in (1, 2, 4)
@@ -44,6 +48,7 @@ def test_batch_equals_single_beam_runs(wave, nx, ny):
         got = bt.dose(i)
         print(i, b["grid"]["ng"], b["grid"]["nz"], float(np.abs(got - ref).max()), flush=True)
         assert np.array_equal(got, ref), i
+        assert np.array_equal(first[i], got), i
     bt.close()
 
 

@@ -145,9 +145,9 @@ def test_fullsize_march_matches_oracle(march_ref, prec, src):
     product every generation 1e-5.  In the split-BF16 modes a scattered generation that starts at zero is
     made of the source alone.  With the scanned fluence W rounded once to BF16 (relative error <= 2^-9)
     and the transfer matrix P2 either split hi + lo (error <= 2^-16, three products) or rounded with
-    compensated columns (a moved entry is at most 1.5 BF16 ulp from its value: <= 1.5 * 2^-8), every
-    product sum_a' P2[a, a'] W[a'] of non-negative terms is off by at most (2^-9 + eps_P) of its value.
-    The bound used is that sum (1e-4 for three products, 8e-3 for one) relative to max |ref_k|; the dose,
+    compensated columns (every entry within one BF16 ulp of its value: <= 2^-7 of it), every product
+    sum_a' P2[a, a'] W[a'] of non-negative terms is off by at most (2^-9 + eps_P) of its value.  The bound
+    used is that sum (1e-4 for three products, 1e-2 for one) relative to max |ref_k|; the dose,
     which the scattered generations enter with a small weight, must stay within 1e-4 (rel-L2) in every
     mode, the bar the FP32 path is held to."""
     c, dref, fref = march_ref
@@ -165,11 +165,14 @@ def test_fullsize_march_matches_oracle(march_ref, prec, src):
           f"; dose rel-L2 {drel:.2e}, max {dmax:.2e}", flush=True)
     if prec == "fp64":
         tols = [1e-12] * NGEN
-        dtol = 1e-12
+        # the oracle's deposit is the difference of a line's energy content before and after each half
+        # step, about E0 / (rho S dz/2) ~ 900 times the deposit itself at 150 MeV, so its FP64 rounding
+        # reaches ~1e-12 of the dose in single cells; the library's flux-form deposit does not cancel
+        dtol, dmaxtol = 1e-12, 1e-11
     else:
-        scat = {"fp32": 1e-5, "bf16x3": 1e-4, "bf16x1": 8e-3}[src]
+        scat = {"fp32": 1e-5, "bf16x3": 1e-4, "bf16x1": 1e-2}[src]
         tols = [1e-5] + [scat] * (NGEN - 1)
-        dtol = 1e-4
+        dtol = dmaxtol = 1e-4
     for k, (e, idx) in enumerate(errs):
         assert e <= tols[k], (k, e, idx)
-    assert drel <= dtol and dmax <= dtol
+    assert drel <= dtol and dmax <= dmaxtol
