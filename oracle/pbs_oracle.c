@@ -561,6 +561,7 @@ static void og_energy_cn_strag(const og_grid *g, const double *S_face, const dou
 #pragma omp parallel
     {
         double *e1 = malloc(G * sizeof(double)), *e2 = malloc(G * sizeof(double));
+        double *c1 = malloc(G * sizeof(double)), *c2 = malloc(G * sizeof(double));
         double *bt = malloc(2 * G * sizeof(double)), *Dt = malloc(4 * G * sizeof(double));
 #pragma omp for schedule(static)
         for (long line = 0; line < NA * NP; line++) {
@@ -568,7 +569,11 @@ static void og_energy_cn_strag(const og_grid *g, const double *S_face, const dou
             double r = rho[pq], c = 0.5 * h * r;
             double *x1 = psi + IDX(g, 0, 0, a, pq);
             double *x2 = psi + IDX(g, 0, 1, a, pq);
-            og_energy_rhs_line(G, S_face, dE, kappa, T_face, Tp_face, r, x1, x2, st, NULL, e1, e2);
+            for (long k = 0; k < G; k++) { /* the line, contiguous */
+                c1[k] = x1[k * st];
+                c2[k] = x2[k * st];
+            }
+            og_energy_rhs_line(G, S_face, dE, kappa, T_face, Tp_face, r, c1, c2, 1, NULL, e1, e2);
             /* elimination from the top: Dt_k = M_k - U_k Dt_{k+1}^-1 L_{k+1}, bt_k = b_k - U_k Dt_{k+1}^-1 bt_{k+1},
              * with M = I - c D0_kk, U = -c Up, L = -c Lo                                                    */
             for (long k = G - 1; k >= 0; k--) {
@@ -609,7 +614,7 @@ static void og_energy_cn_strag(const og_grid *g, const double *S_face, const dou
                 y2p = y2;
             }
         }
-        free(e1); free(e2); free(bt); free(Dt);
+        free(e1); free(e2); free(c1); free(c2); free(bt); free(Dt);
     }
     free(Lo); free(Di); free(Up);
 }

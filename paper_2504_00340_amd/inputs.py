@@ -23,8 +23,26 @@ import numpy as np
 # down-scatter rate lambda (1/MeV); Gamma-law shape/rate of the nuclear
 # deflection angle (App. A.4 forms, synthetic parameters).
 PHYS = dict(bk_alpha=0.0022, bk_p=1.77, e_floor=1.0, highland_es=14.1, x0_water=36.08, mp=938.272,
-            kappa0=0.012, e_c=20.0, lambda_nuc=0.05, gamma_a=2.0, gamma_b=40.0, stopping=0)
+            kappa0=0.012, e_c=20.0, lambda_nuc=0.05, gamma_a=2.0, gamma_b=40.0, stopping=0,
+            straggling=0, scattering=0, material=0, nuc_bands=0)
 STOP_BRAGG_KLEEMAN, STOP_BETHE = 0, 1   # stopping-power model: range fit, or Bethe-Bloch (App. A.1)
+SCAT_HIGHLAND, SCAT_RUTHERFORD = 0, 1   # scattering power: Highland, or screened Rutherford (App. A.3)
+MAT_WATER, MAT_BONE, MAT_AIR = 0, 1, 2  # media of the paper's material table (section 4)
+RHO_MEDIUM = {MAT_WATER: 1.0, MAT_BONE: 1.757, MAT_AIR: 0.001205}   # densities of that table
+
+# The paper's own physics (App. A.1-A.3) for a medium: Bethe-Bloch stopping, Williams straggling,
+# screened-Rutherford scattering.
+def paper_physics(material=MAT_WATER, straggling=1):
+    return dict(PHYS, stopping=STOP_BETHE, straggling=straggling, scattering=SCAT_RUTHERFORD, material=material)
+
+
+# Energy-band nuclear data (App. A.4 fits lambda and the Gamma-law alpha, beta group by group, at
+# groups 100, 200, 300 and 400 of 500 on [1, 260] MeV, i.e. about 52.5, 104.3, 156.1 and 207.9 MeV;
+# each group takes the parameters of the nearest of these anchors).  The values are synthetic (the
+# fits need Monte Carlo data that are not printed): the energy transfer gets harder and the angular
+# law narrower with energy.
+NUC_BANDS = dict(nuc_bands=4, nuc_e=[52.5, 104.3, 156.1, 207.9], nuc_lambda=[0.08, 0.06, 0.05, 0.04],
+                 nuc_alpha=[2.0, 2.0, 2.2, 2.4], nuc_beta=[25.0, 35.0, 45.0, 55.0])
 
 RHO_WATER, RHO_BONE, RHO_LUNG = 1.0, 1.85, 0.26
 
