@@ -222,14 +222,16 @@ class Oracle:
         return out
 
     # the march -------------------------------------------------------------
-    def run(self, beam: dict, rho, state=None):
-        """Full depth march.  rho: [nz, nx, ny].  Returns (dose [nz,nx,ny], final state)."""
+    def run(self, beam: dict, rho, state=None, order=2):
+        """Full depth march.  rho: [nz, nx, ny].  Returns (dose [nz,nx,ny], final state).
+        order 2: Strang steps; order 4: Richardson-extrapolated Strang steps."""
         g = self.g
         rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(g.nz, g.nx * g.ny)
         if state is None:
             state = self.initial(beam)
         dose = np.zeros((g.nz, g.nx * g.ny))
-        lib().og_run(C.byref(g), C.byref(self._tab), _p(rho), _p(state), _p(dose))
+        fn = lib().og_run_extrapolated if order == 4 else lib().og_run
+        fn(C.byref(g), C.byref(self._tab), _p(rho), _p(state), _p(dose))
         return dose.reshape(g.nz, g.nx, g.ny), state
 
     def run_records(self, beam: dict, rho, state=None):
