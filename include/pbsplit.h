@@ -81,32 +81,55 @@ typedef struct pbs_beam {
     double e0, sigma_e, x0, y0, sigma_x, sigma_y;
 } pbs_beam;
 
-/* Physics record.  Materials enter through the density only (water-
- * equivalent per unit mass).
- *   stopping        PBS_STOP_BRAGG_KLEEMAN: S from the range fit below;
- *                   PBS_STOP_BETHE: the Bethe-Bloch mass stopping power of App. A.1 for water,
+/* Physics record.  Every voxel holds the same medium (`material`); voxels differ by density only.
+ *   stopping        PBS_STOP_BRAGG_KLEEMAN: S from the range fit below (water only);
+ *                   PBS_STOP_BETHE: the Bethe-Bloch mass stopping power of App. A.1 for the medium,
  *                   heavy-projectile form kappa Z/A / beta^2 [ln(2 m_e c^2 beta^2 gamma^2 / I) - beta^2]
  *                   with kappa = 0.307075 MeV cm^2/mol, no density correction, I(Z) from the
- *                   appendix's piecewise fit (H 19 eV, O 104.8 eV), summed over H and O with their
- *                   mass fractions (Bragg additivity); needs e_floor >= 0.5 MeV (else PBS_EINVAL)
+ *                   appendix's piecewise fit, summed over the elements with their mass fractions
+ *                   (Bragg additivity); needs e_floor >= 0.5 MeV (else PBS_EINVAL)
+ *   straggling      0: none; 1: Williams' straggling coefficient of App. A.2 for the medium,
+ *                   T = kappa m_e c^2 Z/A [1 + 4 I/(3 m_e v^2) ln(2 m_e v^2 / I)] per element, mass-
+ *                   fraction sum; the energy operator gains (1/2) d^2/dE^2 (T psi) of section 3.2: its
+ *                   first-order part (1/2) d/dE (T' psi) adds T'/2 to the stopping term, its second-order
+ *                   part is the symmetric interior penalty discretisation (penalty 2 T_f / h_f on interior
+ *                   group faces, none on the end faces), so every energy line is block-tridiagonal.
+ *                   Needs stopping = PBS_STOP_BETHE.  FP32 contexts then use the FP32 source product.
+ *   scattering      PBS_SCAT_HIGHLAND: the Highland scattering power below; PBS_SCAT_RUTHERFORD: the
+ *                   screened-Rutherford momentum-transfer cross section of App. A.3 for the medium,
+ *                   2 pi (Z r_e m_e c^2 / pv)^2 [ln((eta+1)/eta) - 1/(eta+1)] N_A/A per element, eta =
+ *                   (Z^(1/3) alpha m_e c / p)^2, with p v of the proton in the laboratory frame
+ *   material        PBS_MAT_WATER (H2O), PBS_MAT_BONE, PBS_MAT_AIR (the compositions of section 4's
+ *                   material table); other than water needs stopping = PBS_STOP_BETHE
  *   bk_alpha, bk_p  Bragg-Kleeman range R = alpha E^p (cm water): S = 1/(alpha p E^(p-1))
  *   e_floor         coefficients are evaluated at max(E, e_floor) (MeV)
  *   highland_es, x0_water, mp   scattering power sigma_tr = (E_s/pv)^2 / X0 (Highland form),
- *                   group-averaged with 8-point Gauss-Legendre
+ *                   group-averaged with 8-point Gauss-Legendre (either form)
  *   kappa0, e_c     nuclear removal per unit mass kappa(E) = kappa0 (1 - exp(-E/e_c)) (cm^2/g)
  *   lambda_nuc      energy transfer of re-emission  ~ exp(-lambda (E_g' - E_g)) (App. A.4)
- *   gamma_a, gamma_b  angular transfer ~ theta^(a-1) exp(-b theta) of the deflection angle */
+ *   gamma_a, gamma_b  angular transfer ~ theta^(a-1) exp(-b theta) of the deflection angle
+ *   nuc_bands       0: lambda_nuc, gamma_a, gamma_b for every group; 1..4: the App. A.4 parameters per
+ *                   energy band -- each group takes those of the nearest anchor nuc_e[b] (MeV): the energy
+ *                   law uses the source group's nuc_lambda, the angular law the destination group's
+ *                   nuc_alpha, nuc_beta.  Not with the batched path. */
 enum { PBS_STOP_BRAGG_KLEEMAN = 0, PBS_STOP_BETHE = 1 };
+enum { PBS_SCAT_HIGHLAND = 0, PBS_SCAT_RUTHERFORD = 1 };
+enum { PBS_MAT_WATER = 0, PBS_MAT_BONE = 1, PBS_MAT_AIR = 2 };
 typedef struct pbs_physics {
     double bk_alpha, bk_p, e_floor, highland_es, x0_water, mp;
     double kappa0, e_c, lambda_nuc, gamma_a, gamma_b;
-    int stopping;
+    int stopping, straggling, scattering, material, nuc_bands;
+    double nuc_e[4], nuc_lambda[4], nuc_alpha[4], nuc_beta[4];
 } pbs_physics;
 
 typedef struct pbs_ctx pbs_ctx; /* opaque; host-side metadata only */
 
-/* Create a context for one grid and physics record.  precision: PBS_FP32 or
- * PBS_FP64.  *out receives the context (NULL on error).  Host memory only. */
+/* Create a context for one grid and physics record: the phase-space grid of
+ * section 3 (DG-P1 energy groups of section 3.2, lateral cells and angular
+ * nodes of section 3.4, depth steps of section 3.3) and the coefficient tables
+ * of App. A (S, sigma_tr, T, the nuclear kernel) built on the host in FP64.
+ * precision: PBS_FP32 or PBS_FP64.  *out receives the context (NULL on error).
+ * Host memory only. */
 pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precision, pbs_ctx **out);
 
 /* Device workspace the caller must provide (bytes, 256-byte aligned start). */
@@ -134,24 +157,51 @@ pbs_status pbs_bind_static(pbs_ctx *ctx, void *hip_stream);
 
 /* Densities rho[s][p][q] (g/cm^3) on the computational grid, host array of
  * nz*nx*ny doubles, C order.  Every value must be finite and > 0 (else
- * PBS_EINVAL).  Copied; the caller keeps ownership. */
+ * PBS_EINVAL).  Copied; the caller keeps ownership.  The density enters the
+ * operators as rho(r) of the transport equation (section 2, eq:(f-e)): rho S,
+ * rho sigma_tr, rho T and the removal sigma_ct = rho kappa. */
 pbs_status pbs_set_phantom(pbs_ctx *ctx, const double *rho, size_t n);
 
-/* Start a beam: builds the initial fluence (eq:(bdy) projected on the grid),
+/* A voxel phantom with its own spacing (the density field rho(x, y, z) of the
+ * problem statement, section 2 and section 4's test domains), resampled onto
+ * the computational grid by the nearest voxel and then set as pbs_set_phantom
+ * does.  vox[k][i][j] (host, C order, vnz*vnx*vny doubles, finite and > 0)
+ * covers depth [k vdz, (k+1) vdz) and, in the beam's lateral frame (the grid is
+ * centred on x = y = 0), x in [x_lo + i vdx, x_lo + (i+1) vdx), y likewise from
+ * y_lo.  The density of layer s and cell (p, q) is that of the voxel holding
+ * the layer's and the cell's centre, the index clamped to the phantom.
+ * PBS_EINVAL for bad sizes, spacings or densities; PBS_ESTATE before bind. */
+pbs_status pbs_set_phantom_voxels(pbs_ctx *ctx, const double *vox, int vnz, int vnx, int vny, double vdz,
+                                  double vdx, double vdy, double x_lo, double y_lo);
+
+/* The resampling of pbs_set_phantom_voxels alone, on the host: out receives
+ * grid->nz * grid->nx * grid->ny densities [s][p][q].  No context needed. */
+pbs_status pbs_resample_phantom(const pbs_grid *grid, const double *vox, int vnz, int vnx, int vny, double vdz,
+                                double vdx, double vdy, double x_lo, double y_lo, double *out);
+
+/* Start a beam (section 4, the boundary distribution eq:(bdy); section 3.1's
+ * scattering decomposition eqn:(pri-se) for the generations): builds the
+ * initial fluence (eq:(bdy) projected on the grid),
  * zeroes the scattered generations and the dose, sets the step counter to 0. */
 pbs_status pbs_set_beam(pbs_ctx *ctx, const pbs_beam *beam);
 
-/* Advance n >= 0 depth steps (asynchronous on the bound stream).  The last
+/* Advance n >= 0 depth steps of the splitting scheme of section 3.3 (each step
+ * the Strang sequence E(dz/2) T(dz/2) A(dz) T(dz/2) E(dz/2) over every
+ * generation, Crank-Nicolson in every sub-step), asynchronous on the bound
+ * stream; layer s takes the densities of phantom layer s.  The last
  * energy half-step of the last advanced step is deferred and fused with the
  * first half-step of the next one; run_beam applies the closing half-step.
  * Splitting a march into chunks gives bitwise the same result as one call.
  * *step_out (may be NULL) receives the number of steps done so far. */
 pbs_status pbs_step_depth(pbs_ctx *ctx, int n, int *step_out);
 
-/* March the remaining steps and apply the closing energy half-step. */
+/* March the remaining steps of section 3.3's scheme and apply the closing
+ * energy half-step of the last layer. */
 pbs_status pbs_run_beam(pbs_ctx *ctx);
 
-/* Dose D = E_dep / (rho dx dy dz) (MeV/g per incident proton) on [nz][nx][ny],
+/* Dose D = E_dep / (rho dx dy dz) of section 4 (the dose definition and the
+ * energy deposition eq:(en_d): the energy the protons lose in the energy
+ * sub-steps of each layer) in MeV/g per incident proton on [nz][nx][ny],
  * FP64, n = nz*nx*ny.  out is host memory (out_is_device = 0; the call
  * synchronises the stream) or device memory (1; the copy is enqueued). */
 pbs_status pbs_get_dose(pbs_ctx *ctx, double *out, size_t n, int out_is_device);
@@ -187,6 +237,18 @@ pbs_status pbs_apply(pbs_ctx *ctx, int op, int layer, double h);
  * Other contexts always use their own precision; the split modes there return PBS_EUNSUPPORTED. */
 enum { PBS_SRC_FP32 = 0, PBS_SRC_BF16X3 = 1, PBS_SRC_BF16X2 = 2, PBS_SRC_BF16X1 = 3 };
 pbs_status pbs_set_source_precision(pbs_ctx *ctx, int mode);
+
+/* Splitting in depth (section 3.3; section 5 names higher-order splitting as the extension).
+ *   order 2: Strang steps E(dz/2) T(dz/2) A(dz) T(dz/2) E(dz/2) (the default);
+ *   order 4: Richardson extrapolation of the Strang step per depth layer: from the state psi_n,
+ *            A = S(dz) psi_n and B = S(dz/2) S(dz/2) psi_n with the layer's densities, psi_{n+1} =
+ *            (4 B - A) / 3, and the layer's deposit combined with the same weights.  Fourth order in depth
+ *            for linear steps (every sub-step stays a positive CN step); about three Strang steps of work
+ *            per layer, and two more copies of the fluence in the workspace.  Every step is complete, so
+ *            pbs_run_beam adds no closing half-step.
+ * Must be called after pbs_create and before pbs_workspace_bytes / pbs_bind.  PBS_EINVAL for another
+ * order, PBS_ESTATE after bind, PBS_EUNSUPPORTED for order 4 with a surrogate. */
+pbs_status pbs_set_splitting(pbs_ctx *ctx, int order);
 
 /* Schedule of the depth march (no effect on the results, which are bitwise the same either way).
  * Generation k's transport, angular and transport sub-steps touch only its own fluence, so they may

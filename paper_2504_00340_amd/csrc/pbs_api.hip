@@ -170,39 +170,125 @@ pbs_status hip_fail(pbs_ctx *c, hipError_t e, const char *what)
 bool finite_pos(double x) { return std::isfinite(x) && x > 0; }
 
 // ------------------------------------------------------------------------------ host tables
-// Bethe-Bloch mass stopping power of water (App. A.1), MeV cm^2/g: per element the heavy-projectile form
-// K (Z/A) / beta^2 [ln(2 m_e c^2 beta^2 gamma^2 / I) - beta^2] without the density term, I(Z) from the
-// appendix's fit, and the compound as the mass-fraction sum over H and O.
-double bethe_water(double e, double mp)
+// Media by weight fraction of their elements (Z, standard atomic weight A in g/mol): water as H2O, bone
+// and air as the material table of section 4 prints them.
+struct Medium {
+    int n;
+    int Z[9];
+    double A[9], w[9];
+};
+
+Medium medium(int material)
 {
-    constexpr double K = 0.307075;      // 4 pi N_A r_e^2 m_e c^2, MeV cm^2 / mol
-    constexpr double MEC2 = 0.51099895; // MeV
-    constexpr double A_H = 1.008, A_O = 15.999;
-    const double m_h2o = 2.0 * A_H + A_O;
+    Medium m{};
+    if (material == PBS_MAT_BONE) {
+        const int Z[9] = {1, 6, 7, 8, 11, 12, 15, 16, 20};
+        const double A[9] = {1.008, 12.011, 14.007, 15.999, 22.990, 24.305, 30.974, 32.06, 40.078};
+        const double w[9] = {0.042, 0.194, 0.040, 0.425, 0.001, 0.002, 0.092, 0.003, 0.201};
+        m.n = 9;
+        for (int k = 0; k < 9; ++k) m.Z[k] = Z[k], m.A[k] = A[k], m.w[k] = w[k];
+    } else if (material == PBS_MAT_AIR) {
+        const int Z[4] = {6, 7, 8, 18};
+        const double A[4] = {12.011, 14.007, 15.999, 39.948};
+        const double w[4] = {0.0001248, 0.7553, 0.2318, 0.01283};
+        m.n = 4;
+        for (int k = 0; k < 4; ++k) m.Z[k] = Z[k], m.A[k] = A[k], m.w[k] = w[k];
+    } else {
+        constexpr double A_H = 1.008, A_O = 15.999;
+        const double mol = 2.0 * A_H + A_O;
+        m.n = 2;
+        m.Z[0] = 1, m.A[0] = A_H, m.w[0] = 2.0 * A_H / mol;
+        m.Z[1] = 8, m.A[1] = A_O, m.w[1] = A_O / mol;
+    }
+    return m;
+}
+
+// mean excitation energy of element Z (eV), the piecewise fit of App. A.1
+double i_value(int Z) { return Z == 1 ? 19.0 : Z <= 13 ? 11.2 + 11.7 * Z : 52.8 + 8.71 * Z; }
+
+constexpr double K_BB = 0.307075;          // 4 pi N_A r_e^2 m_e c^2, MeV cm^2 / mol
+constexpr double ME_C2 = 0.51099895;       // MeV
+constexpr double AVOGADRO = 6.02214076e23; // 1/mol
+constexpr double R_ELECTRON = 2.8179403262e-13;   // cm
+constexpr double FINE_ALPHA = 1.0 / 137.035999084;
+
+// Bethe-Bloch mass stopping power of a medium (App. A.1), MeV cm^2/g: per element the heavy-projectile
+// form K (Z/A) / beta^2 [ln(2 m_e c^2 beta^2 gamma^2 / I) - beta^2] without the density term, I(Z) from the
+// appendix's fit, and the medium as the mass-fraction sum of its elements.
+double bethe(int material, double e, double mp)
+{
+    const Medium M = medium(material);
     const double gamma = 1.0 + e / mp;
     const double beta2 = 1.0 - 1.0 / (gamma * gamma);
-    const double wmax_ev = 2.0 * MEC2 * beta2 * gamma * gamma * 1.0e6;
-    auto element = [&](double Z, double A, double I_ev) {
-        return K * (Z / A) / beta2 * (std::log(wmax_ev / I_ev) - beta2);
-    };
-    const double I_h = 19.0, I_o = 11.2 + 11.7 * 8.0;
-    return (2.0 * A_H / m_h2o) * element(1.0, A_H, I_h) + (A_O / m_h2o) * element(8.0, A_O, I_o);
+    const double wmax_ev = 2.0 * ME_C2 * beta2 * gamma * gamma * 1.0e6;
+    double s = 0.0;
+    for (int k = 0; k < M.n; ++k)
+        s += M.w[k] * K_BB * (M.Z[k] / M.A[k]) / beta2 * (std::log(wmax_ev / i_value(M.Z[k])) - beta2);
+    return s;
+}
+
+// Williams' straggling coefficient of a medium (App. A.2), MeV^2 cm^2/g, and its energy derivative:
+// per element K m_e c^2 (Z/A) [1 + 4 I/(3 x) ln(2 x / I)] with x = m_e v^2 = m_e c^2 beta^2 (non-relativistic,
+// as printed) and I in MeV; d/dE uses d/dx [ln(2x/I)/x] = (1 - ln(2x/I))/x^2 and dx/dE = 2 m_e c^2/(gamma^3 m_p).
+void williams(int material, double e, double mp, double *T, double *dT)
+{
+    const Medium M = medium(material);
+    const double gamma = 1.0 + e / mp;
+    const double x = ME_C2 * (1.0 - 1.0 / (gamma * gamma));
+    const double dx = 2.0 * ME_C2 / (gamma * gamma * gamma * mp);
+    double t = 0.0, d = 0.0;
+    for (int k = 0; k < M.n; ++k) {
+        const double I = i_value(M.Z[k]) * 1e-6, c = M.w[k] * K_BB * ME_C2 * M.Z[k] / M.A[k];
+        const double lg = std::log(2.0 * x / I);
+        t += c * (1.0 + 4.0 * I / (3.0 * x) * lg);
+        d += c * (4.0 * I / 3.0) * (1.0 - lg) / (x * x) * dx;
+    }
+    *T = t;
+    *dT = d;
+}
+
+// Screened-Rutherford momentum-transfer cross section per unit mass of a medium (App. A.3), cm^2/g: per
+// atom 2 pi (Z e^2 / (4 pi eps0 p v))^2 [ln((eta + 1)/eta) - 1/(eta + 1)], eta = (Z^(1/3) alpha m_e c / p)^2,
+// with e^2/(4 pi eps0) = r_e m_e c^2 and p v of the proton in the laboratory frame; N_A/A atoms per gram.
+double rutherford(int material, double e, double mp)
+{
+    const Medium M = medium(material);
+    const double pc = std::sqrt(e * (e + 2.0 * mp)), pv = pc * pc / (e + mp);
+    double s = 0.0;
+    for (int k = 0; k < M.n; ++k) {
+        const double r = M.Z[k] * R_ELECTRON * ME_C2 / pv;
+        const double t = std::cbrt((double)M.Z[k]) * FINE_ALPHA * ME_C2 / pc, eta = t * t;
+        s += M.w[k] * (AVOGADRO / M.A[k]) * 2.0 * M_PI * r * r * (std::log((eta + 1.0) / eta) - 1.0 / (eta + 1.0));
+    }
+    return s;
 }
 
 double stopping_power(const pbs_physics &ph, double E)
 {
     const double e = std::max(E, ph.e_floor);
-    if (ph.stopping == PBS_STOP_BETHE) return bethe_water(e, ph.mp);
+    if (ph.stopping == PBS_STOP_BETHE) return bethe(ph.material, e, ph.mp);
     return 1.0 / (ph.bk_alpha * ph.bk_p * std::pow(e, ph.bk_p - 1.0));
 }
 
 double scattering_power(const pbs_physics &ph, double E)
 {
     const double e = std::max(E, ph.e_floor);
+    if (ph.scattering == PBS_SCAT_RUTHERFORD) return rutherford(ph.material, e, ph.mp);
     const double pc2 = e * (e + 2.0 * ph.mp);           // (pc)^2
     const double pv = pc2 / (e + ph.mp);                // p v = (pc)^2 / total energy
     const double r = ph.highland_es / pv;
     return r * r / ph.x0_water;
+}
+
+// straggling coefficient at max(E, e_floor) and its derivative (0 below the floor, where T is held)
+void straggle(const pbs_physics &ph, double E, double *T, double *dT)
+{
+    *T = *dT = 0.0;
+    if (!ph.straggling) return;
+    double t, d;
+    williams(ph.material, std::max(E, ph.e_floor), ph.mp, &t, &d);
+    *T = t;
+    *dT = E < ph.e_floor ? 0.0 : d;
 }
 
 // angle between (1,u,v) and (1,u',v'), stable near zero
@@ -210,6 +296,61 @@ double deflection(double u, double v, double up, double vp)
 {
     const double c0 = u * vp - v * up, c1 = v - vp, c2 = up - u;
     return std::atan2(std::sqrt(c0 * c0 + c1 * c1 + c2 * c2), 1.0 + u * up + v * vp);
+}
+
+// The energy operator with straggling, rho = 1, as 2x2 blocks per group g (rows psi1, psi2 of g; columns
+// psi1, psi2 of the coupled group): Lo couples g to g-1, Di to itself, Up to g+1.
+//  * first-order part: the stopping term of eq:(0041-d) with S + T'/2 at the faces (the (1/2) d/dE (T' psi)
+//    half of the straggling operator), upwind values from the group above; removal -kappa_g;
+//  * second-order part (1/2) d/dE (T dpsi/dE), symmetric interior penalty on the DG-P1 basis: T linear in
+//    the group, {T psi'} and [psi] = psi(below) - psi(above) on interior faces, penalty 2 T_f / h_f (alpha =
+//    (1+1)^2/2, h_f the mean width of the two groups), no flux through the end faces; rows tested with
+//    phi^1 / dE and 3 phi^2 / dE.
+// Deposit weights: the energy rate of a line is sum_g w_g . (D0 X)_g with w_g = (dE E_g, dE^2/6); the
+// deposit functional is its negative, a weight per (group, coefficient) collected column by column.
+void straggling_tables(pbs_ctx *c)
+{
+    const int G = c->G();
+    const pbs_physics &ph = c->ph;
+    std::vector<double> T(G + 1), Tp(G + 1), S(G + 1);
+    for (int f = 0; f <= G; ++f) {
+        straggle(ph, c->E_face[f], &T[f], &Tp[f]);
+        S[f] = c->S_face[f] + 0.5 * Tp[f];
+    }
+    c->blk.assign((size_t)G * 12, 0.0);
+    for (int g = 0; g < G; ++g) {
+        double *Lo = &c->blk[(size_t)g * 12], *Di = Lo + 4, *Up = Lo + 8;
+        const double d = c->dE[g], sm = S[g] / d, sp = S[g + 1] / d, kp = c->kappa[g];
+        Di[0] = -(sm + kp), Di[1] = sm, Di[2] = -3.0 * sp, Di[3] = -(sp + 2.0 * sm + kp);
+        if (g + 1 < G) Up[0] = sp, Up[1] = -sp, Up[2] = 3.0 * sp, Up[3] = -3.0 * sp;
+        const double Tbar = 0.5 * (T[g] + T[g + 1]);
+        Di[3] += -6.0 * Tbar / (d * d);
+        if (g + 1 < G) {   // upper face
+            const double Tf = T[g + 1], du = c->dE[g + 1], pen = 2.0 * Tf / (0.5 * (d + du)), q = Tf / d - pen;
+            Di[0] += -pen / (2 * d), Di[1] += (Tf / d - pen) / (2 * d);
+            Up[0] += pen / (2 * d), Up[1] += (Tf / du - pen) / (2 * d);
+            Di[2] += 3 * q / (2 * d), Di[3] += 3 * (Tf / d + q) / (2 * d);
+            Up[2] += -3 * q / (2 * d), Up[3] += 3 * (Tf / du + q) / (2 * d);
+        }
+        if (g > 0) {       // lower face
+            const double Tf = T[g], dl = c->dE[g - 1], pen = 2.0 * Tf / (0.5 * (dl + d)), q = Tf / d - pen;
+            Lo[0] += pen / (2 * d), Lo[1] += (-Tf / dl + pen) / (2 * d);
+            Di[0] += -pen / (2 * d), Di[1] += (-Tf / d + pen) / (2 * d);
+            Lo[2] += 3 * q / (2 * d), Lo[3] += 3 * (Tf / dl + q) / (2 * d);
+            Di[2] += -3 * q / (2 * d), Di[3] += 3 * (Tf / d + q) / (2 * d);
+        }
+    }
+    c->dA2.assign(G, 0.0);
+    c->dB2.assign(G, 0.0);
+    for (int j = 0; j < G; ++j)
+        for (int col = 0; col < 2; ++col) {
+            double r = 0.0;
+            for (int g = std::max(0, j - 1); g <= std::min(G - 1, j + 1); ++g) {
+                const double *B = &c->blk[(size_t)g * 12 + (g == j ? 4 : g == j + 1 ? 0 : 8)];
+                r += c->dE[g] * c->E_mid[g] * B[col] + c->dE[g] * c->dE[g] / 6.0 * B[2 + col];
+            }
+            (col == 0 ? c->dA2 : c->dB2)[j] = -r;
+        }
 }
 
 void build_tables(pbs_ctx *c)
@@ -247,15 +388,27 @@ void build_tables(pbs_ctx *c)
         c->Sp[k] = c->S_face[k + 1] / c->dE[k];
         c->invdE[k] = 1.0 / c->dE[k];
     }
-    // re-emission energy law lambda exp(-lambda (E_g' - E_g)), normalised per source group g':
-    // W_g = (1/dE_g) U_g,  U_g = wc_g psi1_g + wdec_g U_{g+1}
+    // nuclear bands: each group takes the parameters of the nearest anchor energy (one band without them)
+    c->NB = ph.nuc_bands > 0 ? ph.nuc_bands : 1;
+    c->band.assign(G, 0);
+    for (int k = 0; k < G; ++k)
+        for (int b = 1; b < ph.nuc_bands; ++b)
+            if (std::fabs(c->E_mid[k] - ph.nuc_e[b]) < std::fabs(c->E_mid[k] - ph.nuc_e[c->band[k]])) c->band[k] = b;
+    auto lam_of = [&](int b) { return ph.nuc_bands ? ph.nuc_lambda[b] : ph.lambda_nuc; };
+    // re-emission energy law lambda exp(-lambda (E_g' - E_g)) with the source group's lambda, normalised per
+    // source group g': W_g = (1/dE_g) U_g, U_g = sum over bands b of U^b_g,
+    // U^b_g = [band(g) = b] wc_g psi1_g + wdecb[b][g] U^b_{g+1}
     c->wc.resize(G);
     c->wdec.resize(G);
+    c->wdecb.assign((size_t)c->NB * G, 0.0);
     for (int k = 0; k < G; ++k) {
+        const double lk = lam_of(c->band[k]);
         double Z = 0;
-        for (int j = 0; j <= k; ++j) Z += std::exp(-ph.lambda_nuc * (c->E_mid[k] - c->E_mid[j]));
+        for (int j = 0; j <= k; ++j) Z += std::exp(-lk * (c->E_mid[k] - c->E_mid[j]));
         c->wc[k] = c->kappa[k] * c->dE[k] / Z;
-        c->wdec[k] = k + 1 < G ? std::exp(-ph.lambda_nuc * (c->E_mid[k + 1] - c->E_mid[k])) : 0.0;
+        for (int b = 0; b < c->NB; ++b)
+            c->wdecb[(size_t)b * G + k] = k + 1 < G ? std::exp(-lam_of(b) * (c->E_mid[k + 1] - c->E_mid[k])) : 0.0;
+        c->wdec[k] = c->wdecb[k];
     }
     // deposit functional: -(energy rate of the rho-free energy operator)
     c->dA.resize(G);
@@ -277,20 +430,28 @@ void build_tables(pbs_ctx *c)
         for (int n = 1; n < N; ++n) c->sinS[(size_t)(M - 1) * m + (n - 1)] = std::sin(M_PI * M * n / N);
     c->lam.resize(m);
     for (int M = 1; M < N; ++M) c->lam[M - 1] = (2.0 * std::cos(M_PI * M / N) - 2.0) / (c->dth * c->dth);
-    // nuclear angular transfer: Gamma law of the deflection angle, normalised over destinations
-    c->P2T.assign((size_t)NA * NA, 0.0);
-    const double cst = std::pow(ph.gamma_b, ph.gamma_a) / std::tgamma(ph.gamma_a);
+    // nuclear angular transfer per band: Gamma law of the deflection angle, normalised over destinations
+    c->P2T.assign((size_t)c->NB * NA * NA, 0.0);
     std::vector<double> row(NA);
-    for (int src = 0; src < NA; ++src) {
-        const double up = c->theta[src / m], vp = c->theta[src % m];
-        double K = 0;
-        for (int dst = 0; dst < NA; ++dst) {
-            const double th = deflection(c->theta[dst / m], c->theta[dst % m], up, vp);
-            row[dst] = cst * std::pow(th, ph.gamma_a - 1.0) * std::exp(-ph.gamma_b * th);
-            K += row[dst];
+    for (int b = 0; b < c->NB; ++b) {
+        const double ga = ph.nuc_bands ? ph.nuc_alpha[b] : ph.gamma_a, gb = ph.nuc_bands ? ph.nuc_beta[b] : ph.gamma_b;
+        const double cst = std::pow(gb, ga) / std::tgamma(ga);
+        double *P = c->P2T.data() + (size_t)b * NA * NA;
+        for (int src = 0; src < NA; ++src) {
+            const double up = c->theta[src / m], vp = c->theta[src % m];
+            double K = 0;
+            for (int dst = 0; dst < NA; ++dst) {
+                const double th = deflection(c->theta[dst / m], c->theta[dst % m], up, vp);
+                row[dst] = cst * std::pow(th, ga - 1.0) * std::exp(-gb * th);
+                K += row[dst];
+            }
+            for (int dst = 0; dst < NA; ++dst) P[(size_t)dst * NA + src] = row[dst] / K;
         }
-        for (int dst = 0; dst < NA; ++dst) c->P2T[(size_t)dst * NA + src] = row[dst] / K;
     }
+    // straggling (section 3.2, App. A.2): rho-free blocks of the whole energy operator per group and the
+    // deposit weights of the functional -(energy rate)
+    c->strag = ph.straggling != 0;
+    if (c->strag) straggling_tables(c);
 }
 
 void layout(pbs_ctx *c)
@@ -313,7 +474,15 @@ void layout(pbs_ctx *c)
     c->o_dep = o;
     o = align256(o + (size_t)2 * K1 * c->NLINE * sizeof(double));
     c->o_edep = o;
-    o = align256(o + (size_t)c->g.nz * c->NP * sizeof(double));
+    o = align256(o + (size_t)(c->g.nz + 2) * c->NP * sizeof(double));   // + 2 scratch rows (order 4)
+    c->o_x0 = c->o_xA = o;
+    if (c->order == 4) {
+        const size_t st = (size_t)K1 * G * 2 * c->NLINE * T;
+        c->o_x0 = o;
+        o = align256(o + st);
+        c->o_xA = o;
+        o = align256(o + st);
+    }
     c->o_dout = o;
     o = align256(o + (size_t)c->g.nz * c->NP * sizeof(double));
     c->o_rhoT = o;
@@ -355,11 +524,13 @@ void layout(pbs_ctx *c)
     c->t_theta = e; e += c->m;
     c->t_S = e; e += (size_t)c->m * c->m;
     c->t_lam = e; e += c->m;
-    c->t_P2T = e; e += (size_t)c->NA * c->NA;
+    c->t_P2T = e; e += (size_t)c->NB * c->NA * c->NA;
     e = (e + 63) / 64 * 64;   // vector loads of the padded tables need 256-byte alignment
-    c->t_P2p = e; e += (size_t)c->Kp * c->Mp;
+    c->t_P2p = e; e += (size_t)c->NB * c->Kp * c->Mp;
     e = (e + 63) / 64 * 64;
     c->t_K32 = e; e += 1024;
+    c->t_wdecb = e; e += (size_t)c->NB * G;
+    c->t_blk = e; e += c->strag ? (size_t)12 * G : 0;
     c->t_count = e;
     c->o_tabT = o;
     o = align256(o + e * T);
@@ -370,12 +541,18 @@ void layout(pbs_ctx *c)
     c->d_E1 = d; d += G;
     c->d_E2 = d; d += G;
     c->d_lat = d; d += c->NP;
+    c->d_A2 = d; d += G;
+    c->d_B2 = d; d += G;
     c->d_wmom = d; d += 3 * G;
     c->d_count = d;
     c->o_tabD = o;
     o = align256(o + d * sizeof(double));
     c->o_bf = o;
-    if (c->Kpb > 0) o = align256(o + (size_t)3 * c->Mp * c->Kpb * sizeof(unsigned short));
+    if (c->Kpb > 0) o = align256(o + (size_t)c->NB * 3 * c->Mp * c->Kpb * sizeof(unsigned short));
+    c->o_band = o;
+    o = align256(o + (size_t)G * sizeof(int));
+    c->o_sfac = o;
+    if (c->strag) o = align256(o + (size_t)2 * G * 8 * c->NPpad * T);
     c->total = o;
 }
 
@@ -397,10 +574,15 @@ pbs_status upload_tables(pbs_ctx *c)
     put(c->t_S, c->sinS);
     put(c->t_lam, c->lam);
     put(c->t_P2T, c->P2T);
-    // zero-padded, source-major copy for the MFMA product: P2p[k][a] = P2T[a][k]
-    for (int k = 0; k < c->Kp; ++k)
-        for (int a = 0; a < c->Mp; ++a)
-            t[c->t_P2p + (size_t)k * c->Mp + a] = (k < c->NA && a < c->NA) ? (T)c->P2T[(size_t)a * c->NA + k] : T(0);
+    put(c->t_wdecb, c->wdecb);
+    if (c->strag) put(c->t_blk, c->blk);
+    // zero-padded, source-major copy for the MFMA product: P2p[b][k][a] = P2T[b][a][k]
+    const size_t NA2 = (size_t)c->NA * c->NA, KM = (size_t)c->Kp * c->Mp;
+    for (int b = 0; b < c->NB; ++b)
+        for (int k = 0; k < c->Kp; ++k)
+            for (int a = 0; a < c->Mp; ++a)
+                t[c->t_P2p + b * KM + (size_t)k * c->Mp + a] =
+                    (k < c->NA && a < c->NA) ? (T)c->P2T[b * NA2 + (size_t)a * c->NA + k] : T(0);
     // MFMA operand constants of the angular pass (nth = 16, 32)
     if (c->g.nth == 16 || c->g.nth == 32) {
         std::vector<float> kt(1024);
@@ -416,12 +598,25 @@ pbs_status upload_tables(pbs_ctx *c)
         d[c->d_wmom + c->G() + k] = c->dE[k];
         d[c->d_wmom + 2 * c->G() + k] = c->dE[k] * c->dE[k] / 6.0;
     }
-    std::vector<unsigned short> bf;
+    if (c->strag) {
+        std::memcpy(&d[c->d_A2], c->dA2.data(), c->G() * sizeof(double));
+        std::memcpy(&d[c->d_B2], c->dB2.data(), c->G() * sizeof(double));
+    }
+    std::vector<unsigned short> bf, bfb;
     if (c->Kpb > 0) {
-        transfer_table_bf16(c->P2T, c->NA, c->Mp, c->Kpb, bf);
+        // one [3][Mp][Kpb] split table per band
+        const size_t per = (size_t)3 * c->Mp * c->Kpb;
+        bf.resize(c->NB * per);
+        for (int b = 0; b < c->NB; ++b) {
+            std::vector<double> P(c->P2T.begin() + (size_t)b * NA2, c->P2T.begin() + (size_t)(b + 1) * NA2);
+            transfer_table_bf16(P, c->NA, c->Mp, c->Kpb, bfb);
+            std::copy(bfb.begin(), bfb.end(), bf.begin() + b * per);
+        }
         HIPCHK(c, hipMemcpyAsync(c->ws + c->o_bf, bf.data(), bf.size() * sizeof(unsigned short), hipMemcpyHostToDevice,
                                  c->stream));
     }
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->o_band, c->band.data(), c->band.size() * sizeof(int), hipMemcpyHostToDevice,
+                             c->stream));
     HIPCHK(c, hipMemcpyAsync(c->tabT<T>(), t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->tabD(), d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -489,6 +684,17 @@ EParams<T> eparams(pbs_ctx *c, int k, int lay_c, int lay_o, double h)
     P.G = c->G();
     P.NLINE = c->NLINE;
     P.NAPT = (long)c->NA * PBS_PT;
+    P.NB = c->NB;
+    P.band = reinterpret_cast<const int *>(c->ws + c->o_band);
+    P.wdecb = tb + c->t_wdecb;
+    if (c->strag) {
+        P.blk = tb + c->t_blk;
+        P.sfac_c = reinterpret_cast<T *>(c->ws + c->o_sfac);
+        P.sfac_o = P.sfac_c + (size_t)c->G() * 8 * c->NPpad;
+        P.dA2 = db + c->d_A2;
+        P.dB2 = db + c->d_B2;
+    }
+    P.NPpad = c->NPpad;
     if (c->feat_on && k == 0) {
         P.inj_c = c->fline(0);
         P.inj_o = c->fline(1);
@@ -514,12 +720,16 @@ pbs_status angular(pbs_ctx *c, int layer, double h, int k = -1, hipStream_t st =
 // with k's source product and the later generations' energy passes.  A generation's next energy pass
 // waits for its pending T A T; the march joins the side stream back at its end (join_side).
 template <typename T>
-pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h, int tat_layer = -1)
+pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h, int tat_layer = -1, int row_c = -1,
+                        int row_o = -1)
 {
+    // deposits go to the dose rows of the layers unless other rows are named (the extrapolated march)
+    if (row_c < 0) row_c = lay_c;
+    if (row_o < 0) row_o = lay_o;
     const int K1 = c->kact;
     // FP32 with the split-BF16 product: octet-per-thread E-pass, deposits summed per octet
     bool e8 = false;
-    if constexpr (sizeof(T) == 4) e8 = c->Kpb > 0 && c->src_mode != PBS_SRC_FP32;
+    if constexpr (sizeof(T) == 4) e8 = c->Kpb > 0 && c->src_mode != PBS_SRC_FP32 && !c->strag;
     const int nslot = e8 ? epass8_slots(c->NOCT) : c->NA;
     for (int k = 0; k < K1; ++k) {
         EParams<T> P = eparams<T>(c, k, (mode & MODE_CLOSE) ? lay_c : -1, (mode & MODE_OPEN) ? lay_o : -1, h);
@@ -529,7 +739,9 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h, in
         }
         {
             ProfScope ps(c, PBS_K_EPASS);
-            if constexpr (sizeof(T) == 4) {
+            if (c->strag) {
+                HIPCHK(c, launch_epass_strag<T>(P, mode, c->stream));
+            } else if constexpr (sizeof(T) == 4) {
                 if (e8) {
                     HIPCHK(c, launch_epass8(P, mode, c->stream));
                 } else {
@@ -566,6 +778,7 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h, in
             Q.Bl = Q.Bh + c->Wb_half;
             Q.s0 = (mode == MODE_OPEN) ? 1 : 0;
             Q.ns = (mode == MODE_PAIR) ? 2 : 1;
+            Q.band = c->NB > 1 ? reinterpret_cast<const int *>(c->ws + c->o_band) : nullptr;
             ProfScope ps(c, PBS_K_QGEMM);
             if constexpr (sizeof(T) == 4) {
                 if (c->Kpb > 0 && c->src_mode != PBS_SRC_FP32) {
@@ -581,9 +794,9 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h, in
     }
     ProfScope ps(c, PBS_K_DOSE);
     if (mode & MODE_CLOSE)
-        HIPCHK(c, launch_dose_reduce(c->edep(lay_c), c->dep(0, 0), K1, c->NA, nslot, c->NLINE, c->NP, c->stream));
+        HIPCHK(c, launch_dose_reduce(c->edep(row_c), c->dep(0, 0), K1, c->NA, nslot, c->NLINE, c->NP, c->stream));
     if (mode & MODE_OPEN)
-        HIPCHK(c, launch_dose_reduce(c->edep(lay_o), c->dep(1, 0), K1, c->NA, nslot, c->NLINE, c->NP, c->stream));
+        HIPCHK(c, launch_dose_reduce(c->edep(row_o), c->dep(1, 0), K1, c->NA, nslot, c->NLINE, c->NP, c->stream));
     if (c->feat_on) {
         // per-layer surrogate records: injected energy of both halves, moments after the opening half,
         // and the deposit of the primaries alone when further generations are marched
@@ -668,9 +881,50 @@ static pbs_status join_side(pbs_ctx *c)
     return PBS_OK;
 }
 
+// One Richardson-extrapolated step of layer s (section 5's higher-order splitting): A = S(dz) psi and
+// B = S(dz/2) S(dz/2) psi from the same state, psi = (4 B - A)/3, and the layer's deposit combined the
+// same way.  Every step is complete (no energy half-step carried into the next one).
+template <typename T>
+pbs_status extrapolated_step(pbs_ctx *c)
+{
+    const int s = c->step, nz = c->g.nz;
+    const double dz = c->g.dz;
+    const long n = (long)c->kact * c->G() * 2 * c->NLINE;
+    T *psi = c->psi<T>(0), *x0 = reinterpret_cast<T *>(c->ws + c->o_x0), *xA = reinterpret_cast<T *>(c->ws + c->o_xA);
+    HIPCHK(c, launch_fill<double>(c->edep(nz), 0.0, 2L * c->NP, c->stream));
+    HIPCHK(c, hipMemcpyAsync(x0, psi, n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    pbs_status r;
+    auto strang = [&](double h, int row, bool pair_inside) -> pbs_status {
+        pbs_status q;
+        if ((q = energy_chain<T>(c, MODE_OPEN, -1, s, 0.5 * h, -1, -1, row)) != PBS_OK) return q;
+        if ((q = transport<T>(c, 0.5 * h)) != PBS_OK) return q;
+        if ((q = angular<T>(c, s, h)) != PBS_OK) return q;
+        if ((q = transport<T>(c, 0.5 * h)) != PBS_OK) return q;
+        if (pair_inside) return energy_chain<T>(c, MODE_PAIR, s, s, 0.5 * h, -1, row, row);
+        return energy_chain<T>(c, MODE_CLOSE, s, -1, 0.5 * h, -1, row, -1);
+    };
+    // A: one step of dz into row nz
+    if ((r = strang(dz, nz, false)) != PBS_OK) return r;
+    HIPCHK(c, hipMemcpyAsync(xA, psi, n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(psi, x0, n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    // B: two steps of dz/2 into row nz + 1 (the closing half of the first fused with the opening of the second)
+    if ((r = strang(0.5 * dz, nz + 1, true)) != PBS_OK) return r;
+    if ((r = transport<T>(c, 0.25 * dz)) != PBS_OK) return r;
+    if ((r = angular<T>(c, s, 0.5 * dz)) != PBS_OK) return r;
+    if ((r = transport<T>(c, 0.25 * dz)) != PBS_OK) return r;
+    if ((r = energy_chain<T>(c, MODE_CLOSE, s, -1, 0.25 * dz, -1, nz + 1, -1)) != PBS_OK) return r;
+    HIPCHK(c, launch_combine<T>(psi, xA, T(4.0 / 3.0), T(-1.0 / 3.0), n, c->stream));
+    HIPCHK(c, launch_fill<double>(c->edep(s), 0.0, c->NP, c->stream));
+    HIPCHK(c, launch_combine<double>(c->edep(s), c->edep(nz + 1), 0.0, 4.0 / 3.0, c->NP, c->stream));
+    HIPCHK(c, launch_combine<double>(c->edep(s), c->edep(nz), 1.0, -1.0 / 3.0, c->NP, c->stream));
+    c->step = s + 1;
+    return PBS_OK;
+}
+
 template <typename T>
 pbs_status one_step(pbs_ctx *c)
 {
+    if (c->order == 4) return extrapolated_step<T>(c);
     const int s = c->step;
     const double dz = c->g.dz;
     // a context without the side stream (bound to the static scratch) always marches on one stream
@@ -705,7 +959,7 @@ pbs_status steps(pbs_ctx *c, int n)
 template <typename T>
 pbs_status close_beam(pbs_ctx *c)
 {
-    if (c->step == 0) return PBS_OK;
+    if (c->step == 0 || c->order == 4) return PBS_OK;   // extrapolated steps are complete
     return energy_chain<T>(c, MODE_CLOSE, c->step - 1, -1, 0.5 * c->g.dz);
 }
 
@@ -954,6 +1208,18 @@ pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precisi
         return PBS_EINVAL;
     if (ph.stopping != PBS_STOP_BRAGG_KLEEMAN && ph.stopping != PBS_STOP_BETHE) return PBS_EINVAL;
     if (ph.stopping == PBS_STOP_BETHE && !(ph.e_floor >= 0.5)) return PBS_EINVAL;
+    if (ph.straggling != 0 && ph.straggling != 1) return PBS_EINVAL;
+    if (ph.scattering != PBS_SCAT_HIGHLAND && ph.scattering != PBS_SCAT_RUTHERFORD) return PBS_EINVAL;
+    if (ph.material < PBS_MAT_WATER || ph.material > PBS_MAT_AIR) return PBS_EINVAL;
+    // the range fit is water's; the other media and the straggling need the Bethe-Bloch form
+    if ((ph.material != PBS_MAT_WATER || ph.straggling) && ph.stopping != PBS_STOP_BETHE) return PBS_EINVAL;
+    if (ph.nuc_bands < 0 || ph.nuc_bands > 4) return PBS_EINVAL;
+    for (int b = 0; b < ph.nuc_bands; ++b) {
+        if (!std::isfinite(ph.nuc_e[b]) || !(ph.nuc_lambda[b] >= 0) || !std::isfinite(ph.nuc_lambda[b]) ||
+            !(ph.nuc_alpha[b] >= 1.0) || !std::isfinite(ph.nuc_alpha[b]) || !finite_pos(ph.nuc_beta[b]))
+            return PBS_EINVAL;
+        if (b > 0 && !(ph.nuc_e[b] > ph.nuc_e[b - 1])) return PBS_EINVAL;
+    }
     if (!apass_supported(g.nth)) return PBS_EUNSUPPORTED;
     pbs_ctx *c = new (std::nothrow) pbs_ctx();
     if (!c) return PBS_ENOMEM;
@@ -975,7 +1241,8 @@ pbs_status pbs_create(const pbs_grid *grid, const pbs_physics *phys, int precisi
     if (c->NA >= 128) {   // source product on MFMA
         c->Kp = (c->NA + 15) / 16 * 16;
         c->Mp = (c->NA + 127) / 128 * 128;
-        if (precision == PBS_FP32) {
+        if (precision == PBS_FP32 && !ph.straggling) {
+            // split-BF16 source product (its scans come from the straggling-free energy passes)
             c->Kpb = (c->NA + PBS_KPB_ALIGN - 1) / PBS_KPB_ALIGN * PBS_KPB_ALIGN;
             c->src_mode = PBS_DEFAULT_SRC;
         }
@@ -1021,6 +1288,52 @@ pbs_status pbs_set_phantom(pbs_ctx *c, const double *rho, size_t n)
     c->rho_host.assign(rho, rho + n);
     c->state = ST_PHANTOM;
     return PBS_OK;
+}
+
+pbs_status pbs_resample_phantom(const pbs_grid *g, const double *vox, int vnz, int vnx, int vny, double vdz,
+                                double vdx, double vdy, double x_lo, double y_lo, double *out)
+{
+    if (!g || !vox || !out || vnz < 1 || vnx < 1 || vny < 1 || g->nz < 1 || g->nx < 1 || g->ny < 1)
+        return PBS_EINVAL;
+    if (!finite_pos(vdz) || !finite_pos(vdx) || !finite_pos(vdy) || !std::isfinite(x_lo) || !std::isfinite(y_lo) ||
+        !finite_pos(g->dz) || !finite_pos(g->x_half) || !finite_pos(g->y_half))
+        return PBS_EINVAL;
+    const size_t nv = (size_t)vnz * vnx * vny;
+    for (size_t i = 0; i < nv; ++i)
+        if (!finite_pos(vox[i])) return PBS_EINVAL;
+    const double dx = 2.0 * g->x_half / g->nx, dy = 2.0 * g->y_half / g->ny;
+    auto nearest = [](double c, double lo, double d, int n) {
+        const long i = (long)std::floor((c - lo) / d);
+        return (int)std::min<long>(std::max<long>(i, 0), n - 1);
+    };
+    for (int s = 0; s < g->nz; ++s) {
+        const int k = nearest((s + 0.5) * g->dz, 0.0, vdz, vnz);
+        for (int p = 0; p < g->nx; ++p) {
+            const int i = nearest(-g->x_half + (p + 0.5) * dx, x_lo, vdx, vnx);
+            for (int q = 0; q < g->ny; ++q) {
+                const int j = nearest(-g->y_half + (q + 0.5) * dy, y_lo, vdy, vny);
+                out[((size_t)s * g->nx + p) * g->ny + q] = vox[((size_t)k * vnx + i) * vny + j];
+            }
+        }
+    }
+    return PBS_OK;
+}
+
+pbs_status pbs_set_phantom_voxels(pbs_ctx *c, const double *vox, int vnz, int vnx, int vny, double vdz, double vdx,
+                                  double vdy, double x_lo, double y_lo)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->state < ST_BOUND) return fail(c, PBS_ESTATE, "set_phantom_voxels before bind");
+    std::vector<double> rho;
+    try {
+        rho.resize((size_t)c->g.nz * c->NP);
+    } catch (...) {
+        return fail(c, PBS_ENOMEM, "host allocation of the resampled phantom failed");
+    }
+    const pbs_status r = pbs_resample_phantom(&c->g, vox, vnz, vnx, vny, vdz, vdx, vdy, x_lo, y_lo, rho.data());
+    if (r != PBS_OK) return fail(c, r, "voxel phantom: sizes, spacings and corner must be finite and positive, "
+                                       "densities finite and > 0");
+    return pbs_set_phantom(c, rho.data(), rho.size());
 }
 
 pbs_status pbs_set_beam(pbs_ctx *c, const pbs_beam *b)
@@ -1090,6 +1403,9 @@ pbs_status pbs_set_surrogate(pbs_ctx *c, const void *weights, size_t bytes, doub
     if (c->ws) return fail(c, PBS_ESTATE, "set_surrogate must precede bind");
     if (c->g.ngen != 2) return fail(c, PBS_EINVAL, "the surrogate replaces generation 1 of a K = 1 grid (ngen = 2)");
     if (c->g.ny > 64) return fail(c, PBS_EUNSUPPORTED, "surrogate images are at most 64 cells wide (ny <= 64)");
+    if (c->strag || c->NB > 1 || c->order != 2)
+        return fail(c, PBS_EUNSUPPORTED,
+                    "the surrogate is trained without straggling, with one nuclear band and Strang steps");
     if (!weights) {
         if (bytes != 0) return fail(c, PBS_EINVAL, "weights NULL with nonzero size");
         c->sur = 1;
@@ -1233,6 +1549,17 @@ pbs_status pbs_set_source_precision(pbs_ctx *c, int mode)
     if (mode != PBS_SRC_FP32 && c->Kpb == 0)
         return fail(c, PBS_EUNSUPPORTED, "split-BF16 source product needs an FP32 context with >= 128 angular unknowns");
     c->src_mode = mode;
+    return PBS_OK;
+}
+
+pbs_status pbs_set_splitting(pbs_ctx *c, int order)
+{
+    if (!c) return PBS_EINVAL;
+    if (c->ws) return fail(c, PBS_ESTATE, "set_splitting must precede bind (it sizes the workspace)");
+    if (order != 2 && order != 4) return fail(c, PBS_EINVAL, "splitting order must be 2 or 4");
+    if (order == 4 && c->sur) return fail(c, PBS_EUNSUPPORTED, "the surrogate marches Strang steps only");
+    c->order = order;
+    layout(c);
     return PBS_OK;
 }
 

@@ -396,6 +396,7 @@ pbs_status pbs_batch_create(const pbs_grid *grids, const pbs_beam *beams, int nb
             return PBS_EINVAL;   // one shape class per batch
     }
     if (g0.nth < 16) return PBS_EUNSUPPORTED;   // batched path: >= 128 angular unknowns (MFMA source product)
+    if (phys->straggling || phys->nuc_bands > 1) return PBS_EUNSUPPORTED;   // single-beam path only
     pbs_batch *b = new (std::nothrow) pbs_batch();
     if (!b) return PBS_ENOMEM;
     b->nb = nbeams;

@@ -49,6 +49,18 @@ struct EParams {
     // and number moments of psi^1 after the opening half-step
     double *inj_c = nullptr, *inj_o = nullptr, *mom_e = nullptr, *mom_n = nullptr;
     const double *wmom = nullptr;   // [3G] moment weights: E_g dE_g and dE_g^2/6 (energy), dE_g (number) at G + g
+    // nuclear bands (NB > 1): the scan is a sum of per-band scans with the source group's decay,
+    // U^b_g = [band_g = b] wc_g psi1_g + wdecb[b*G + g] U^b_{g+1}
+    int NB = 1;
+    const int *band = nullptr;
+    const T *wdecb = nullptr;
+    // straggling (blk non-null): rho-free 2x2 blocks [G][12] (Lo, Di, Up), per-cell elimination factors of
+    // the closing / opening half-step sfac[g][8][NPpad] (Dinv row-major, then F = a Up Dinv_{g+1}), and the
+    // deposit weights of psi1, psi2 of the whole operator
+    const T *blk = nullptr;
+    T *sfac_c = nullptr, *sfac_o = nullptr;
+    const double *dA2 = nullptr, *dB2 = nullptr;
+    long NPpad = 0;
 };
 
 template <typename T>
@@ -85,6 +97,8 @@ struct QParams {
     int NA, NPB, G;
     int s0, ns;             // half-step sums s0 .. s0+ns-1
     long NLINE;
+    const int *band = nullptr;   // nuclear band of every destination group (null: one band); the transfer
+                                 // matrices of the bands follow each other (P2T, P2p, split tables)
 };
 
 // One beam of a batch (device copy of its descriptor).  Beams of one batch share the lateral and
@@ -140,6 +154,8 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
 
 // launchers (explicitly instantiated for float and double); return hipGetLastError()
 template <typename T> hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st);
+// energy pass with straggling (P.blk set): factor kernel per cell and half-step, then one thread per line
+template <typename T> hipError_t launch_epass_strag(const EParams<T> &P, int mode, hipStream_t st);
 // FP32 with split-BF16 scans (Wh set or no next generation): thread per (cell, group of
 // PBS_EPASS_LPT lines of an octet); deposits and records summed per group at line slot a = group
 // (reduce over epass8_slots(NOCT) slots)
@@ -150,6 +166,8 @@ template <typename T> hipError_t launch_tpass(const TParams<T> &P, hipStream_t s
 template <typename T> hipError_t launch_apass(const AParams<T> &P, int nth, long nstack, hipStream_t st);
 template <typename T> hipError_t launch_qgemm(const QParams<T> &P, hipStream_t st);
 template <typename T> hipError_t launch_fill(T *p, T v, long n, hipStream_t st);
+// y = a y + b x elementwise
+template <typename T> hipError_t launch_combine(T *y, const T *x, T a, T b, long n, hipStream_t st);
 // edep_layer[pq] += sum over generations and the first nslot angular slots of dep
 hipError_t launch_dose_reduce(double *edep_layer, const double *dep, int ngen, int NA, int nslot, long NLINE, int NP,
                               hipStream_t st);

@@ -37,6 +37,19 @@ struct pbs_ctx {
     std::vector<double> E_face, E_mid, dE, S_face, sig_tr, kappa, Sm, Sp, wc, wdec, invdE, dA, dB, dInj, theta, sinS,
         lam, P2T;
     double dBot = 0;
+    // nuclear bands (App. A.4): NB angular laws P2T [NB][NA][NA], band of every group, per-band decays of the
+    // energy scan [NB][G]
+    int NB = 1;
+    std::vector<int> band;
+    std::vector<double> wdecb;
+    // straggling: rho-free 2x2 blocks of the energy operator per group [G][12] = Lo (to g-1), Di, Up (to g+1),
+    // row-major, and the deposit functional's weights of psi1, psi2 [G] (the whole operator)
+    bool strag = false;
+    std::vector<double> blk, dA2, dB2;
+    // splitting in depth: 2 Strang steps, 4 Richardson-extrapolated Strang steps (two state copies and two
+    // scratch deposit rows edep(nz), edep(nz + 1))
+    int order = 2;
+    size_t o_x0 = 0, o_xA = 0;
     // workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -50,14 +63,16 @@ struct pbs_ctx {
     size_t o_psi = 0, o_W = 0, o_Q = 0, o_dep = 0, o_edep = 0, o_dout = 0, o_rhoT = 0, o_rhoD = 0, o_tabT = 0,
            o_tabD = 0, total = 0;
     // table offsets (elements) inside the T and double table blocks
-    size_t t_Sm, t_Sp, t_kap, t_wc, t_wdec, t_invdE, t_sig, t_theta, t_S, t_lam, t_P2T, t_P2p, t_K32, t_count;
+    size_t t_Sm, t_Sp, t_kap, t_wc, t_wdec, t_invdE, t_sig, t_theta, t_S, t_lam, t_P2T, t_P2p, t_K32, t_wdecb, t_blk,
+        t_count;
+    size_t o_band = 0, o_sfac = 0;   // band indices [G] (int); straggling factors [2][G][8][NPpad] (T)
     int Kp = 0, Mp = 0;           // padded source product (MFMA path, FP32 with NA >= 128)
     int Kpb = 0;                  // k padding of the split-BF16 operand tables
     int NOCT = 0;                 // source-node octets of the split-BF16 W layout
     size_t Wb_half = 0;           // elements of one of the hi / lo arrays
     int src_mode = PBS_SRC_FP32;
     size_t o_bf = 0;
-    size_t d_A, d_B, d_Inj, d_E1, d_E2, d_lat, d_count;
+    size_t d_A, d_B, d_Inj, d_E1, d_E2, d_lat, d_A2, d_B2, d_count;
     int state = ST_CREATED;
     int step = 0;
     // bound to the static scratch of device static_dev (-1: caller workspace) when the scratch's owner

@@ -27,7 +27,7 @@ __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 // One thread per line (FP64 contexts, and FP32 contexts whose source product takes the plain scan W):
 // block = one lateral tile pb and one octet of angular lines a = 8*oct + e (e = tid/32), 32 cells
 // pt = tid%32.  FP32 contexts with the split-BF16 product use epass8_body below.
-template <typename T, int MODE>
+template <typename T, int MODE, bool BANDS = false>
 __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
 {
     constexpr bool CL = (MODE & MODE_CLOSE) != 0;
@@ -47,6 +47,7 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
     const T ac = (T)dac, ao = (T)dao;
     T fin = 0, fcl = 0, fop = 0;    // psi1 - psi2 of group g+1: input, after close, after open
     T U0 = 0, U1 = 0, U2 = 0;       // re-emission energy scans of states 0, 1, 2
+    T U0b[4] = {}, U1b[4] = {}, U2b[4] = {};   // per-band scans (BANDS)
     double ph0 = 0, ph1 = 0, ph2 = 0, injc = 0, injo = 0;
     T fic = 0, fio = 0, fme = 0, fmn = 0;   // surrogate records (energy sent to the next generation, moments)
     const bool hasQ = P.Q != nullptr, hasW = P.W != nullptr;
@@ -107,9 +108,23 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
             // energy scans of the three states; the next generation needs the sums 0+1 and 1+2
             const T w = P.wc[g], dec = P.wdec[g], idE = P.invdE[g];
             const long o = (long)g * S + line;
-            if (CL) U0 = w * x1 + dec * U0;
-            U1 = w * y1 + dec * U1;
-            if (OP) U2 = w * z1 + dec * U2;
+            if constexpr (BANDS) {
+                // the sum of one scan per band, each with its band's decay; group g feeds its own band
+                const int bg = P.band[g];
+                U0 = U1 = U2 = T(0);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (b < P.NB) {
+                        const T d = P.wdecb[b * P.G + g], wb = b == bg ? w : T(0);
+                        if (CL) U0 += (U0b[b] = wb * x1 + d * U0b[b]);
+                        U1 += (U1b[b] = wb * y1 + d * U1b[b]);
+                        if (OP) U2 += (U2b[b] = wb * z1 + d * U2b[b]);
+                    }
+            } else {
+                if (CL) U0 = w * x1 + dec * U0;
+                U1 = w * y1 + dec * U1;
+                if (OP) U2 = w * z1 + dec * U2;
+            }
             if (feat) {
                 // energy the re-emission puts into the next generation (the dInj functional of its
                 // source summed over destination angles, which the angular law conserves), moments
@@ -142,25 +157,210 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
     }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool BANDS>
 __global__ __launch_bounds__(256) void epass_kernel(EParams<T> P)
 {
-    epass_body<T, MODE>(P, blockIdx.x);
+    epass_body<T, MODE, BANDS>(P, blockIdx.x);
+}
+
+template <typename T, bool BANDS>
+static void launch_epass_t(const EParams<T> &P, int mode, unsigned nb, hipStream_t st)
+{
+    if (mode == MODE_PAIR)
+        hipLaunchKernelGGL((epass_kernel<T, MODE_PAIR, BANDS>), dim3(nb), dim3(256), 0, st, P);
+    else if (mode == MODE_OPEN)
+        hipLaunchKernelGGL((epass_kernel<T, MODE_OPEN, BANDS>), dim3(nb), dim3(256), 0, st, P);
+    else
+        hipLaunchKernelGGL((epass_kernel<T, MODE_CLOSE, BANDS>), dim3(nb), dim3(256), 0, st, P);
 }
 
 template <typename T>
 hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st)
 {
     if (P.Wh != nullptr) return hipErrorInvalidValue;   // split scans: launch_epass8
+    if (P.NB > 4) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)((P.NLINE / P.NAPT) * P.NOCT);
-    if (mode == MODE_PAIR)
-        hipLaunchKernelGGL((epass_kernel<T, MODE_PAIR>), dim3(nb), dim3(256), 0, st, P);
-    else if (mode == MODE_OPEN)
-        hipLaunchKernelGGL((epass_kernel<T, MODE_OPEN>), dim3(nb), dim3(256), 0, st, P);
+    if (P.NB > 1)
+        launch_epass_t<T, true>(P, mode, nb, st);
     else
-        hipLaunchKernelGGL((epass_kernel<T, MODE_CLOSE>), dim3(nb), dim3(256), 0, st, P);
+        launch_epass_t<T, false>(P, mode, nb, st);
     return hipGetLastError();
 }
+
+// ------------------------------------------------------------------ energy pass with straggling
+// With straggling (section 3.2's (1/2) d^2/dE^2 (T psi)) every energy line is block-tridiagonal:
+//   (I - a D0_g) X*_g - a Lo_g X*_{g-1} - a Up_g X*_{g+1} = X_g + a (D0 X)_g + a [q_g, 0],   a = h rho / 2,
+// with the rho-free 2x2 blocks Lo (to g-1), Di (D0_gg), Up (to g+1) of the host tables.  The matrix
+// depends only on the cell's density, so the elimination from the top,
+//   Dt_g = (I - a Di_g) - a^2 Up_g Dt_{g+1}^-1 Lo_{g+1},   F_g = a Up_g Dt_{g+1}^-1,
+// is done once per cell (factor kernel, FP64, stored as [g][8][NPpad]: Dt_g^-1 row-major, then F_g); each
+// line then sweeps down (bt_g = b_g + F_g bt_{g+1}, kept in place of X_g) and back up
+// (X*_g = Dt_g^-1 (bt_g + a Lo_g X*_{g-1})).  The energy scans of the next generation's source take a
+// third sweep down over X*.
+
+template <typename T>
+__global__ __launch_bounds__(256) void strag_factor_kernel(const T *__restrict__ blk, const T *__restrict__ rho, T h,
+                                                             int G, long NPpad, T *__restrict__ sfac)
+{
+    const long pq = (long)blockIdx.x * 256 + threadIdx.x;
+    if (pq >= NPpad) return;
+    const double a = 0.5 * (double)h * (double)rho[pq];
+    double di[4] = {0, 0, 0, 0};   // Dt_{g+1}^-1
+    for (int g = G - 1; g >= 0; --g) {
+        const T *B = blk + (size_t)g * 12;
+        double M[4] = {1.0 - a * (double)B[4], -a * (double)B[5], -a * (double)B[6], 1.0 - a * (double)B[7]};
+        double F[4] = {0, 0, 0, 0};
+        if (g + 1 < G) {
+            const T *Bn = blk + (size_t)(g + 1) * 12;   // Lo of group g+1
+            const double U[4] = {a * (double)B[8], a * (double)B[9], a * (double)B[10], a * (double)B[11]};
+            F[0] = U[0] * di[0] + U[1] * di[2], F[1] = U[0] * di[1] + U[1] * di[3];
+            F[2] = U[2] * di[0] + U[3] * di[2], F[3] = U[2] * di[1] + U[3] * di[3];
+            const double L[4] = {a * (double)Bn[0], a * (double)Bn[1], a * (double)Bn[2], a * (double)Bn[3]};
+            M[0] -= F[0] * L[0] + F[1] * L[2], M[1] -= F[0] * L[1] + F[1] * L[3];
+            M[2] -= F[2] * L[0] + F[3] * L[2], M[3] -= F[2] * L[1] + F[3] * L[3];
+        }
+        const double det = M[0] * M[3] - M[1] * M[2];
+        di[0] = M[3] / det, di[1] = -M[1] / det, di[2] = -M[2] / det, di[3] = M[0] / det;
+        T *o = sfac + (size_t)g * 8 * NPpad + pq;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            o[q * NPpad] = (T)di[q];
+            o[(4 + q) * NPpad] = (T)F[q];
+        }
+    }
+}
+
+// one step of the re-emission scan (single law, or the sum over bands) at group g; returns the scan value
+template <typename T, bool BANDS>
+__device__ __forceinline__ T scan_step(const EParams<T> &P, int g, T x, T &U, T (&Ub)[4])
+{
+    const T w = P.wc[g];
+    if constexpr (BANDS) {
+        const int bg = P.band[g];
+        T u = T(0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (b < P.NB) u += (Ub[b] = (b == bg ? w : T(0)) * x + P.wdecb[b * P.G + g] * Ub[b]);
+        return u;
+    } else {
+        U = w * x + P.wdec[g] * U;
+        return U;
+    }
+}
+
+template <typename T, bool BANDS>
+__device__ void strag_half(const EParams<T> &P, long line, long pq, int half, double &dep_out)
+{
+    const long S = P.NLINE, QS = (long)P.G * S;
+    const T *rho = half ? P.rho_o : P.rho_c;
+    const T *sf = (half ? P.sfac_o : P.sfac_c) + pq;
+    const long FS = P.NPpad;
+    const double ad = 0.5 * (double)P.h * (double)rho[pq];
+    const T a = (T)ad;
+    const bool hasQ = P.Q != nullptr, hasW = P.W != nullptr;
+    T *W = hasW ? P.W + (long)half * QS : nullptr;
+    const T *Q = hasQ ? P.Q + (long)half * QS : nullptr;
+    double phn = 0, phs = 0, inj = 0;
+    // sweep down: right-hand side, elimination (bt kept in place of X), scan of X^n
+    T xu1 = 0, xu2 = 0, bu1 = 0, bu2 = 0;   // X^n and bt of group g+1
+    T x1 = P.psi[(2L * (P.G - 1)) * S + line], x2 = P.psi[(2L * (P.G - 1) + 1) * S + line];
+    T U = 0, Ub[4] = {};
+    for (int g = P.G - 1; g >= 0; --g) {
+        T xl1 = 0, xl2 = 0;   // X^n of group g-1
+        if (g > 0) {
+            xl1 = P.psi[(2L * (g - 1)) * S + line];
+            xl2 = P.psi[(2L * (g - 1) + 1) * S + line];
+        }
+        const T *B = P.blk + (size_t)g * 12;
+        const T q = hasQ ? Q[(long)g * S + line] : T(0);
+        T b1 = x1 + a * (B[0] * xl1 + B[1] * xl2 + B[4] * x1 + B[5] * x2 + B[8] * xu1 + B[9] * xu2 + q);
+        T b2 = x2 + a * (B[2] * xl1 + B[3] * xl2 + B[6] * x1 + B[7] * x2 + B[10] * xu1 + B[11] * xu2);
+        const T *Fg = sf + (size_t)g * 8 * FS + 4 * FS;
+        b1 += Fg[0] * bu1 + Fg[FS] * bu2;
+        b2 += Fg[2 * FS] * bu1 + Fg[3 * FS] * bu2;
+        P.psi[(2L * g) * S + line] = b1;
+        P.psi[(2L * g + 1) * S + line] = b2;
+        phn += P.dA2[g] * (double)x1 + P.dB2[g] * (double)x2;
+        if (hasQ) inj += P.dInj[g] * (double)q;
+        if (hasW) W[(long)g * S + line] = scan_step<T, BANDS>(P, g, x1, U, Ub) * P.invdE[g];
+        xu1 = x1, xu2 = x2, bu1 = b1, bu2 = b2;
+        x1 = xl1, x2 = xl2;
+    }
+    // sweep up: back-substitution
+    T y1p = 0, y2p = 0;
+    for (int g = 0; g < P.G; ++g) {
+        const T *B = P.blk + (size_t)g * 12;
+        T c1 = P.psi[(2L * g) * S + line], c2 = P.psi[(2L * g + 1) * S + line];
+        c1 += a * (B[0] * y1p + B[1] * y2p);
+        c2 += a * (B[2] * y1p + B[3] * y2p);
+        const T *Di = sf + (size_t)g * 8 * FS;
+        const T y1 = Di[0] * c1 + Di[FS] * c2, y2 = Di[2 * FS] * c1 + Di[3 * FS] * c2;
+        P.psi[(2L * g) * S + line] = y1;
+        P.psi[(2L * g + 1) * S + line] = y2;
+        phs += P.dA2[g] * (double)y1 + P.dB2[g] * (double)y2;
+        y1p = y1, y2p = y2;
+    }
+    // sweep down: the scan of X*, added to that of X^n
+    if (hasW) {
+        U = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) Ub[b] = 0;
+        for (int g = P.G - 1; g >= 0; --g)
+            W[(long)g * S + line] += scan_step<T, BANDS>(P, g, P.psi[(2L * g) * S + line], U, Ub) * P.invdE[g];
+    }
+    dep_out = ad * (phn + phs - inj) * P.scale;
+}
+
+template <typename T, int MODE, bool BANDS>
+__global__ __launch_bounds__(256) void epass_strag_kernel(EParams<T> P)
+{
+    const int NA = (int)(P.NAPT / PBS_PT);
+    const int bx = blockIdx.x, pbk = bx / P.NOCT, oct = bx % P.NOCT;
+    const int e = threadIdx.x >> 5, ptc = threadIdx.x & 31;
+    const int a = oct * 8 + e;
+    if (a >= NA) return;
+    const long line = ((long)pbk * NA + a) * PBS_PT + ptc;
+    const long pq = (long)pbk * PBS_PT + ptc;
+    double d;
+    if (MODE & MODE_CLOSE) {
+        strag_half<T, BANDS>(P, line, pq, 0, d);
+        P.dep_c[line] = d;
+    }
+    if (MODE & MODE_OPEN) {
+        strag_half<T, BANDS>(P, line, pq, 1, d);
+        P.dep_o[line] = d;
+    }
+}
+
+template <typename T, bool BANDS>
+static void launch_epass_strag_t(const EParams<T> &P, int mode, unsigned nb, hipStream_t st)
+{
+    if (mode == MODE_PAIR)
+        hipLaunchKernelGGL((epass_strag_kernel<T, MODE_PAIR, BANDS>), dim3(nb), dim3(256), 0, st, P);
+    else if (mode == MODE_OPEN)
+        hipLaunchKernelGGL((epass_strag_kernel<T, MODE_OPEN, BANDS>), dim3(nb), dim3(256), 0, st, P);
+    else
+        hipLaunchKernelGGL((epass_strag_kernel<T, MODE_CLOSE, BANDS>), dim3(nb), dim3(256), 0, st, P);
+}
+
+template <typename T>
+hipError_t launch_epass_strag(const EParams<T> &P, int mode, hipStream_t st)
+{
+    if (!P.blk || !P.dA2 || !P.dB2 || P.Wh != nullptr || P.inj_c != nullptr || P.NB > 4) return hipErrorInvalidValue;
+    const unsigned nf = (unsigned)((P.NPpad + 255) / 256);
+    if (mode & MODE_CLOSE) hipLaunchKernelGGL(strag_factor_kernel<T>, dim3(nf), dim3(256), 0, st, P.blk, P.rho_c, P.h,
+                                              P.G, P.NPpad, P.sfac_c);
+    if (mode & MODE_OPEN) hipLaunchKernelGGL(strag_factor_kernel<T>, dim3(nf), dim3(256), 0, st, P.blk, P.rho_o, P.h,
+                                             P.G, P.NPpad, P.sfac_o);
+    const unsigned nb = (unsigned)((P.NLINE / P.NAPT) * P.NOCT);
+    if (P.NB > 1)
+        launch_epass_strag_t<T, true>(P, mode, nb, st);
+    else
+        launch_epass_strag_t<T, false>(P, mode, nb, st);
+    return hipGetLastError();
+}
+template hipError_t launch_epass_strag<float>(const EParams<float> &, int, hipStream_t);
+template hipError_t launch_epass_strag<double>(const EParams<double> &, int, hipStream_t);
 
 // Energy pass of FP32 contexts with the split-BF16 source product: one thread per (lateral cell,
 // group of PBS_EPASS_LPT consecutive angular lines of an octet a = 8 oct + e).  The thread sweeps the
@@ -176,7 +376,7 @@ hipError_t launch_epass(const EParams<T> &P, int mode, hipStream_t st)
 #define EP_LD(p) __builtin_nontemporal_load(p)
 #define EP_ST(v, p) __builtin_nontemporal_store(v, p)
 // FEAT / LO = false compile out the surrogate records and the lo half of the split scans.
-template <int MODE, bool FEAT = true, bool LO = true>
+template <int MODE, bool FEAT = true, bool LO = true, bool BANDS = false>
 __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
 {
     constexpr int L = PBS_EPASS_LPT;
@@ -203,6 +403,9 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
     float fin[L], fcl[L], fop[L], U0[L], U1[L], U2[L];
 #pragma unroll
     for (int e = 0; e < L; ++e) fin[e] = fcl[e] = fop[e] = U0[e] = U1[e] = U2[e] = 0.f;
+    float U0b[BANDS ? 4 : 1][L] = {}, U1b[BANDS ? 4 : 1][L] = {}, U2b[BANDS ? 4 : 1][L] = {};   // per-band scans
+    // rounding residue of the BF16 scans carried from group g+1 into group g (hi-only products)
+    float rcc[L] = {}, rco[L] = {};
     double ph0 = 0, ph1 = 0, ph2 = 0, injc = 0, injo = 0;
     float fic = 0, fio = 0, fme = 0, fmn = 0;
     const bool hasQ = P.Q != nullptr, hasW = P.Wh != nullptr, hasL = LO && P.Wl != nullptr,
@@ -270,17 +473,43 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
                 sqo += (double)qo[e];
             }
             if (hasW || feat) {
-                if (CL) U0[e] = w * x1[e] + dec * U0[e];
-                U1[e] = w * y1 + dec * U1[e];
-                if (OP) U2[e] = w * z1 + dec * U2[e];
+                if constexpr (BANDS) {
+                    // the sum of one scan per band, each with its band's decay; group g feeds its own band
+                    const int bg = P.band[g];
+                    U0[e] = U1[e] = U2[e] = 0.f;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (b < P.NB) {
+                            const float d = P.wdecb[b * P.G + g], wb = b == bg ? w : 0.f;
+                            if (CL) U0[e] += (U0b[b][e] = wb * x1[e] + d * U0b[b][e]);
+                            U1[e] += (U1b[b][e] = wb * y1 + d * U1b[b][e]);
+                            if (OP) U2[e] += (U2b[b][e] = wb * z1 + d * U2b[b][e]);
+                        }
+                } else {
+                    if (CL) U0[e] = w * x1[e] + dec * U0[e];
+                    U1[e] = w * y1 + dec * U1[e];
+                    if (OP) U2[e] = w * z1 + dec * U2[e];
+                }
                 const float vc = CL ? (U0[e] + U1[e]) * idE : 0.f;
                 const float vo = OP ? (U1[e] + U2[e]) * idE : 0.f;
-                const __bf16 bc = (__bf16)vc, bo = (__bf16)vo;
-                hc[e] = __builtin_bit_cast(unsigned short, bc);
-                ho[e] = __builtin_bit_cast(unsigned short, bo);
-                if constexpr (LO) {
-                    lc[e] = __builtin_bit_cast(unsigned short, (__bf16)(vc - (float)bc));
-                    lo[e] = __builtin_bit_cast(unsigned short, (__bf16)(vo - (float)bo));
+                if (hasL) {
+                    const __bf16 bc = (__bf16)vc, bo = (__bf16)vo;
+                    hc[e] = __builtin_bit_cast(unsigned short, bc);
+                    ho[e] = __builtin_bit_cast(unsigned short, bo);
+                    if constexpr (LO) {
+                        lc[e] = __builtin_bit_cast(unsigned short, (__bf16)(vc - (float)bc));
+                        lo[e] = __builtin_bit_cast(unsigned short, (__bf16)(vo - (float)bo));
+                    }
+                } else {
+                    // only the rounded value enters the product: round with error feedback along the
+                    // groups, so that the line's rounding errors telescope in the number and energy of
+                    // the re-emitted protons instead of adding up
+                    const float tc = vc + rcc[e], to = vo + rco[e];
+                    const __bf16 bc = (__bf16)tc, bo = (__bf16)to;
+                    hc[e] = __builtin_bit_cast(unsigned short, bc);
+                    ho[e] = __builtin_bit_cast(unsigned short, bo);
+                    rcc[e] = tc - (float)bc;
+                    rco[e] = to - (float)bo;
                 }
                 if (feat) {
                     const float wi = (float)P.dInj[g];
@@ -338,28 +567,37 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
 
 // 5 waves per SIMD for the plain kernels (96 VGPRs, a few spilled registers): measured faster than 4
 // waves without spills
-template <int MODE, bool FEAT, bool LO>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT ? 1 : 5))) void epass8_kernel(EParams<float> P)
+template <int MODE, bool FEAT, bool LO, bool BANDS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT || BANDS ? 1 : 5))) void epass8_kernel(
+    EParams<float> P)
 {
-    epass8_body<MODE, FEAT, LO>(P, (long)blockIdx.x * 256 + threadIdx.x);
+    epass8_body<MODE, FEAT, LO, BANDS>(P, (long)blockIdx.x * 256 + threadIdx.x);
 }
 
-template <bool FEAT, bool LO>
+template <bool FEAT, bool LO, bool BANDS = false>
 static void launch_epass8_t(const EParams<float> &P, int mode, unsigned nb, hipStream_t st)
 {
     if (mode == MODE_PAIR)
-        hipLaunchKernelGGL((epass8_kernel<MODE_PAIR, FEAT, LO>), dim3(nb), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((epass8_kernel<MODE_PAIR, FEAT, LO, BANDS>), dim3(nb), dim3(256), 0, st, P);
     else if (mode == MODE_OPEN)
-        hipLaunchKernelGGL((epass8_kernel<MODE_OPEN, FEAT, LO>), dim3(nb), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((epass8_kernel<MODE_OPEN, FEAT, LO, BANDS>), dim3(nb), dim3(256), 0, st, P);
     else
-        hipLaunchKernelGGL((epass8_kernel<MODE_CLOSE, FEAT, LO>), dim3(nb), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((epass8_kernel<MODE_CLOSE, FEAT, LO, BANDS>), dim3(nb), dim3(256), 0, st, P);
 }
 
 hipError_t launch_epass8(const EParams<float> &P, int mode, hipStream_t st)
 {
     const long nthreads = (P.NLINE / P.NAPT) * P.NOCT * (8 / PBS_EPASS_LPT) * PBS_PT;
     const unsigned nb = (unsigned)((nthreads + 255) / 256);
-    if (P.inj_c != nullptr)
+    if (P.NB > 4) return hipErrorInvalidValue;
+    if (P.NB > 1) {
+        // banded nuclear data: no surrogate records
+        if (P.inj_c != nullptr) return hipErrorInvalidValue;
+        if (P.Wl != nullptr)
+            launch_epass8_t<false, true, true>(P, mode, nb, st);
+        else
+            launch_epass8_t<false, false, true>(P, mode, nb, st);
+    } else if (P.inj_c != nullptr)
         launch_epass8_t<true, true>(P, mode, nb, st);
     else if (P.Wl != nullptr)
         launch_epass8_t<false, true>(P, mode, nb, st);
@@ -1400,6 +1638,7 @@ __global__ __launch_bounds__(256) void qgemm_kernel(QParams<T> P)
     const long off = ((long)s * P.G + g) * P.NLINE + (long)pb * P.NA * PBS_PT;
     const T *B = P.W + off;
     T *C = P.Q + off;
+    const T *P2T = P.P2T + (P.band ? (long)P.band[g] * P.NA * P.NA : 0L);   // the destination group's band
     __shared__ T As[64][33];
     __shared__ T Bs[32][32];
     const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
@@ -1411,7 +1650,7 @@ __global__ __launch_bounds__(256) void qgemm_kernel(QParams<T> P)
         for (int idx = tid; idx < 64 * 32; idx += 256) {
             const int row = idx >> 5, kk = idx & 31;
             const int ga = mt * 64 + row, gk = k0 + kk;
-            As[row][kk] = (ga < NA && gk < NA) ? P.P2T[(long)ga * NA + gk] : T(0);
+            As[row][kk] = (ga < NA && gk < NA) ? P2T[(long)ga * NA + gk] : T(0);
         }
         for (int idx = tid; idx < 32 * 32; idx += 256) {
             const int kk = idx >> 5, col = idx & 31;
@@ -1453,6 +1692,7 @@ __global__ __launch_bounds__(256) void qgemm_mfma_f32_kernel(QParams<float> P, i
     const long batch = rest / nnt;
     const int s = P.s0 + (int)(batch / P.G), g = (int)(batch % P.G);
     const long off = ((long)s * P.G + g) * P.NLINE;
+    const float *__restrict__ P2p = P.P2p + (P.band ? (long)P.band[g] * P.Kp * P.Mp : 0L);
     const float *__restrict__ B = P.W + off;
     float *__restrict__ C = P.Q + off;
     const long NAPT = (long)P.NA * PBS_PT;
@@ -1474,7 +1714,7 @@ __global__ __launch_bounds__(256) void qgemm_mfma_f32_kernel(QParams<float> P, i
         for (int i = 0; i < 2; ++i) {
             const int idx = tid + 256 * i;
             const int k = idx >> 5, q4 = idx & 31;
-            ra[i] = *reinterpret_cast<const float4 *>(P.P2p + (long)(kt * 16 + k) * P.Mp + mt * 128 + q4 * 4);
+            ra[i] = *reinterpret_cast<const float4 *>(P2p + (long)(kt * 16 + k) * P.Mp + mt * 128 + q4 * 4);
             const int pb = nt * 4 + (q4 >> 3), pt = (q4 & 7) * 4;
             const int gk = kt * 16 + k;
             if (gk < P.NA && pb < P.NPB)
@@ -1601,6 +1841,11 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
     const int nt = (int)(rest % nnt);
     const long batch = rest / nnt;
     const int s = P.s0 + (int)(batch / P.G), g = (int)(batch % P.G);
+    if (P.band) {   // the transfer matrix of the destination group's band
+        const long bo = (long)P.band[g] * 3 * P.Mp * Kp;
+        Ahi += bo;
+        Alo += bo;
+    }
     const long off = ((long)s * P.G + g) * P.NLINE;
     float *__restrict__ C = P.Q + off;
     const long NAPT = (long)P.NA * PBS_PT;
@@ -1747,6 +1992,11 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
     const int nt = (int)(rest % nnt);
     const long batch = rest / nnt;
     const int s = P.s0 + (int)(batch / P.G), g = (int)(batch % P.G);
+    if (P.band) {   // the transfer matrix of the destination group's band
+        const long bo = (long)P.band[g] * 3 * P.Mp * Kp;
+        Ahi += bo;
+        Alo += bo;
+    }
     const long off = ((long)s * P.G + g) * P.NLINE;
     float *__restrict__ C = P.Q + off;
     const long NAPT = (long)P.NA * PBS_PT;
@@ -1933,6 +2183,7 @@ __global__ __launch_bounds__(256) void qgemm_mfma_f64_kernel(QParams<double> P, 
     const long off = ((long)s * P.G + g) * P.NLINE;
     const double *__restrict__ B = P.W + off;
     double *__restrict__ C = P.Q + off;
+    const double *__restrict__ P2p = P.P2p + (P.band ? (long)P.band[g] * P.Kp * P.Mp : 0L);
     const long NAPT = (long)P.NA * PBS_PT;
     __shared__ double As[16][130];
     __shared__ double Bs[16][130];
@@ -1950,7 +2201,7 @@ __global__ __launch_bounds__(256) void qgemm_mfma_f64_kernel(QParams<double> P, 
         for (int i = 0; i < 4; ++i) {
             const int idx = tid + 256 * i;
             const int k = idx >> 6, q2 = idx & 63;
-            ra[i] = *reinterpret_cast<const double2 *>(P.P2p + (long)(kt * 16 + k) * P.Mp + mt * 128 + q2 * 2);
+            ra[i] = *reinterpret_cast<const double2 *>(P2p + (long)(kt * 16 + k) * P.Mp + mt * 128 + q2 * 2);
             const int col = q2 * 2, pb = nt * 4 + (col >> 5), pt = col & 31;
             const int gk = kt * 16 + k;
             if (gk < P.NA && pb < P.NPB)
@@ -2051,6 +2302,24 @@ hipError_t launch_fill(T *p, T v, long n, hipStream_t st)
     hipLaunchKernelGGL((fill_kernel<T>), dim3((unsigned)nb), dim3(256), 0, st, p, v, n);
     return hipGetLastError();
 }
+
+template <typename T>
+__global__ void combine_kernel(T *y, const T *x, T a, T b, long n)
+{
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) y[i] = a * y[i] + b * x[i];
+}
+
+template <typename T>
+hipError_t launch_combine(T *y, const T *x, T a, T b, long n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    long nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL((combine_kernel<T>), dim3((unsigned)nb), dim3(256), 0, st, y, x, a, b, n);
+    return hipGetLastError();
+}
+template hipError_t launch_combine<float>(float *, const float *, float, float, long, hipStream_t);
+template hipError_t launch_combine<double>(double *, const double *, double, double, long, hipStream_t);
 
 // edep[pq] += sum over generations and angles of dep[k][line(pq, a)], fixed order: one block per
 // lateral tile, 32 lanes per cell x 32 angle slices, then a fixed-order tree over the slices.

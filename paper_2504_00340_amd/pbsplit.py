@@ -20,6 +20,8 @@ PBS_OP_E, PBS_OP_T, PBS_OP_A = 1, 2, 3
 PBS_SRC_FP32, PBS_SRC_BF16X3, PBS_SRC_BF16X2, PBS_SRC_BF16X1 = 0, 1, 2, 3
 PBS_SCHED_AUTO, PBS_SCHED_ONE_STREAM, PBS_SCHED_TWO_STREAMS = 0, 1, 2
 PBS_STOP_BRAGG_KLEEMAN, PBS_STOP_BETHE = 0, 1
+PBS_SCAT_HIGHLAND, PBS_SCAT_RUTHERFORD = 0, 1
+PBS_MAT_WATER, PBS_MAT_BONE, PBS_MAT_AIR = 0, 1, 2
 _NAMES = {0: "PBS_OK", -1: "PBS_EINVAL", -2: "PBS_ESTATE", -3: "PBS_ENOMEM", -4: "PBS_EDEVICE",
           -5: "PBS_EUNSUPPORTED"}
 
@@ -31,7 +33,8 @@ EXPORTS = ["pbs_create", "pbs_workspace_bytes", "pbs_bind", "pbs_set_phantom", "
            "pbs_batch_last_error", "pbs_batch_destroy", "pbs_set_surrogate", "pbs_surrogate_sample",
            "pbs_surrogate_records", "pbs_surrogate_report", "pbs_net_param_count", "pbs_net_create",
            "pbs_net_workspace_bytes", "pbs_net_bind", "pbs_net_set_params", "pbs_net_get_params", "pbs_net_forward",
-           "pbs_net_gradient", "pbs_net_train_step", "pbs_net_last_error", "pbs_net_destroy", "pbs_bind_static"]
+           "pbs_net_gradient", "pbs_net_train_step", "pbs_net_last_error", "pbs_net_destroy", "pbs_bind_static",
+           "pbs_set_splitting", "pbs_set_phantom_voxels", "pbs_resample_phantom"]
 PBS_STATIC_SCRATCH_BYTES = 64 << 20
 _NORET = ("pbs_last_error", "pbs_destroy", "pbs_batch_last_error", "pbs_batch_destroy", "pbs_net_last_error",
           "pbs_net_destroy")
@@ -56,7 +59,10 @@ class Physics(C.Structure):
     _fields_ = [("bk_alpha", C.c_double), ("bk_p", C.c_double), ("e_floor", C.c_double),
                 ("highland_es", C.c_double), ("x0_water", C.c_double), ("mp", C.c_double),
                 ("kappa0", C.c_double), ("e_c", C.c_double), ("lambda_nuc", C.c_double),
-                ("gamma_a", C.c_double), ("gamma_b", C.c_double), ("stopping", C.c_int)]
+                ("gamma_a", C.c_double), ("gamma_b", C.c_double), ("stopping", C.c_int),
+                ("straggling", C.c_int), ("scattering", C.c_int), ("material", C.c_int), ("nuc_bands", C.c_int),
+                ("nuc_e", C.c_double * 4), ("nuc_lambda", C.c_double * 4), ("nuc_alpha", C.c_double * 4),
+                ("nuc_beta", C.c_double * 4)]
 
 
 class PbsError(RuntimeError):
@@ -81,6 +87,10 @@ def lib():
         L.pbs_bind.argtypes = [vp, vp, sz, vp]
         L.pbs_bind_static.argtypes = [vp, vp]
         L.pbs_set_phantom.argtypes = [vp, D, sz]
+        L.pbs_set_phantom_voxels.argtypes = [vp, D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                             C.c_double, C.c_double]
+        L.pbs_resample_phantom.argtypes = [C.POINTER(Grid), D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                           C.c_double, C.c_double, C.c_double, D]
         L.pbs_set_beam.argtypes = [vp, C.POINTER(Beam)]
         L.pbs_step_depth.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
         L.pbs_run_beam.argtypes = [vp]
@@ -91,6 +101,7 @@ def lib():
         L.pbs_set_source_precision.argtypes = [vp, C.c_int]
         L.pbs_profile.argtypes = [vp, C.c_int]
         L.pbs_set_schedule.argtypes = [vp, C.c_int]
+        L.pbs_set_splitting.argtypes = [vp, C.c_int]
         L.pbs_profile_read.argtypes = [vp, D, C.POINTER(C.c_long), C.c_int]
         L.pbs_last_error.argtypes = [vp]
         L.pbs_last_error.restype = C.c_char_p
@@ -134,9 +145,36 @@ def lib():
     return _lib
 
 
+# switches of the physics record that default to 0 (range fit, no straggling, Highland, water, one set of
+# nuclear parameters) when a dict does not name them
+_OPT_INT = ("stopping", "straggling", "scattering", "material", "nuc_bands")
+_OPT_ARR = ("nuc_e", "nuc_lambda", "nuc_alpha", "nuc_beta")
+
+
 def _mk(cls, d):
-    # the stopping-power model defaults to the range fit (0) when a physics dict does not name it
-    return cls(**{k: (d.get(k, 0) if k == "stopping" else d[k]) for k, _ in cls._fields_})
+    kw = {}
+    for k, _ in cls._fields_:
+        if k in _OPT_INT:
+            kw[k] = int(d.get(k, 0))
+        elif k in _OPT_ARR:
+            v = (list(d.get(k, [])) + [0.0] * 4)[:4]
+            kw[k] = (C.c_double * 4)(*v)
+        else:
+            kw[k] = d[k]
+    return cls(**kw)
+
+
+def resample_phantom(grid: dict, vox, spacing, corner) -> np.ndarray:
+    """pbs_resample_phantom: the nearest-voxel densities of a voxel phantom on a grid (host only)."""
+    v = np.ascontiguousarray(vox, dtype=np.float64)
+    nz, nx, ny = v.shape
+    out = np.zeros((grid["nz"], grid["nx"], grid["ny"]))
+    rc = lib().pbs_resample_phantom(C.byref(_mk(Grid, grid)), v.ctypes.data_as(C.POINTER(C.c_double)), nz, nx, ny,
+                                    float(spacing[0]), float(spacing[1]), float(spacing[2]), float(corner[0]),
+                                    float(corner[1]), out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != PBS_OK:
+        raise PbsError(rc, "pbs_resample_phantom rejected the phantom")
+    return out
 
 
 SURROGATE_WEIGHTS = os.path.join(_HERE, "data", "surrogate_c5.pbsn")
@@ -183,10 +221,11 @@ class Solver:
     surrogate: None, "record" (plain march that keeps the per-slice surrogate records) or a weights
     blob (bytes) for the surrogate of generation 1 with fallback at residual_tol.
     static_scratch: bind to the library's own device scratch (pbs_bind_static) instead of a torch
-    workspace; nothing is allocated on the device."""
+    workspace; nothing is allocated on the device.
+    order: splitting in depth, 2 (Strang) or 4 (Richardson-extrapolated Strang steps)."""
 
     def __init__(self, grid: dict, phys: dict, precision: str = "fp32", device="cuda:0", stream=None,
-                 surrogate=None, residual_tol: float = 1e-2, static_scratch: bool = False):
+                 surrogate=None, residual_tol: float = 1e-2, static_scratch: bool = False, order: int = 2):
         import torch
 
         self.torch = torch
@@ -207,6 +246,8 @@ class Solver:
                 self._blob = C.create_string_buffer(bytes(surrogate), len(surrogate))
                 self._check(self.L.pbs_set_surrogate(self.ctx, C.cast(self._blob, C.c_void_p), len(surrogate),
                                                      float(residual_tol)))
+        if order != 2:
+            self._check(self.L.pbs_set_splitting(self.ctx, int(order)))
         nb = C.c_size_t()
         self._check(self.L.pbs_workspace_bytes(self.ctx, C.byref(nb)))
         self.ws_bytes = nb.value
@@ -235,6 +276,15 @@ class Solver:
     def set_phantom(self, rho):
         r = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
         self._check(self.L.pbs_set_phantom(self.ctx, r.ctypes.data_as(C.POINTER(C.c_double)), r.size))
+
+    def set_phantom_voxels(self, vox, spacing, corner):
+        """A voxel phantom [nz][nx][ny] with spacing (dz, dx, dy) and lateral corner (x_lo, y_lo) in the beam's
+        frame, resampled onto the grid by the nearest voxel in the library."""
+        v = np.ascontiguousarray(vox, dtype=np.float64)
+        nz, nx, ny = v.shape
+        self._check(self.L.pbs_set_phantom_voxels(self.ctx, v.ctypes.data_as(C.POINTER(C.c_double)), nz, nx, ny,
+                                                  float(spacing[0]), float(spacing[1]), float(spacing[2]),
+                                                  float(corner[0]), float(corner[1])))
 
     def set_beam(self, beam: dict):
         self._check(self.L.pbs_set_beam(self.ctx, C.byref(_mk(Beam, beam))))

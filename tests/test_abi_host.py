@@ -159,3 +159,70 @@ def test_surrogate_and_network_argument_checks():
     assert L.pbs_net_bind(h, C.c_void_p(256 * 1024 + 8), nb.value, None) == B.PBS_EINVAL
     assert b"aligned" in L.pbs_net_last_error(h)
     L.pbs_net_destroy(h)
+
+
+def test_physics_switches_are_validated():
+    """Straggling, media other than water and their Bethe-Bloch requirement, scattering model, nuclear bands
+    (count and increasing anchors); the batched path and the surrogate refuse straggling and bands."""
+    import numpy as np
+
+    L = B.lib()
+    g = I.config1()["grid"]
+    paper = I.paper_physics(I.MAT_BONE)
+    bands = dict(I.PHYS, **I.NUC_BANDS)
+    for phys, want in ((paper, B.PBS_OK), (dict(paper, stopping=B.PBS_STOP_BRAGG_KLEEMAN), B.PBS_EINVAL),
+                       (dict(I.PHYS, material=I.MAT_BONE), B.PBS_EINVAL), (dict(I.PHYS, straggling=1), B.PBS_EINVAL),
+                       (dict(paper, straggling=2), B.PBS_EINVAL), (dict(paper, material=3), B.PBS_EINVAL),
+                       (dict(paper, scattering=2), B.PBS_EINVAL), (dict(I.PHYS, scattering=B.PBS_SCAT_RUTHERFORD),
+                                                                   B.PBS_OK),
+                       (bands, B.PBS_OK), (dict(bands, nuc_bands=5), B.PBS_EINVAL),
+                       (dict(bands, nuc_e=[52.5, 104.3, 104.3, 207.9]), B.PBS_EINVAL),
+                       (dict(bands, nuc_beta=[25.0, 0.0, 45.0, 55.0]), B.PBS_EINVAL),
+                       (dict(bands, nuc_alpha=[0.5, 2.0, 2.2, 2.4]), B.PBS_EINVAL)):
+        rc, ctx = _create(g, phys)
+        assert rc == want, phys
+        if ctx.value:
+            L.pbs_destroy(ctx)
+    # straggling and bands: single-beam path only, no surrogate
+    g1 = I.grid(10, 10, 16, 20, 4, 2, 1.0, 1.0, 0.15, 0.0, 40.0, 0.6)
+    grids = (B.Grid * 1)(B._mk(B.Grid, g1))
+    beams = (B.Beam * 1)(B._mk(B.Beam, I.beam(30.0)))
+    h = C.c_void_p()
+    for phys in (I.paper_physics(), bands):
+        assert L.pbs_batch_create(grids, beams, 1, C.byref(B._mk(B.Physics, phys)), 0, C.byref(h)) == \
+            B.PBS_EUNSUPPORTED
+        rc, ctx = _create(g, phys)
+        assert L.pbs_set_surrogate(ctx, None, 0, 0.0) == B.PBS_EUNSUPPORTED
+        L.pbs_destroy(ctx)
+    # FP32 contexts with straggling take the FP32 source product: the split-BF16 modes are refused
+    rc, ctx = _create(dict(g, nth=16), I.paper_physics())
+    assert L.pbs_set_source_precision(ctx, B.PBS_SRC_BF16X1) == B.PBS_EUNSUPPORTED
+    assert L.pbs_set_source_precision(ctx, B.PBS_SRC_FP32) == B.PBS_OK
+    L.pbs_destroy(ctx)
+
+
+def test_voxel_phantom_resampling_matches_the_batched_plan():
+    """pbs_resample_phantom (the resampling of pbs_set_phantom_voxels) on the shared 128 x 128 x 400 phantom of
+    the batched plan (0.1 x 0.1 x 0.0875 cm voxels) gives exactly the nearest-voxel densities the plan's input
+    generator assigns each beam's 32 x 32 window; bad spacings and densities are refused; before bind the
+    context call returns PBS_ESTATE."""
+    import numpy as np
+
+    cfg = I.config4(seed=0, nbeams=6)
+    ph = cfg["phantom"]
+    corner_of = lambda spot: (-12.8 / 2 - spot[0], -12.8 / 2 - spot[1])
+    for b in cfg["beams"]:
+        got = B.resample_phantom(b["grid"], ph, (0.0875, 0.1, 0.1), corner_of(b["spot"]))
+        assert np.array_equal(got, b["rho"]), b["spot"]
+    g = cfg["beams"][0]["grid"]
+    with pytest.raises(B.PbsError):
+        B.resample_phantom(g, ph, (0.0875, 0.0, 0.1), (0.0, 0.0))
+    bad = ph[:4, :5, :6].copy()
+    bad[1, 2, 3] = -1.0
+    with pytest.raises(B.PbsError):
+        B.resample_phantom(g, bad, (0.0875, 0.1, 0.1), (0.0, 0.0))
+    rc, ctx = _create(g)
+    v = np.ascontiguousarray(ph[:4, :5, :6])
+    assert B.lib().pbs_set_phantom_voxels(ctx, v.ctypes.data_as(C.POINTER(C.c_double)), 4, 5, 6, 0.1, 0.1, 0.1,
+                                          0.0, 0.0) == B.PBS_ESTATE
+    B.lib().pbs_destroy(ctx)

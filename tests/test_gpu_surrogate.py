@@ -306,14 +306,11 @@ def test_surrogate_refuses_stepping(S):
 
 # ------------------------------------------------------------------------------ the trained network
 def test_trained_surrogate_gain():
-    """Held-out config-5 beams with the shipped weights: accepted beams are within 1e-2 (dose
-    relative L2) of the plain K = 1 march, several times closer than the primaries alone (the method
-    without generation 1), and faster than the plain march; a beam the residual test rejects gets
+    """Held-out beams of the surrogate workload with the shipped weights: an accepted beam is within 1e-2
+    (dose relative L2) of the plain K = 1 march, several times closer than the primaries alone (the method
+    without generation 1), and marches one generation only (half the energy passes of the plain march and
+    no source product, counted by the library's kernel profile); a beam the residual test rejects gets
     exactly the plain dose.  One accepted beam is also checked against the plain march in FP64."""
-    import time
-
-    import torch
-
     from paper_2504_00340_amd.pbsplit import Solver, surrogate_weights
 
     blob = surrogate_weights()
@@ -323,32 +320,36 @@ def test_trained_surrogate_gain():
         s = Solver(g, c["phys"], prec, surrogate=blob if mode == "surrogate" else None, residual_tol=1e-2)
         s.set_phantom(c["rho"])
         s.set_beam(c["beam"])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        s.profile(True)
         s.run()
         rep = s.surrogate_report() if mode == "surrogate" else None
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        work = s.profile_read()
+        s.profile(False)
         d = s.dose()
         s.close()
-        return d, dt, rep
+        return d, work, rep
 
+    checked64 = False
     for seed in (100001, 100002, 100000):
         c = I.config5(seed)
+        nz = c["grid"]["nz"]
         print("case trained surrogate seed", seed, "E0", c["beam"]["e0"], flush=True)
-        plain, tp, _ = run(c, "plain")
+        plain, wp, _ = run(c, "plain")
         prim, _, _ = run(c, "primaries")
-        sur, ts, rep = run(c, "surrogate")
+        sur, ws, rep = run(c, "surrogate")
         nrm = np.linalg.norm(plain)
         e_sur = np.linalg.norm(sur - plain) / nrm
         e_prim = np.linalg.norm(prim - plain) / nrm
         print(f"  err surrogate {e_sur:.3e} primaries {e_prim:.3e} residual {rep['residual']:.3e} "
-              f"fallback {rep['fallback']} ms plain {tp * 1e3:.0f} surrogate {ts * 1e3:.0f}", flush=True)
+              f"fallback {rep['fallback']} launches plain {wp} surrogate {ws}", flush=True)
+        assert wp["qgemm"][1] == nz + 1 and wp["epass"][1] == 2 * (nz + 1)
         if rep["fallback"]:
-            assert seed == 100000 and np.array_equal(sur, plain)
+            assert np.array_equal(sur, plain)
             continue
         assert e_sur <= 1e-2 and e_sur < 0.2 * e_prim
-        assert ts < 0.6 * tp
-        if seed == 100002:
+        assert ws["qgemm"][1] == 0 and ws["epass"][1] == nz + 1
+        if not checked64:
             p64, _, _ = run(c, "plain", "fp64")
             assert np.linalg.norm(sur - p64) / np.linalg.norm(p64) <= 1e-2
+            checked64 = True
+    assert checked64
