@@ -62,9 +62,9 @@ def algorithmic(grid, tsz=4):
 # kernel names of each kind at the two march workloads (as rocprofv3 reports them)
 KIND_KERNEL = {
     "c3": {"tpass": "tpass_wide_kernel<96>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16g_kernel<1>",
-           "epass": "epass8_kernel<3, false, false>"},
+           "epass": "epass8_kernel<3, false, false, false>"},
     "c2": {"tpass": "tpass_affine_kernel<64>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16g_kernel<1>",
-           "epass": "epass8_kernel<3, false, false>"},
+           "epass": "epass8_kernel<3, false, false, false>"},
 }
 TRAFFIC_FILE = {"c3": "traffic_c3_hetero_fp32.md", "c2": "traffic_c2_water_fp32.md"}
 

@@ -220,3 +220,25 @@ def test_bethe_stopping_march_matches_oracle(O, prec, tol):
     assert _rel(s.dose(), dref) < tol
     assert _rel(s.state(), fref) < 10 * tol
     s.close()
+
+
+def test_voxel_phantom_entry_equals_resampled_densities():
+    """pbs_set_phantom_voxels (nearest-voxel resampling in the library) gives bitwise the march of
+    pbs_set_phantom with the densities of the batched plan's own sampling of its shared phantom."""
+    from paper_2504_00340_amd.pbsplit import Solver
+
+    cfg = I.config4(seed=0, nbeams=2)
+    b = cfg["beams"][1]
+    g = dict(b["grid"], nz=40, ng=24, dz=b["grid"]["dz"])
+    out = []
+    for mode in ("voxels", "direct"):
+        s = Solver(g, cfg["phys"], precision="fp32")
+        if mode == "voxels":
+            s.set_phantom_voxels(cfg["phantom"], (0.0875, 0.1, 0.1), (-6.4 - b["spot"][0], -6.4 - b["spot"][1]))
+        else:
+            s.set_phantom(b["rho"][:40])
+        s.set_beam(b["beam"])
+        s.run()
+        out.append(s.dose())
+        s.close()
+    assert np.array_equal(out[0], out[1])
