@@ -614,12 +614,15 @@ template <typename T>
 __device__ __forceinline__ T superbee_slope(T dup, T dface)
 {
     const T au = fabs(dup), af = fabs(dface);
-    T v;
-    if constexpr (sizeof(T) == 4)
-        v = __builtin_amdgcn_fmed3f(au, af, 2.f * fminf(au, af));
-    else
-        v = fmin(fmax(au, af), T(2) * fmin(au, af));
-    return signbit(dup) == signbit(dface) ? copysign(v, dface) : T(0);
+    if constexpr (sizeof(T) == 4) {
+        const float v = __builtin_amdgcn_fmed3f(au, af, 2.f * fminf(au, af));
+        // v <= 2|dup|, so clamping copysign(v, dface) between 0 and 2 dup keeps it when the two differences
+        // agree in sign and gives 0 when they do not (no compare, no condition register)
+        return __builtin_amdgcn_fmed3f(copysignf(v, dface), 0.f, 2.f * dup);
+    } else {
+        const T v = fmin(fmax(au, af), T(2) * fmin(au, af));
+        return signbit(dup) == signbit(dface) ? copysign(v, dface) : T(0);
+    }
 }
 
 // The transport sweep reads and writes every plane once: non-temporal loads and stores (both are needed:
@@ -757,6 +760,30 @@ __device__ __forceinline__ float dpp_z(float x)
 // DPP controls (GFX9): row_shr:n = 0x110 + n, wave_shl:1 = 0x130, wave_shr:1 = 0x138,
 // row_bcast:15 = 0x142, row_bcast:31 = 0x143.  Lanes without a source receive 0 (the ghost value).
 
+// One step of a row scan, y += c * y[source lane of the DPP pattern], as a single v_fmac_f32_dpp (rows
+// outside the row mask keep y; lanes without a source read 0 and keep y).  The compiler does not fold a
+// DPP move into a multiply-accumulate (a move plus an FMA per step), so the step is written out; the
+// leading s_nop gives the two wait states a DPP read needs after a VALU write of its source.  Only used
+// where the whole wave is active.
+#define PBS_FMAC_DPP(y, c, ctrl, rmask) \
+    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 " ctrl " row_mask:" rmask " bank_mask:0xf bound_ctrl:1" \
+                 : "+v"(y) : "v"(c))
+
+// y_q = b_q + c y_{q-1} within each 16-lane row: Kogge-Stone over distances 1, 2, 4, 8 (multipliers c^d)
+__device__ __forceinline__ void scan_rows16(float &y, float c1, float c2, float c4, float c8)
+{
+    PBS_FMAC_DPP(y, c1, "row_shr:1", "0xf");
+    PBS_FMAC_DPP(y, c2, "row_shr:2", "0xf");
+    PBS_FMAC_DPP(y, c4, "row_shr:4", "0xf");
+    PBS_FMAC_DPP(y, c8, "row_shr:8", "0xf");
+}
+// ... then lane 15 of rows 0 and 2 into rows 1 and 3 (m16 = c^((lane & 15) + 1)) ...
+__device__ __forceinline__ void scan_join32(float &y, float m16) { PBS_FMAC_DPP(y, m16, "row_bcast:15", "0xa"); }
+// ... then lane 31 into rows 2 and 3 (m32 = c^((lane & 31) + 1))
+__device__ __forceinline__ void scan_join64(float &y, float m32) { PBS_FMAC_DPP(y, m32, "row_bcast:31", "0xc"); }
+// two wait states after the last scan step, for any DPP read of y that the compiler places next
+__device__ __forceinline__ void scan_done() { asm volatile("s_nop 1"); }
+
 __device__ __forceinline__ void tpass_dpp_body(const TParams<float> &P, long plane)
 {
     if (plane >= P.nplanes) return;   // uniform per wave
@@ -810,12 +837,10 @@ __device__ __forceinline__ void tpass_dpp_body(const TParams<float> &P, long pla
             const float R = p0 - ax * ((p0 - pm1) + (dxp - dxm)) - ay * ((p0 - left) + (dyp - dym));
             float y = (R + ax * ym1) * idiag;
             // y_q = b_q + c y_{q-1} along the row: Kogge-Stone within rows of 16, then row broadcasts
-            y += c1 * dpp_f<0x111, 0xF>(y);
-            y += c2 * dpp_f<0x112, 0xF>(y);
-            y += c4 * dpp_f<0x114, 0xF>(y);
-            y += c8 * dpp_f<0x118, 0xF>(y);
-            y += m16 * dpp_f<0x142, 0xA>(y);
-            y += m32 * dpp_f<0x143, 0xC>(y);
+            scan_rows16(y, c1, c2, c4, c8);
+            scan_join32(y, m16);
+            scan_join64(y, m32);
+            scan_done();
             if (valid) *addr(r0 + i) = y;
             pm1 = p0;
             dxm = dxp;
@@ -901,12 +926,10 @@ __device__ __forceinline__ void tpass_affine_body(const TParams<float> &P, long 
             const float dxp = superbee_slope(p0 - pm1, p1 - p0);
             const float R = p0 - ax * ((p0 - pm1) + (dxp - dxm)) - ay * ((p0 - left) + (dyp - dym));
             float y = (R + ax * ym1) * idiag;
-            y += c1 * dpp_z<0x111>(y);
-            y += c2 * dpp_z<0x112>(y);
-            y += c4 * dpp_z<0x114>(y);
-            y += c8 * dpp_z<0x118>(y);
-            y += m16 * dpp_z<0x142>(y);
-            y += m32 * dpp_z<0x143>(y);
+            scan_rows16(y, c1, c2, c4, c8);
+            scan_join32(y, m16);
+            scan_join64(y, m32);
+            scan_done();
             if (FULL || valid) TP_ST(y, st);
             st += step;
             pm1 = p0;
@@ -996,11 +1019,9 @@ __device__ __forceinline__ void tpass_pair_body(const TParams<float> &P, long pa
             const float dxp = superbee_slope(p0 - pm1, p1 - p0);
             const float R = p0 - ax * ((p0 - pm1) + (dxp - dxm)) - ay * ((p0 - left) + (dyp - dym));
             float y = (R + ax * ym1) * idiag;
-            y += c1 * dpp_z<0x111>(y);
-            y += c2 * dpp_z<0x112>(y);
-            y += c4 * dpp_z<0x114>(y);
-            y += c8 * dpp_z<0x118>(y);
-            y += m16 * dpp_z<0x142>(y);
+            scan_rows16(y, c1, c2, c4, c8);
+            scan_join32(y, m16);
+            scan_done();
             if (live) TP_ST(y, st);
             st += step;
             pm1 = p0;
@@ -1117,12 +1138,10 @@ __device__ __forceinline__ void tpass_wide_body(const TParams<float> &P, long pl
                 const float dxp = superbee_slope(p0 - pm1[s], p1 - p0);
                 const float R = p0 - ax * ((p0 - pm1[s]) + (dxp - dxm[s])) - ay * ((p0 - left[s]) + (dyp[s] - dym));
                 float y = (R + ax * ym1[s]) * idiag;
-                y += c1 * dpp_z<0x111>(y);
-                y += c2 * dpp_z<0x112>(y);
-                y += c4 * dpp_z<0x114>(y);
-                y += c8 * dpp_z<0x118>(y);
-                y += m16 * dpp_z<0x142>(y);
-                y += m32 * dpp_z<0x143>(y);
+                scan_rows16(y, c1, c2, c4, c8);
+                scan_join32(y, m16);
+                scan_join64(y, m32);
+                scan_done();
                 if (s > 0) y += m64 * carry;
                 carry = lane_of(y, 63);
                 if (valid[s]) TP_ST(y, st[s]);
@@ -1145,6 +1164,192 @@ __global__ __launch_bounds__(256) void tpass_wide_kernel(TParams<float> P)
     tpass_wide_body<NY>(P, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
+constexpr int TPASS_W2_PF = 4;   // rows loaded ahead per operation in the two-plane ny = 96 sweep
+
+// ny = 96 with two planes per wave (A = plane 2w, B = plane 2w + 1; the plane count is even).  A row of
+// both planes is three full 64-lane operations: A columns 0-63, B columns 0-63, then A columns 64-95 in
+// lanes 0-31 beside B columns 64-95 in lanes 32-63.  The one-plane sweep of this width spends two
+// operations per row with a quarter of its lanes idle and is instruction-bound; here no lane idles.
+// The third operation carries each half's own angle coefficients; its row scan stops at the 16-lane
+// broadcast (it never crosses lane 31/32) and takes the carry y_63 of its plane's first operation.
+// Neighbours across the seams (A 63|64, B 63|64) move by readlane and masked products; column 96 is the
+// ghost.
+// Addresses are 32-bit byte offsets in a buffer resource based at plane A's slab (plane B lies in the
+// same slab or the next); each lane steps by its plane's signed row stride.
+__device__ __forceinline__ void tpass_wide2_body(const TParams<float> &P, int pair)
+{
+    constexpr int NY = 96;
+    if (2L * pair >= P.nplanes) return;   // uniform per wave
+    const int lane = threadIdx.x & 63;
+    const int ql = lane & 31;
+    const bool hi = lane >= 32;
+    const long NAPT = (long)P.NA * PBS_PT;
+    const int nx = P.nx;
+    const long plA = 2L * pair, plB = plA + 1;
+    const int aA = (int)(plA % P.NA), aB = (int)(plB % P.NA);
+    const long slabA = plA / P.NA, slabB = plB / P.NA;
+    const float cxA = P.theta[aA / P.m], cyA = P.theta[aA % P.m];
+    const float cxB = P.theta[aB / P.m], cyB = P.theta[aB % P.m];
+    const bool mxA = cxA < 0.f, myA = cyA < 0.f, mxB = cxB < 0.f, myB = cyB < 0.f;
+    const float axA = fabsf(cxA) * P.h_half_over_dx, ayA = fabsf(cyA) * P.h_half_over_dy;
+    const float axB = fabsf(cxB) * P.h_half_over_dx, ayB = fabsf(cyB) * P.h_half_over_dy;
+    const float idA = 1.f / (1.f + axA + ayA), idB = 1.f / (1.f + axB + ayB);
+    const float cqA = ayA * idA, cqB = ayB * idB;
+    // byte offsets from plane A's slab: plane origin + column (mirrored) + first row (mirrored)
+    const long RSB = 3 * NAPT * 4;   // bytes from row p to row p + 1
+    const long originA = (long)aA * PBS_PT * 4;
+    const long originB = ((slabB - slabA) * P.NLINE + (long)aB * PBS_PT) * 4;
+    auto col = [&](int q, bool my) -> long {
+        const int qc = my ? NY - 1 - q : q;
+        return ((long)(qc >> 5) * NAPT + (qc & 31)) * 4;
+    };
+    const long row0A = mxA ? (long)(nx - 1) * RSB : 0, row0B = mxB ? (long)(nx - 1) * RSB : 0;
+    const int stepA = (int)(mxA ? -RSB : RSB), stepB = (int)(mxB ? -RSB : RSB);
+    unsigned ld[3], st[3];
+    int step[3];
+    ld[0] = (unsigned)(originA + col(lane, myA) + row0A);
+    ld[1] = (unsigned)(originB + col(lane, myB) + row0B);
+    ld[2] = (unsigned)(hi ? originB + col(64 + ql, myB) + row0B : originA + col(64 + ql, myA) + row0A);
+    step[0] = stepA;
+    step[1] = stepB;
+    step[2] = hi ? stepB : stepA;
+#pragma unroll
+    for (int o = 0; o < 3; ++o) st[o] = ld[o];
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(P.psi + slabA * P.NLINE), (short)0, (int)(2 * P.NLINE * 4 < 0x7fffffffL ? 2 * P.NLINE * 4 : 0x7fffffffL),
+        0x00020000);
+    // scan multipliers per operation: cq^(2^i) for the row shifts, cq^((lane & 15) + 1) and
+    // cq^((lane & 31) + 1) for the broadcasts; in the third operation each half has its own cq, and
+    // cq^(ql + 1) takes the carry of its plane's first operation (zero in the other half)
+    auto powers = [](float cq, int e) {
+        float m = 1.f, pw = cq;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            if ((e >> i) & 1) m *= pw;
+            pw *= pw;
+        }
+        return m;
+    };
+    float c1[3], c2[3], c4[3], c8[3], m16[3], ax[3], ay[3], idg[3];
+    const float cq3 = hi ? cqB : cqA;
+    const float cqs[3] = {cqA, cqB, cq3};
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        c1[o] = cqs[o];
+        c2[o] = c1[o] * c1[o];
+        c4[o] = c2[o] * c2[o];
+        c8[o] = c4[o] * c4[o];
+        m16[o] = powers(cqs[o], (lane & 15) + 1);
+    }
+    const float m32A = powers(cqA, (lane & 31) + 1), m32B = powers(cqB, (lane & 31) + 1);
+    const float mcA = hi ? 0.f : powers(cqA, ql + 1), mcB = hi ? powers(cqB, ql + 1) : 0.f;
+    ax[0] = axA; ay[0] = ayA; idg[0] = idA;
+    ax[1] = axB; ay[1] = ayB; idg[1] = idB;
+    ax[2] = hi ? axB : axA; ay[2] = hi ? ayB : ayA; idg[2] = hi ? idB : idA;
+    // lane masks for the seam corrections, kept opaque (a select would run the DPP moves next to it under
+    // a partial exec mask, where the switched-off lanes would stop serving as move sources)
+    float e63 = lane == 63 ? 1.f : 0.f, e0 = lane == 0 ? 1.f : 0.f, e32 = lane == 32 ? 1.f : 0.f;
+    float keep_l = ql == 0 ? 0.f : 1.f, keep_r = ql == 31 ? 0.f : 1.f;
+    asm volatile("" : "+v"(e63), "+v"(e0), "+v"(e32), "+v"(keep_l), "+v"(keep_r));
+    auto lane_of = [](float v, int l) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    };
+    // the left neighbour in the third operation: the lane below, but plane A's and plane B's column 63
+    // (scalars sa, sb) in lanes 0 and 32 -- exact, as every other term is a product with 0
+    auto left3 = [&](float v, float sa, float sb) { return keep_l * dpp_z<0x138>(v) + e0 * sa + e32 * sb; };
+    constexpr int PF = TPASS_W2_PF;
+    float rb[3][2 * PF];
+#pragma unroll
+    for (int i = 0; i < PF; ++i)
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            rb[o][i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, ld[o], 0, 2));
+            ld[o] += step[o];
+        }
+    float dxb[3], dxm[3], ym1[3];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        dxb[o] = rb[o][0];   // p0 - p_{-1} with the ghost row upstream
+        dxm[o] = ym1[o] = 0.f;
+    }
+    for (int r0 = 0; r0 < nx; r0 += PF) {
+        const bool more = r0 + PF < nx;
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < PF; ++i)
+#pragma unroll
+                for (int o = 0; o < 3; ++o) {
+                    rb[o][PF + i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, ld[o], 0, 2));
+                    ld[o] += step[o];
+                }
+        } else {
+#pragma unroll
+            for (int i = 0; i < PF; ++i)
+#pragma unroll
+                for (int o = 0; o < 3; ++o) rb[o][PF + i] = 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            float p0[3], dy[3], ayv[3];
+#pragma unroll
+            for (int o = 0; o < 3; ++o) p0[o] = rb[o][i];
+            // lateral differences p0 - left and right - p0, seams patched
+            const float rA = lane_of(p0[2], 0), rB = lane_of(p0[2], 32);
+            const float lA = lane_of(p0[0], 63), lB = lane_of(p0[1], 63);
+            float bf[3];
+            ayv[0] = p0[0] - dpp_z<0x138>(p0[0]);
+            bf[0] = dpp_z<0x130>(p0[0]) - p0[0] + e63 * rA;
+            ayv[1] = p0[1] - dpp_z<0x138>(p0[1]);
+            bf[1] = dpp_z<0x130>(p0[1]) - p0[1] + e63 * rB;
+            ayv[2] = p0[2] - left3(p0[2], lA, lB);
+            bf[2] = keep_r * dpp_z<0x130>(p0[2]) - p0[2];
+#pragma unroll
+            for (int o = 0; o < 3; ++o) dy[o] = superbee_slope(ayv[o], bf[o]);
+            // dyp - dym, the seams taking the upstream plane's lane-63 slope
+            float dd[3];
+            dd[0] = dy[0] - dpp_z<0x138>(dy[0]);
+            dd[1] = dy[1] - dpp_z<0x138>(dy[1]);
+            dd[2] = dy[2] - left3(dy[2], lane_of(dy[0], 63), lane_of(dy[1], 63));
+            float y[3];
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                const float dxf = rb[o][i + 1] - p0[o];
+                const float dxp = superbee_slope(dxb[o], dxf);
+                const float R = p0[o] - ax[o] * (dxb[o] + (dxp - dxm[o])) - ay[o] * (ayv[o] + dd[o]);
+                y[o] = (R + ax[o] * ym1[o]) * idg[o];
+                dxb[o] = dxf;
+                dxm[o] = dxp;
+            }
+            scan_rows16(y[0], c1[0], c2[0], c4[0], c8[0]);
+            scan_join32(y[0], m16[0]);
+            scan_join64(y[0], m32A);
+            scan_rows16(y[1], c1[1], c2[1], c4[1], c8[1]);
+            scan_join32(y[1], m16[1]);
+            scan_join64(y[1], m32B);
+            scan_rows16(y[2], c1[2], c2[2], c4[2], c8[2]);
+            scan_join32(y[2], m16[2]);
+            scan_done();
+            y[2] += mcA * lane_of(y[0], 63);
+            y[2] += mcB * lane_of(y[1], 63);
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, y[o]), rs, st[o], 0, 2);
+                st[o] += step[o];
+                ym1[o] = y[o];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PF; ++i)
+#pragma unroll
+            for (int o = 0; o < 3; ++o) rb[o][i] = rb[o][PF + i];
+    }
+}
+
+__global__ __launch_bounds__(256) void tpass_wide2_kernel(TParams<float> P)
+{
+    tpass_wide2_body(P, __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6))));
+}
+
 template <typename T>
 hipError_t launch_tpass(const TParams<T> &P, hipStream_t st)
 {
@@ -1157,6 +1362,12 @@ hipError_t launch_tpass(const TParams<T> &P, hipStream_t st)
         if (P.nx % TPASS_PF == 0 && P.ny == 32) {
             const long pairs = (P.nplanes + 1) / 2;
             hipLaunchKernelGGL(tpass_pair_kernel, dim3((unsigned)((pairs + 3) / 4)), dim3(256), 0, st, P);
+            return hipGetLastError();
+        }
+        if (P.nx % TPASS_W2_PF == 0 && P.ny == 96 && P.nplanes % 2 == 0 && 2 * P.NLINE * 4 < 0x7fffffffL &&
+            P.nplanes / 2 < 0x7fffffffL) {
+            const long pairs = P.nplanes / 2;
+            hipLaunchKernelGGL(tpass_wide2_kernel, dim3((unsigned)((pairs + 3) / 4)), dim3(256), 0, st, P);
             return hipGetLastError();
         }
         if (P.nx % TPASS_PF == 0 && P.ny == 96) {

@@ -37,9 +37,12 @@ RAGGED = [dict(nx=6, ny=5, nth=6, ng=7, ngen=3, seed=1),
           # row-affine transport sweeps (ny = 64 / 32, nx a multiple of 8)
           dict(nx=16, ny=64, nth=6, ng=3, ngen=2, seed=6),
           dict(nx=8, ny=32, nth=16, ng=3, ngen=2, seed=7),
-          # two-segment row-affine sweeps (ny = 96 / 128, nx a multiple of 8)
+          # two-segment row-affine sweeps (ny = 96 / 128, nx a multiple of 8); at ny = 96 two planes per wave,
+          # with odd angle counts (pairs straddle slabs and mirrorings) and nx a multiple of 4 only
           dict(nx=8, ny=96, nth=6, ng=3, ngen=2, seed=8),
-          dict(nx=16, ny=128, nth=4, ng=2, ngen=2, seed=9)]
+          dict(nx=16, ny=128, nth=4, ng=2, ngen=2, seed=9),
+          dict(nx=12, ny=96, nth=16, ng=2, ngen=1, seed=10),
+          dict(nx=4, ny=96, nth=4, ng=3, ngen=2, seed=11)]
 
 
 @pytest.fixture(scope="module")
