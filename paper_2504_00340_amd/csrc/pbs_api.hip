@@ -121,7 +121,9 @@ void transfer_table_bf16(const std::vector<double> &P2T, int NA, int Mp, int Kpb
 }
 
 // nth = 32: the 31-point sine transform split by mode parity, [(mat*4 + s)*64 + lane] =
-// A_mat[lane % 16][4 s + lane / 16] for mat = Sodd, Seven, Sodd^T, Seven^T.
+// A_mat[perm(lane % 16)][4 s + lane / 16] for mat = Sodd, Seven and A_mat[4 s + lane / 16][perm(lane % 16)]
+// for mat = Sodd^T, Seven^T, perm(4 g + q) = 4 q + g (the row order that keeps the angular pass's LDS
+// stores free of bank conflicts).
 // nth = 16: the dense 15-point transform zero-padded to 16 x 16, [s*64 + lane] = S[lane % 16][4 s + lane / 16].
 void apass_mfma_table(int nth, float *t)
 {
@@ -131,7 +133,7 @@ void apass_mfma_table(int nth, float *t)
         auto seven = [](int r, int i) { return (r < 15 && i < 15) ? std::sin(M_PI * 2 * (r + 1) * (i + 1) / 32.0) : 0.0; };
         for (int s = 0; s < 4; ++s)
             for (int lane = 0; lane < 64; ++lane) {
-                const int row = lane % 16, k = 4 * s + lane / 16;
+                const int row = 4 * (lane % 4) + (lane % 16) / 4, k = 4 * s + lane / 16;
                 t[(0 * 4 + s) * 64 + lane] = (float)sodd(row, k);
                 t[(1 * 4 + s) * 64 + lane] = (float)seven(row, k);
                 t[(2 * 4 + s) * 64 + lane] = (float)sodd(k, row);

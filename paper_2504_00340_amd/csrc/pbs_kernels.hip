@@ -1524,7 +1524,15 @@ static hipError_t launch_apass_n(const AParams<T> &P, long nstack, hipStream_t s
 // v_mfma_f32_16x16x4_f32 whose 16 columns are 16 lateral cells of one angular line.  The block's
 // 31 x 31 x 16 values stay in LDS between the transforms; each wave owns whole lines, so the
 // transforms work in place without block-wide barriers.
-//   Ktab[(mat*4 + s)*64 + lane] = A_mat[lane % 16][4 s + lane / 16] for mat = Sodd, Seven, Sodd^T, Seven^T.
+// LDS banks: an MFMA result holds rows 4 (lane / 16) + q in lane groups of 16, so writing row r of the
+// result with r = 4 (lane / 16) + q puts the four lane groups of one store 4 rows apart, a multiple of
+// the bank count at every row stride here (4-way conflicts).  The operand rows are therefore permuted,
+// result row 4 g + q holding output index 4 q + g, so one store's lane groups are one row apart; and
+// the modes are kept de-interleaved (odd block in rows 0-15, even block in rows 16-30, in both angular
+// directions), so consecutive odd (even) modes are adjacent.  Every LDS access then reaches 32
+// distinct banks per half wave.
+//   Ktab[(mat*4 + s)*64 + lane] = A_mat[perm(lane % 16)][4 s + lane / 16] for mat = Sodd, Seven and
+//   A_mat[4 s + lane / 16][perm(lane % 16)] for mat = Sodd^T, Seven^T, perm(4 g + q) = 4 q + g.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c)
@@ -1557,17 +1565,18 @@ __device__ __forceinline__ void apass_mfma32_body(const AParams<float> &P, const
         Bo[s] = Ktab[(2 * 4 + s) * 64 + lane];
         Be[s] = Ktab[(3 * 4 + s) * 64 + lane];
     }
+    // result row 4 r4 + q holds mode (or node) block index 4 q + r4
     float lamO[4], lamE[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int r = 4 * r4 + q;
+        const int r = 4 * q + r4;
         lamO[q] = P.lam[2 * r];
         lamE[q] = r < 15 ? P.lam[2 * r + 1] : 0.f;
     }
     const float al = 0.25f * P.h * P.sig[g] * P.rho[(long)pb * PBS_PT + c0 + cc];
     __syncthreads();
 
-    // forward over the first angular index; line = column j
+    // forward over the first angular index; line = column j.  Odd mode r -> row r, even mode r -> row 16 + r.
     for (int j = wid; j < m; j += APASS32_NT / 64) {
         floatx4 yo = {0.f, 0.f, 0.f, 0.f}, ye = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -1580,13 +1589,14 @@ __device__ __forceinline__ void apass_mfma32_body(const AParams<float> &P, const
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int r = 4 * r4 + q;
-            L[((2 * r) * m + j) * PC + cc] = yo[q];
-            if (r < 15) L[((2 * r + 1) * m + j) * PC + cc] = ye[q];
+            const int r = 4 * q + r4;
+            L[(r * m + j) * PC + cc] = yo[q];
+            if (r < 15) L[((16 + r) * m + j) * PC + cc] = ye[q];
         }
     }
     __syncthreads();
-    // over the second index: forward, CN factor, inverse; line = mode k of the first index
+    // over the second index: forward, CN factor, inverse; line = row k (odd mode k, or even mode k - 16, of
+    // the first index)
     for (int k = wid; k < m; k += APASS32_NT / 64) {
         floatx4 zo = {0.f, 0.f, 0.f, 0.f}, ze = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -1597,10 +1607,10 @@ __device__ __forceinline__ void apass_mfma32_body(const AParams<float> &P, const
             zo = mfma16(Ao[s], jp < 15 ? ya + yb : ya, zo);
             ze = mfma16(Ae[s], ya - yb, ze);
         }
-        const float lk = P.lam[k];
+        const float lk = P.lam[k < 16 ? 2 * k : 2 * (k - 16) + 1];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int r = 4 * r4 + q;
+            const int r = 4 * q + r4;
             const float to = al * (lk + lamO[q]);
             zo[q] = zo[q] * (1.f + to) * __builtin_amdgcn_rcpf(1.f - to);
             const float te = al * (lk + lamE[q]);
@@ -1609,9 +1619,9 @@ __device__ __forceinline__ void apass_mfma32_body(const AParams<float> &P, const
         // modes back through LDS into the operand layout (same wave, same line: in-order LDS)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int r = 4 * r4 + q;
-            L[(k * m + 2 * r) * PC + cc] = zo[q];
-            if (r < 15) L[(k * m + 2 * r + 1) * PC + cc] = ze[q];
+            const int r = 4 * q + r4;
+            L[(k * m + r) * PC + cc] = zo[q];
+            if (r < 15) L[(k * m + 16 + r) * PC + cc] = ze[q];
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1619,8 +1629,8 @@ __device__ __forceinline__ void apass_mfma32_body(const AParams<float> &P, const
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int r = 4 * s + r4;
-            const float bo = L[(k * m + 2 * r) * PC + cc];
-            const float be = r < 15 ? L[(k * m + 2 * r + 1) * PC + cc] : 0.f;
+            const float bo = L[(k * m + r) * PC + cc];
+            const float be = r < 15 ? L[(k * m + 16 + r) * PC + cc] : 0.f;
             u = mfma16(Bo[s], bo, u);
             v = mfma16(Be[s], be, v);
         }
@@ -1628,7 +1638,7 @@ __device__ __forceinline__ void apass_mfma32_body(const AParams<float> &P, const
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int jp = 4 * r4 + q;
+            const int jp = 4 * q + r4;
             if (jp < 15) {
                 L[(k * m + jp) * PC + cc] = u[q] + v[q];
                 L[(k * m + 30 - jp) * PC + cc] = u[q] - v[q];
@@ -1645,8 +1655,8 @@ __device__ __forceinline__ void apass_mfma32_body(const AParams<float> &P, const
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int r = 4 * s + r4;
-            const float bo = L[((2 * r) * m + j) * PC + cc];
-            const float be = r < 15 ? L[((2 * r + 1) * m + j) * PC + cc] : 0.f;
+            const float bo = L[(r * m + j) * PC + cc];
+            const float be = r < 15 ? L[((16 + r) * m + j) * PC + cc] : 0.f;
             u = mfma16(Bo[s], bo, u);
             v = mfma16(Be[s], be, v);
         }
@@ -1654,7 +1664,7 @@ __device__ __forceinline__ void apass_mfma32_body(const AParams<float> &P, const
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int ip = 4 * r4 + q;
+            const int ip = 4 * q + r4;
             if (ip < 15) {
                 L[(ip * m + j) * PC + cc] = (u[q] + v[q]) * sc;
                 L[((30 - ip) * m + j) * PC + cc] = (u[q] - v[q]) * sc;

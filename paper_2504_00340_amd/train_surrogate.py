@@ -1,6 +1,7 @@
 """Train the surrogate of generation 1 on the solver's own output, on one GPU.
 
   python -m paper_2504_00340_amd.train_surrogate --out <blob>      (240 beams, 30000 Adam steps)
+  python -m paper_2504_00340_amd.train_surrogate --evaluate <blob> --eval-seeds 100
 
 1. Data: for every training seed, a K = 1 beam of the surrogate workload (64 x 64 cells on
    +-4 cm, 16 x 16 angular nodes on +-0.15 rad, 96 groups on [0, E0 + 10] MeV, 300 depth steps over
@@ -151,6 +152,31 @@ def evaluate(blob: bytes, seeds, nz: int = 300, tol: float = 1e-2, log=print):
     return rows
 
 
+def summarize(rows):
+    """Accept rate, error distribution of the accepted beams and of the network alone, throughput."""
+    acc = [r for r in rows if not r["fallback"]]
+    en = np.array([r["err_net"] for r in rows])
+    ea = np.array([r["err_surrogate"] for r in acc]) if acc else np.zeros(0)
+    out = dict(accepted=len(acc), accept_rate=len(acc) / len(rows),
+               mean_err_net=float(en.mean()), max_err_net=float(en.max()),
+               p90_err_net=float(np.percentile(en, 90)),
+               mean_err_surrogate=float(np.mean([r["err_surrogate"] for r in rows])),
+               max_err_surrogate=float(np.max([r["err_surrogate"] for r in rows])),
+               mean_err_accepted=float(ea.mean()) if acc else None, max_err_accepted=float(ea.max()) if acc else None,
+               mean_err_primaries=float(np.mean([r["err_primaries"] for r in rows])),
+               fallback_energies=[r["e0"] for r in rows if r["fallback"]],
+               beams_per_s_plain=len(rows) / (np.sum([r["ms_plain"] for r in rows]) * 1e-3),
+               beams_per_s_surrogate=len(rows) / (np.sum([r["ms_surrogate"] for r in rows]) * 1e-3),
+               speedup=float(np.sum([r["ms_plain"] for r in rows]) / np.sum([r["ms_surrogate"] for r in rows])))
+    for lo, hi in ((70, 130), (130, 190), (190, 230)):
+        sel = [r for r in rows if lo <= r["e0"] < hi]
+        if sel:
+            out[f"band_{lo}_{hi}"] = dict(n=len(sel), accepted=sum(1 for r in sel if not r["fallback"]),
+                                          mean_err_net=float(np.mean([r["err_net"] for r in sel])),
+                                          max_err_net=float(np.max([r["err_net"] for r in sel])))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--train-seeds", type=int, default=240)
@@ -160,9 +186,23 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--out", required=True, help="weights blob to write")
+    ap.add_argument("--out", default=None, help="weights blob to write")
+    ap.add_argument("--evaluate", default=None, metavar="BLOB",
+                    help="skip data and training: evaluate this weights blob on the held-out seeds")
     ap.add_argument("--report", default=None, help="JSON summary to write")
     a = ap.parse_args(argv)
+    if a.evaluate:
+        with open(a.evaluate, "rb") as f:
+            blob = f.read()
+        rows = evaluate(blob, range(EVAL_SEED0, EVAL_SEED0 + a.eval_seeds), a.nz)
+        summary = dict(weights=a.evaluate, eval_seeds=a.eval_seeds, **summarize(rows), eval=rows)
+        print(json.dumps({k: v for k, v in summary.items() if k != "eval"}), flush=True)
+        if a.report:
+            with open(a.report, "w") as f:
+                json.dump(summary, f, indent=1)
+        return
+    if not a.out:
+        ap.error("--out is required unless --evaluate is given")
     X, T, energy = generate(range(TRAIN_SEED0, TRAIN_SEED0 + a.train_seeds), a.nz)
     leak, leak_rms = fit_leak(energy)
     print(f"generation-1 leak fraction {energy[:, 5].min():.3f} .. {energy[:, 5].max():.3f}; model "
@@ -176,13 +216,7 @@ def main(argv=None):
     rows = evaluate(blob, range(EVAL_SEED0, EVAL_SEED0 + a.eval_seeds), a.nz)
     summary = dict(train_seeds=a.train_seeds, slices=a.train_seeds * a.nz, steps=a.steps, batch=a.batch, lr=a.lr,
                    leak_model=leak.tolist(), leak_rms=leak_rms, final_loss=float(losses[-100:].mean()), eval=rows,
-                   train_beams=energy.tolist(),
-                   mean_err_net=float(np.mean([r["err_net"] for r in rows])),
-                   max_err_net=float(np.max([r["err_net"] for r in rows])),
-                   mean_err_surrogate=float(np.mean([r["err_surrogate"] for r in rows])),
-                   max_err_surrogate=float(np.max([r["err_surrogate"] for r in rows])),
-                   mean_err_primaries=float(np.mean([r["err_primaries"] for r in rows])),
-                   speedup=float(np.sum([r["ms_plain"] for r in rows]) / np.sum([r["ms_surrogate"] for r in rows])))
+                   train_beams=energy.tolist(), **summarize(rows))
     print(json.dumps({k: v for k, v in summary.items() if k not in ("eval", "train_beams")}), flush=True)
     if a.report:
         with open(a.report, "w") as f:
