@@ -36,16 +36,21 @@ def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def algorithmic(grid, tsz=4):
-    """Algorithmic bytes (and flops of the source product) per launch of every kernel kind."""
+def algorithmic(grid, tsz=4, source="bf16x1"):
+    """Algorithmic bytes (and flops of the source product) per launch of every kernel kind, with the
+    energy scans W and the source Q counted in the form the mode stores them: FP32 contexts keep W as
+    BF16 hi (+ lo in the three-product mode) and Q as BF16 in the single-product mode, FP32 otherwise."""
     nx, ny, nth, G, K1 = grid["nx"], grid["ny"], grid["nth"], grid["ng"], grid["ngen"]
     NA, NP = (nth - 1) ** 2, nx * ny
     lines = NA * NP
+    split = tsz == 4 and source != "fp32" and NA >= 128
+    wb = (4 if source == "bf16x3" else 2) if split else tsz      # bytes per scanned value
+    qb = 2 if split and source == "bf16x1" else tsz               # bytes per source value
     # energy pass (fused pair): psi1, psi2 read + write (4 values per group and line), per line
     # two densities and two FP64 deposits; generation k>0 also reads the 2 source sums, k<K writes 2
     ep = []
     for k in range(K1):
-        per = 4 * tsz + (2 * tsz if k > 0 else 0) + (2 * tsz if k + 1 < K1 else 0)
+        per = 4 * tsz + (2 * qb if k > 0 else 0) + (2 * wb if k + 1 < K1 else 0)
         ep.append(G * lines * per + lines * (2 * 8 + 2 * tsz))
     ep_bytes = sum(ep) / K1
     # T and A launch over all generations at once, or per generation (on the side stream) when one
@@ -54,7 +59,7 @@ def algorithmic(grid, tsz=4):
     tp_bytes = per_launch * G * 2 * lines * 2 * tsz          # every plane read and written once
     ap_bytes = per_launch * G * 2 * lines * 2 * tsz + NP * tsz
     qg_flops = 2.0 * NA * NA * 2 * G * NP            # one source product (2 half-step sums) per generation
-    qg_bytes = 2 * G * lines * 2 * tsz + NA * NA * tsz
+    qg_bytes = 2 * G * lines * (wb + qb) + NA * NA * (2 if split else tsz)
     return dict(epass=("bytes", ep_bytes), tpass=("bytes", tp_bytes), apass=("bytes", ap_bytes),
                 qgemm=("flops", qg_flops, qg_bytes))
 
@@ -124,7 +129,7 @@ def march(cfg, tag, precision, source, warmup, steps):
     log(f"{cfg['name']}: kernel totals over the timed region (ms, launches): "
         + ", ".join(f"{k} {v[0]:.1f}/{v[1]}" for k, v in prof.items()))
     tsz = 8 if precision == "fp64" else 4
-    alg = algorithmic(g, tsz)
+    alg = algorithmic(g, tsz, source)
     kernels = {}
     for k, (ms, n) in prof.items():
         if n == 0:

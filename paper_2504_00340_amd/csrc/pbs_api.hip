@@ -652,6 +652,14 @@ struct ProfScope {
 };
 
 // ---------------------------------------------------------------------------- march schedule
+// The single-product BF16 source product stores its result Q in BF16 too (halving the source traffic of
+// the product and of the energy pass that reads it); every other mode keeps Q in the working precision.
+// Only the split-BF16 energy pass reads the BF16 form, so straggling (its own energy pass) keeps FP32.
+bool source_bf16(const pbs_ctx *c)
+{
+    return c->tsz == 4 && c->Kpb > 0 && c->src_mode == PBS_SRC_BF16X1 && !c->strag;
+}
+
 template <typename T>
 EParams<T> eparams(pbs_ctx *c, int k, int lay_c, int lay_o, double h)
 {
@@ -660,6 +668,7 @@ EParams<T> eparams(pbs_ctx *c, int k, int lay_c, int lay_o, double h)
     double *db = c->tabD();
     P.psi = c->psi<T>(k);
     P.Q = (k > 0) ? c->Q<T>() : nullptr;
+    P.Qb = (k > 0 && source_bf16(c)) ? reinterpret_cast<const unsigned short *>(c->Q<T>()) : nullptr;
     P.W = (k + 1 < c->kact) ? c->W<T>() : nullptr;
     P.Wh = P.Wl = nullptr;
     P.NOCT = c->NOCT;
@@ -768,6 +777,7 @@ pbs_status energy_chain(pbs_ctx *c, int mode, int lay_c, int lay_o, double h, in
             Q.P2T = c->tabT<T>() + c->t_P2T;
             Q.W = c->W<T>();
             Q.Q = c->Q<T>();
+            Q.Qb = source_bf16(c) ? reinterpret_cast<unsigned short *>(c->Q<T>()) : nullptr;
             Q.NA = c->NA;
             Q.NPB = c->NPB;
             Q.G = c->G();

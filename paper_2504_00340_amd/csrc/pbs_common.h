@@ -27,6 +27,8 @@ struct EParams {
     T *psi;                 // one generation
     const T *Q;             // [2][G][NLINE] source without the density factor, Q^n + Q* of the closing (0)
                             // and opening (1) half-step, or null
+    const unsigned short *Qb = nullptr;   // the same source in BF16, [2][G][NPB][NAq / 4][PT][4] with
+                                          // NAq = NA rounded up to 4 (a = 4 a4 + e), which then replaces Q
     T *W;                   // [2][G][NLINE] energy-scanned psi^1 of this generation, summed over the two
                             // states of each half-step (0: close, 1: open), or null
     unsigned short *Wh, *Wl;   // split-BF16 form of W (hi, lo): [2][G][NPB][NOCT][PT][8], a' = 8*oct + e;
@@ -90,6 +92,7 @@ struct QParams {
     const T *P2T;           // [NA][NA]: P2T[a][a'] = probability a' -> a
     const T *W;             // [2][G][NLINE]
     T *Q;                   // [2][G][NLINE]
+    unsigned short *Qb = nullptr;   // non-null: write the source in BF16 there instead (EParams::Qb layout)
     const T *P2p;           // [Kp][Mp] zero-padded P2 (k = source node, row = destination), MFMA path
     int Kp, Mp;
     const unsigned short *Bh, *Bl;   // split-BF16 W (see EParams), split-BF16 path

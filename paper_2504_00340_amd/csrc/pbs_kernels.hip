@@ -375,6 +375,7 @@ template hipError_t launch_epass_strag<double>(const EParams<double> &, int, hip
 // 64 x 64-cell, 31 x 31-angle, 128-group, 4-generation beam).
 #define EP_LD(p) __builtin_nontemporal_load(p)
 #define EP_ST(v, p) __builtin_nontemporal_store(v, p)
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __builtin_bit_cast(float, (unsigned)h << 16); }
 // FEAT / LO = false compile out the surrogate records and the lo half of the split scans.
 template <int MODE, bool FEAT = true, bool LO = true, bool BANDS = false>
 __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
@@ -410,6 +411,11 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
     float fic = 0, fio = 0, fme = 0, fmn = 0;
     const bool hasQ = P.Q != nullptr, hasW = P.Wh != nullptr, hasL = LO && P.Wl != nullptr,
                feat = FEAT && P.inj_c != nullptr;
+    const bool qbf = hasQ && P.Qb != nullptr;
+    const int NAq = (NA + 3) & ~3;
+    const long QSb = (long)P.G * NPB * NAq * PBS_PT;
+    typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+    static_assert(L == 4, "the BF16 source is read as 4-line chunks");
     const long SB = (long)P.G * NPB * P.NOCT * (PBS_PT * 8);
     for (int g = P.G - 1; g >= 0; --g) {
         const float sm = P.Sm[g], sp = P.Sp[g], kp = P.kap[g];
@@ -428,10 +434,24 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
             x1[e] = v ? EP_LD(&p1[e * PBS_PT]) : 0.f;
             x2[e] = v ? EP_LD(&p2[e * PBS_PT]) : 0.f;
             qc[e] = qo[e] = 0.f;
-            if (hasQ && v) {
+            if (hasQ && !qbf && v) {
                 const long o = (long)g * S + line0 + e * PBS_PT;
                 if (CL) qc[e] = EP_LD(&P.Q[o]);
                 if (OP) qo[e] = EP_LD(&P.Q[QS + o]);
+            }
+        }
+        if (qbf && nval > 0) {
+            // the BF16 source holds the thread's 4 lines of one cell as one 8-byte chunk
+            const long o = (((long)g * NPB + pbk) * NAq + 8 * oct + L * sub) * PBS_PT + pt * L;
+            if (CL) {
+                const u16x4 c = EP_LD(reinterpret_cast<const u16x4 *>(P.Qb + o));
+#pragma unroll
+                for (int e = 0; e < L; ++e) qc[e] = e < nval ? bf16_to_f32(c[e]) : 0.f;
+            }
+            if (OP) {
+                const u16x4 c = EP_LD(reinterpret_cast<const u16x4 *>(P.Qb + QSb + o));
+#pragma unroll
+                for (int e = 0; e < L; ++e) qo[e] = e < nval ? bf16_to_f32(c[e]) : 0.f;
             }
         }
         const float w = P.wc[g], dec = P.wdec[g], idE = P.invdE[g];
@@ -2043,6 +2063,26 @@ __device__ __forceinline__ void store_source_tile(float *__restrict__ C, long NA
     }
 }
 
+// The same tile into the BF16 source [pb][row / 4][32 cells][4] (Qb): lane l holds column l % 32 of rows
+// 8 q + 4 (l / 32) + 0..3, i.e. one 4-row group of one cell, which leaves as one 8-byte store (each wave
+// instruction writes 2 x 256 B contiguous) with no exchange between lanes.  Rows NA .. NAq - 1 come from
+// the zero-padded rows of the transfer matrix.
+__device__ __forceinline__ void store_source_tile_bf16(unsigned short *__restrict__ Cb, int NAq, int pb, int row0,
+                                                       const floatx16 &a, int lane, int NPB)
+{
+    typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int row = row0 + 8 * q + 4 * (lane >> 5);
+        if (pb < NPB && row < NAq) {
+            u16x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = __builtin_bit_cast(unsigned short, (__bf16)a[4 * q + e]);
+            __builtin_nontemporal_store(v, reinterpret_cast<u16x4 *>(&Cb[((long)pb * NAq + row) * PBS_PT + (lane & 31) * 4]));
+        }
+    }
+}
+
 template <int BN, int NPROD>
 __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const unsigned short *__restrict__ Ahi,
                                                   const unsigned short *__restrict__ Alo, int Kp, int nmt, int nnt,
@@ -2069,6 +2109,8 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
     }
     const long off = ((long)s * P.G + g) * P.NLINE;
     float *__restrict__ C = P.Q + off;
+    const int NAq = (P.NA + 3) & ~3;
+    unsigned short *__restrict__ Cb = P.Qb ? P.Qb + ((long)s * P.G + g) * P.NPB * NAq * PBS_PT : nullptr;
     const long NAPT = (long)P.NA * PBS_PT;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WN, wn = wid % WN;
@@ -2165,7 +2207,12 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-            store_source_tile(C, NAPT, nt * NPBT + wn * 2 + j, mt * 128 + wm * 64 + i * 32, acc[i][j], lane, P.NA, P.NPB);
+            if (Cb)
+                store_source_tile_bf16(Cb, NAq, nt * NPBT + wn * 2 + j, mt * 128 + wm * 64 + i * 32, acc[i][j], lane,
+                                       P.NPB);
+            else
+                store_source_tile(C, NAPT, nt * NPBT + wn * 2 + j, mt * 128 + wm * 64 + i * 32, acc[i][j], lane, P.NA,
+                                  P.NPB);
 }
 
 // Source product with the energy-scanned fluence read straight from global memory: its split
@@ -2220,6 +2267,8 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
     }
     const long off = ((long)s * P.G + g) * P.NLINE;
     float *__restrict__ C = P.Q + off;
+    const int NAq = (P.NA + 3) & ~3;
+    unsigned short *__restrict__ Cb = P.Qb ? P.Qb + ((long)s * P.G + g) * P.NPB * NAq * PBS_PT : nullptr;
     const long NAPT = (long)P.NA * PBS_PT;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WN, wn = wid % WN;
@@ -2326,8 +2375,12 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
     for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < TJ; ++j)
-            store_source_tile(C, NAPT, nt * 8 + wn * TJ + j, mt * 128 + wm * (32 * TI) + i * 32, acc[i][j], lane, P.NA,
-                              P.NPB);
+            if (Cb)
+                store_source_tile_bf16(Cb, NAq, nt * 8 + wn * TJ + j, mt * 128 + wm * (32 * TI) + i * 32, acc[i][j],
+                                       lane, P.NPB);
+            else
+                store_source_tile(C, NAPT, nt * 8 + wn * TJ + j, mt * 128 + wm * (32 * TI) + i * 32, acc[i][j], lane,
+                                  P.NA, P.NPB);
 }
 
 template <int NPROD>
@@ -2639,6 +2692,7 @@ __global__ __launch_bounds__(256) void epass_batched_kernel(
     const int G = B.G;
     P.psi = B.psi + (long)k * G * 2 * Sh.NLINE;
     P.Q = k > 0 ? B.Q : nullptr;
+    P.Qb = (k > 0 && Sh.nprod == 1) ? reinterpret_cast<const unsigned short *>(B.Q) : nullptr;
     P.W = nullptr;
     const bool w = k + 1 < Sh.ngen;
     P.Wh = w ? B.Wh : nullptr;
@@ -2685,6 +2739,7 @@ __attribute__((amdgpu_waves_per_eu(BN == 0 && NPROD == 1 ? QG_WPE : 1))) void qg
     P.P2T = nullptr;
     P.W = nullptr;
     P.Q = B.Q;
+    P.Qb = NPROD == 1 ? reinterpret_cast<unsigned short *>(B.Q) : nullptr;   // single product: BF16 source
     P.P2p = nullptr;
     P.Kp = Sh.Kpb;
     P.Mp = Sh.Mp;
