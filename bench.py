@@ -66,7 +66,7 @@ def algorithmic(grid, tsz=4, source="bf16x1"):
 
 # kernel names of each kind at the two march workloads (as rocprofv3 reports them)
 KIND_KERNEL = {
-    "c3": {"tpass": "tpass_wide_kernel<96>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16g_kernel<1>",
+    "c3": {"tpass": "tpass_wide2_kernel", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16g_kernel<1>",
            "epass": "epass8_kernel<3, false, false, false>"},
     "c2": {"tpass": "tpass_affine_kernel<64>", "apass": "apass_mfma32_kernel", "qgemm": "qgemm_bf16g_kernel<1>",
            "epass": "epass8_kernel<3, false, false, false>"},
