@@ -587,8 +587,14 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
 
 // 5 waves per SIMD for the plain kernels (96 VGPRs, a few spilled registers): measured faster than 4
 // waves without spills
+// Minimum waves per SIMD of the plain energy passes (compile-time knob).  At 5 the compiler held the
+// pair-mode kernel to 96 VGPRs and spilled 80 bytes per thread, reloaded in every group step; at 4 it
+// takes 114 VGPRs with no scratch (config-2 energy pass 2.94 -> 2.71 ms per launch, config 3 -1 %).
+#ifndef EP_WPE
+#define EP_WPE 4
+#endif
 template <int MODE, bool FEAT, bool LO, bool BANDS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT || BANDS ? 1 : 5))) void epass8_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT || BANDS ? 1 : EP_WPE))) void epass8_kernel(
     EParams<float> P)
 {
     epass8_body<MODE, FEAT, LO, BANDS>(P, (long)blockIdx.x * 256 + threadIdx.x);

@@ -79,8 +79,9 @@ def generate(seeds, nz: int = 300, log=print):
     return X, T, np.array(energy)
 
 
-def train(X, T, steps: int, batch: int, lr: float, seed: int, log=print):
-    """Adam on random minibatches; returns (params, per-step losses)."""
+def train(X, T, steps: int, batch: int, lr: float, seed: int, log=print, weights=None):
+    """Adam on random minibatches (slices drawn uniformly, or with probability proportional to `weights`,
+    one per slice); returns (params, per-step losses)."""
     import torch
 
     n = X.shape[0]
@@ -88,10 +89,14 @@ def train(X, T, steps: int, batch: int, lr: float, seed: int, log=print):
     net.set_params(init_params(seed))
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
+    wt = None if weights is None else torch.as_tensor(weights, dtype=torch.float32, device="cuda")
     losses = torch.zeros(steps, dtype=torch.float64, device="cuda")
     t0 = time.time()
     for k in range(steps):
-        idx = torch.randint(0, n, (batch,), device="cuda", generator=g)
+        if wt is None:
+            idx = torch.randint(0, n, (batch,), device="cuda", generator=g)
+        else:
+            idx = torch.multinomial(wt, batch, replacement=True, generator=g)
         xb = X.index_select(0, idx).contiguous()
         tb = T.index_select(0, idx).contiguous()
         lr_k = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * k / steps)))
@@ -186,6 +191,8 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--energy-weight", type=float, default=0.0, metavar="P",
+                    help="draw a beam's slices with weight (E0 / 150 MeV)^P (0: uniform)")
     ap.add_argument("--out", default=None, help="weights blob to write")
     ap.add_argument("--evaluate", default=None, metavar="BLOB",
                     help="skip data and training: evaluate this weights blob on the held-out seeds")
@@ -208,13 +215,17 @@ def main(argv=None):
     print(f"generation-1 leak fraction {energy[:, 5].min():.3f} .. {energy[:, 5].max():.3f}; model "
           f"{leak.tolist()} rms {leak_rms:.3e}; injected / primary deposit "
           f"{np.mean(energy[:, 3] / energy[:, 6]):.3e}", flush=True)
-    params, losses = train(X, T, a.steps, a.batch, a.lr, a.seed)
+    weights = None
+    if a.energy_weight:
+        weights = np.repeat((energy[:, 1] / 150.0) ** a.energy_weight, a.nz)
+    params, losses = train(X, T, a.steps, a.batch, a.lr, a.seed, weights=weights)
     del X, T
     blob = pack_weights(params, leak)
     with open(a.out, "wb") as f:
         f.write(blob)
     rows = evaluate(blob, range(EVAL_SEED0, EVAL_SEED0 + a.eval_seeds), a.nz)
     summary = dict(train_seeds=a.train_seeds, slices=a.train_seeds * a.nz, steps=a.steps, batch=a.batch, lr=a.lr,
+                   energy_weight=a.energy_weight,
                    leak_model=leak.tolist(), leak_rms=leak_rms, final_loss=float(losses[-100:].mean()), eval=rows,
                    train_beams=energy.tolist(), **summarize(rows))
     print(json.dumps({k: v for k, v in summary.items() if k not in ("eval", "train_beams")}), flush=True)
