@@ -229,11 +229,14 @@ pbs_status pbs_apply(pbs_ctx *ctx, int op, int layer, double h);
  *   PBS_SRC_FP32    FP32 MFMA
  *   PBS_SRC_BF16X3  both operands split as hi + lo bfloat16, three BF16 MFMA products accumulated
  *                   in FP32 (relative error of each term <= ~2^-15)
- *   PBS_SRC_BF16X2  the transfer matrix split as hi + lo, the energy-scanned fluence rounded once to
- *                   bfloat16 (unbiased rounding, independent per cell and group), two BF16 products
+ *   PBS_SRC_BF16X2  the transfer matrix split as hi + lo, the energy-scanned fluence rounded to bfloat16
+ *                   with error feedback along the groups (each line carries its rounding residue into
+ *                   the next group, so the errors telescope in the re-emitted number and energy), two
+ *                   BF16 products
  *   PBS_SRC_BF16X1  one BF16 product: the transfer matrix rounded to bfloat16 with every column
- *                   compensated to keep its exact sum (the number of re-emitted protons), the
- *                   scanned fluence rounded once; the default
+ *                   compensated to keep its exact sum (the number of re-emitted protons), the scanned
+ *                   fluence rounded as in BF16X2, and the product itself stored in bfloat16 (read once,
+ *                   by the next generation's energy pass); the default
  * Other contexts always use their own precision; the split modes there return PBS_EUNSUPPORTED. */
 enum { PBS_SRC_FP32 = 0, PBS_SRC_BF16X3 = 1, PBS_SRC_BF16X2 = 2, PBS_SRC_BF16X1 = 3 };
 pbs_status pbs_set_source_precision(pbs_ctx *ctx, int mode);

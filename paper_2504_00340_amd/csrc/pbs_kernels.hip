@@ -1191,6 +1191,12 @@ __global__ __launch_bounds__(256) void tpass_wide_kernel(TParams<float> P)
 }
 
 constexpr int TPASS_W2_PF = 4;   // rows loaded ahead per operation in the two-plane ny = 96 sweep
+// LDS reserved per block of the two-plane sweep, which uses none: it caps the sweep at 3 blocks (12 waves)
+// per CU.  Fewer concurrent plane streams suit the memory system: a copy with the sweep's addresses runs
+// 5.18 -> 5.43 TB/s at 2 blocks per CU, and the config-3 sweep 8.76 -> 8.47 ms per launch at 2 or 3.
+#ifndef TP_W2_LDS
+#define TP_W2_LDS 54000
+#endif
 
 // ny = 96 with two planes per wave (A = plane 2w, B = plane 2w + 1; the plane count is even).  A row of
 // both planes is three full 64-lane operations: A columns 0-63, B columns 0-63, then A columns 64-95 in
@@ -1393,7 +1399,7 @@ hipError_t launch_tpass(const TParams<T> &P, hipStream_t st)
         if (P.nx % TPASS_W2_PF == 0 && P.ny == 96 && P.nplanes % 2 == 0 && 2 * P.NLINE * 4 < 0x7fffffffL &&
             P.nplanes / 2 < 0x7fffffffL) {
             const long pairs = P.nplanes / 2;
-            hipLaunchKernelGGL(tpass_wide2_kernel, dim3((unsigned)((pairs + 3) / 4)), dim3(256), 0, st, P);
+            hipLaunchKernelGGL(tpass_wide2_kernel, dim3((unsigned)((pairs + 3) / 4)), dim3(256), TP_W2_LDS, st, P);
             return hipGetLastError();
         }
         if (P.nx % TPASS_PF == 0 && P.ny == 96) {
@@ -1464,9 +1470,19 @@ __device__ __forceinline__ void apass_body(const AParams<T> &P, int bx, long by)
     const int pb = bx / (PBS_PT / PC);
     const int c0 = (bx % (PBS_PT / PC)) * PC;
     T *blk = P.psi + stack * P.NLINE + (long)pb * NA * PBS_PT + c0;
-    for (int idx = tid; idx < NA * PC; idx += 256) {
-        const int a = idx / PC, c = idx % PC;
-        L[idx] = blk[(long)a * PBS_PT + c];
+    // 8 loads in flight per thread before their LDS stores (a load-store loop waits for each in turn)
+    for (int i0 = tid; i0 < NA * PC; i0 += 8 * 256) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * 256;
+            if (idx < NA * PC) v[u] = blk[(long)(idx / PC) * PBS_PT + idx % PC];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * 256;
+            if (idx < NA * PC) L[idx] = v[u];
+        }
     }
     __syncthreads();
     constexpr T inv2N = T(2) / T(N);
@@ -2447,9 +2463,10 @@ hipError_t launch_qgemm_bf16s(const QParams<float> &P, const unsigned short *Ahi
 
 // FP64 MFMA version (v_mfma_f64_16x16x4_f64, output row = lane/16 + 4 q, column = lane % 16).
 // Block tile 128 x 128 (4 lateral tiles), BK = 16; 4 waves in 2 x 2, each 64 x 64 = 4 x 4 MFMA tiles.
+// Up to 2 waves per SIMD: with the compiler's default target it spilled 80 bytes per thread.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void qgemm_mfma_f64_kernel(QParams<double> P, int nmt, int nnt, long nlogical,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void qgemm_mfma_f64_kernel(QParams<double> P, int nmt, int nnt, long nlogical,
                                                              long per_xcd)
 {
     const long bid = blockIdx.x;
