@@ -23,6 +23,15 @@ typedef unsigned short u16x8v __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
+// Per-group table entries are the same for every lane: read through the constant address space they
+// become scalar loads (one per wave, kept apart from the vector memory counter) instead of a vector load
+// per lane that the group step then waits for.
+template <typename T>
+__device__ __forceinline__ T tab(const T *p, long i)
+{
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 // ------------------------------------------------------------------------------- energy pass
 // One thread per line (FP64 contexts, and FP32 contexts whose source product takes the plain scan W):
 // block = one lateral tile pb and one octet of angular lines a = 8*oct + e (e = tid/32), 32 cells
@@ -56,7 +65,7 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
         T *p1 = P.psi + (2L * g) * S + line;
         T *p2 = p1 + S;
         const T x1 = *p1, x2 = *p2;
-        const T sm = P.Sm[g], sp = P.Sp[g], kp = P.kap[g];
+        const T sm = tab(P.Sm, g), sp = tab(P.Sp, g), kp = tab(P.kap, g);
         // rho-free operator: psi1 row [-(S-+k), S-], psi2 row [-3S+, -(S+ + 2S- + k)], coupling S+[1,3]
         const T d11 = -(sm + kp), d12 = sm, d21 = T(-3) * sp, d22 = -(sp + T(2) * sm + kp);
         const T c1 = sp, c2 = T(3) * sp;
@@ -90,7 +99,7 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
         *p1 = z1;
         *p2 = z2;
         // deposit functional (FP64): stopping + removal of every state, bottom-face outflow
-        const double A = P.dA[g], B = P.dB[g];
+        const double A = tab(P.dA, g), B = tab(P.dB, g);
         if (CL) ph0 += A * (double)x1 + B * (double)x2;
         ph1 += A * (double)y1 + B * (double)y2;
         if (OP) ph2 += A * (double)z1 + B * (double)z2;
@@ -100,22 +109,22 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
             if (OP) ph2 += P.dBot * ((double)z1 - (double)z2);
         }
         if (hasQ) {
-            const double wi = P.dInj[g];
+            const double wi = tab(P.dInj, g);
             if (CL) injc += wi * (double)qc;
             if (OP) injo += wi * (double)qo;
         }
         if (hasW || feat) {
             // energy scans of the three states; the next generation needs the sums 0+1 and 1+2
-            const T w = P.wc[g], dec = P.wdec[g], idE = P.invdE[g];
+            const T w = tab(P.wc, g), dec = tab(P.wdec, g), idE = tab(P.invdE, g);
             const long o = (long)g * S + line;
             if constexpr (BANDS) {
                 // the sum of one scan per band, each with its band's decay; group g feeds its own band
-                const int bg = P.band[g];
+                const int bg = tab(P.band, g);
                 U0 = U1 = U2 = T(0);
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
                     if (b < P.NB) {
-                        const T d = P.wdecb[b * P.G + g], wb = b == bg ? w : T(0);
+                        const T d = tab(P.wdecb, (long)b * P.G + g), wb = b == bg ? w : T(0);
                         if (CL) U0 += (U0b[b] = wb * x1 + d * U0b[b]);
                         U1 += (U1b[b] = wb * y1 + d * U1b[b]);
                         if (OP) U2 += (U2b[b] = wb * z1 + d * U2b[b]);
@@ -128,12 +137,12 @@ __device__ __forceinline__ void epass_body(const EParams<T> &P, int bx)
             if (feat) {
                 // energy the re-emission puts into the next generation (the dInj functional of its
                 // source summed over destination angles, which the angular law conserves), moments
-                const T wi = (T)P.dInj[g];
+                const T wi = (T)tab(P.dInj, g);
                 if (CL) fic += wi * ((U0 + U1) * idE);
                 if (OP) {
                     fio += wi * ((U1 + U2) * idE);
-                    fme += (T)P.wmom[g] * z1 + (T)P.wmom[2 * P.G + g] * z2;
-                    fmn += (T)P.wmom[P.G + g] * z1;
+                    fme += (T)tab(P.wmom, g) * z1 + (T)tab(P.wmom, 2L * P.G + g) * z2;
+                    fmn += (T)tab(P.wmom, (long)P.G + g) * z1;
                 }
             }
             if (hasW) {
@@ -234,16 +243,16 @@ __global__ __launch_bounds__(256) void strag_factor_kernel(const T *__restrict__
 template <typename T, bool BANDS>
 __device__ __forceinline__ T scan_step(const EParams<T> &P, int g, T x, T &U, T (&Ub)[4])
 {
-    const T w = P.wc[g];
+    const T w = tab(P.wc, g);
     if constexpr (BANDS) {
-        const int bg = P.band[g];
+        const int bg = tab(P.band, g);
         T u = T(0);
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-            if (b < P.NB) u += (Ub[b] = (b == bg ? w : T(0)) * x + P.wdecb[b * P.G + g] * Ub[b]);
+            if (b < P.NB) u += (Ub[b] = (b == bg ? w : T(0)) * x + tab(P.wdecb, (long)b * P.G + g) * Ub[b]);
         return u;
     } else {
-        U = w * x + P.wdec[g] * U;
+        U = w * x + tab(P.wdec, g) * U;
         return U;
     }
 }
@@ -280,9 +289,9 @@ __device__ void strag_half(const EParams<T> &P, long line, long pq, int half, do
         b2 += Fg[2 * FS] * bu1 + Fg[3 * FS] * bu2;
         P.psi[(2L * g) * S + line] = b1;
         P.psi[(2L * g + 1) * S + line] = b2;
-        phn += P.dA2[g] * (double)x1 + P.dB2[g] * (double)x2;
-        if (hasQ) inj += P.dInj[g] * (double)q;
-        if (hasW) W[(long)g * S + line] = scan_step<T, BANDS>(P, g, x1, U, Ub) * P.invdE[g];
+        phn += tab(P.dA2, g) * (double)x1 + tab(P.dB2, g) * (double)x2;
+        if (hasQ) inj += tab(P.dInj, g) * (double)q;
+        if (hasW) W[(long)g * S + line] = scan_step<T, BANDS>(P, g, x1, U, Ub) * tab(P.invdE, g);
         xu1 = x1, xu2 = x2, bu1 = b1, bu2 = b2;
         x1 = xl1, x2 = xl2;
     }
@@ -297,7 +306,7 @@ __device__ void strag_half(const EParams<T> &P, long line, long pq, int half, do
         const T y1 = Di[0] * c1 + Di[FS] * c2, y2 = Di[2 * FS] * c1 + Di[3 * FS] * c2;
         P.psi[(2L * g) * S + line] = y1;
         P.psi[(2L * g + 1) * S + line] = y2;
-        phs += P.dA2[g] * (double)y1 + P.dB2[g] * (double)y2;
+        phs += tab(P.dA2, g) * (double)y1 + tab(P.dB2, g) * (double)y2;
         y1p = y1, y2p = y2;
     }
     // sweep down: the scan of X*, added to that of X^n
@@ -306,7 +315,7 @@ __device__ void strag_half(const EParams<T> &P, long line, long pq, int half, do
 #pragma unroll
         for (int b = 0; b < 4; ++b) Ub[b] = 0;
         for (int g = P.G - 1; g >= 0; --g)
-            W[(long)g * S + line] += scan_step<T, BANDS>(P, g, P.psi[(2L * g) * S + line], U, Ub) * P.invdE[g];
+            W[(long)g * S + line] += scan_step<T, BANDS>(P, g, P.psi[(2L * g) * S + line], U, Ub) * tab(P.invdE, g);
     }
     dep_out = ad * (phn + phs - inj) * P.scale;
 }
@@ -418,7 +427,7 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
     static_assert(L == 4, "the BF16 source is read as 4-line chunks");
     const long SB = (long)P.G * NPB * P.NOCT * (PBS_PT * 8);
     for (int g = P.G - 1; g >= 0; --g) {
-        const float sm = P.Sm[g], sp = P.Sp[g], kp = P.kap[g];
+        const float sm = tab(P.Sm, g), sp = tab(P.Sp, g), kp = tab(P.kap, g);
         const float d11 = -(sm + kp), d12 = sm, d21 = -3.f * sp, d22 = -(sp + 2.f * sm + kp);
         const float c1 = sp, c2 = 3.f * sp;
         const float mc11 = 1.f - ac * d11, mc12 = -ac * d12, mc21 = -ac * d21, mc22 = 1.f - ac * d22;
@@ -454,7 +463,7 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
                 for (int e = 0; e < L; ++e) qo[e] = e < nval ? bf16_to_f32(c[e]) : 0.f;
             }
         }
-        const float w = P.wc[g], dec = P.wdec[g], idE = P.invdE[g];
+        const float w = tab(P.wc, g), dec = tab(P.wdec, g), idE = tab(P.invdE, g);
         double s0a = 0, s0b = 0, s1a = 0, s1b = 0, s2a = 0, s2b = 0, sqc = 0, sqo = 0;
         typedef unsigned short chunk_t __attribute__((ext_vector_type(L)));
         chunk_t hc, lc, ho, lo;
@@ -495,12 +504,12 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
             if (hasW || feat) {
                 if constexpr (BANDS) {
                     // the sum of one scan per band, each with its band's decay; group g feeds its own band
-                    const int bg = P.band[g];
+                    const int bg = tab(P.band, g);
                     U0[e] = U1[e] = U2[e] = 0.f;
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
                         if (b < P.NB) {
-                            const float d = P.wdecb[b * P.G + g], wb = b == bg ? w : 0.f;
+                            const float d = tab(P.wdecb, (long)b * P.G + g), wb = b == bg ? w : 0.f;
                             if (CL) U0[e] += (U0b[b][e] = wb * x1[e] + d * U0b[b][e]);
                             U1[e] += (U1b[b][e] = wb * y1 + d * U1b[b][e]);
                             if (OP) U2[e] += (U2b[b][e] = wb * z1 + d * U2b[b][e]);
@@ -532,12 +541,12 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
                     rco[e] = to - (float)bo;
                 }
                 if (feat) {
-                    const float wi = (float)P.dInj[g];
+                    const float wi = (float)tab(P.dInj, g);
                     if (CL) fic += wi * vc;
                     if (OP) {
                         fio += wi * vo;
-                        fme += (float)P.wmom[g] * z1 + (float)P.wmom[2 * P.G + g] * z2;
-                        fmn += (float)P.wmom[P.G + g] * z1;
+                        fme += (float)tab(P.wmom, g) * z1 + (float)tab(P.wmom, 2L * P.G + g) * z2;
+                        fmn += (float)tab(P.wmom, (long)P.G + g) * z1;
                     }
                 }
             }
@@ -546,7 +555,7 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
             fop[e] = z1 - z2;
         }
         // deposit functional (FP64), summed over the lines: A, B depend on the energy group only
-        const double A = P.dA[g], B = P.dB[g];
+        const double A = tab(P.dA, g), B = tab(P.dB, g);
         if (CL) ph0 += A * s0a + B * s0b;
         ph1 += A * s1a + B * s1b;
         if (OP) ph2 += A * s2a + B * s2b;
@@ -556,7 +565,7 @@ __device__ __forceinline__ void epass8_body(const EParams<float> &P, long gid)
             if (OP) ph2 += P.dBot * (s2a - s2b);
         }
         if (hasQ) {
-            const double wi = P.dInj[g];
+            const double wi = tab(P.dInj, g);
             if (CL) injc += wi * sqc;
             if (OP) injo += wi * sqo;
         }
@@ -2247,7 +2256,8 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
 // with QG_WM = 2 a wave owns 64 rows x 4 lateral tiles.  B fragments of the next QG_PFD 16-node steps
 // are in flight while a step computes.
 // Tuning knobs (compile-time): B prefetch depth in 16-node steps (single-beam and batched kernels),
-// minimum waves per SIMD for the one-product kernels, and waves along rows.
+// minimum waves per SIMD for the one-product kernels, waves along rows, and two LDS buffers for the
+// transfer-matrix stage (one barrier per stage instead of two).
 #ifndef QG_PFD
 #define QG_PFD 3
 #endif
@@ -2259,6 +2269,9 @@ __device__ __forceinline__ void qgemm_bf16s_body(const QParams<float> &P, const 
 #endif
 #ifndef QG_WM
 #define QG_WM 1
+#endif
+#ifndef QG_DB
+#define QG_DB 1
 #endif
 
 template <int NPROD, int PFD_ = QG_PFD>
@@ -2274,7 +2287,8 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
     constexpr bool ALO = NPROD >= 2;
     constexpr int WM = QG_WM, WN = 4 / WM;       // waves along rows / along lateral tiles
     constexpr int TI = 4 / WM, TJ = 8 / WN;      // 32-row tiles and lateral tiles per wave
-    __shared__ unsigned short sAh[128 * LD], sAl[ALO ? 128 * LD : 8];
+    constexpr int NBUF = QG_DB ? 2 : 1;   // A stages in LDS (2: the next stage is written during this one)
+    __shared__ unsigned short sAh[NBUF][128 * LD], sAl[NBUF][ALO ? 128 * LD : 8];
     const long logical = (bid & 7) * per_xcd + (bid >> 3);
     if (logical >= nlogical) return;
     const int mt = (int)(logical % nmt);
@@ -2335,12 +2349,12 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
             if constexpr (ALO) ral[c] = *reinterpret_cast<const u16x8 *>(Alo + ao);
         }
     };
-    auto astore = [&]() {
+    auto astore = [&](int buf) {
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int ch = tid + NT * c, arow = ch / (BK / 8), akq = ch % (BK / 8);
-            *reinterpret_cast<u16x8 *>(&sAh[arow * LD + akq * 8]) = rah[c];
-            if constexpr (ALO) *reinterpret_cast<u16x8 *>(&sAl[arow * LD + akq * 8]) = ral[c];
+            *reinterpret_cast<u16x8 *>(&sAh[buf][arow * LD + akq * 8]) = rah[c];
+            if constexpr (ALO) *reinterpret_cast<u16x8 *>(&sAl[buf][arow * LD + akq * 8]) = ral[c];
         }
     };
     // ring of B fragments: step kk lives in slot kk % NR; steps kk + 1 .. kk + PFD are in flight.
@@ -2350,11 +2364,12 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
     static_assert(PFD < NR && KS % NR == 0, "B ring");
     u16x8 bbh[NR][TJ], bbl[NR][TJ];
     aload(0);
-    astore();
+    astore(0);
 #pragma unroll
     for (int d = 0; d < PFD; ++d) bload(min(d, KS * nk - 1), bbh[d], bbl[d]);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
+        const int cur = NBUF == 2 ? (kt & 1) : 0;
         aload(min(kt + 1, nk - 1));
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
@@ -2369,9 +2384,9 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
 #pragma unroll
             for (int i = 0; i < TI; ++i) {
                 const int r = wm * (32 * TI) + i * 32 + (lane & 31);
-                ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAh[r * LD + ko]));
+                ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAh[cur][r * LD + ko]));
                 if constexpr (ALO)
-                    al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAl[r * LD + ko]));
+                    al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&sAl[cur][r * LD + ko]));
             }
 #pragma unroll
             for (int j = 0; j < TJ; ++j) {
@@ -2387,10 +2402,16 @@ __device__ __forceinline__ void qgemm_bf16g_body(const QParams<float> &P, const 
                 }
             }
         }
-        __syncthreads();
-        if (kt + 1 < nk) {
-            astore();
+        if constexpr (NBUF == 2) {
+            // the other buffer was last read in the previous stage, which every wave has left
+            if (kt + 1 < nk) astore(cur ^ 1);
             __syncthreads();
+        } else {
+            __syncthreads();
+            if (kt + 1 < nk) {
+                astore(0);
+                __syncthreads();
+            }
         }
     }
 #pragma unroll
@@ -2618,29 +2639,29 @@ hipError_t launch_combine(T *y, const T *x, T a, T b, long n, hipStream_t st)
 template hipError_t launch_combine<float>(float *, const float *, float, float, long, hipStream_t);
 template hipError_t launch_combine<double>(double *, const double *, double, double, long, hipStream_t);
 
-// edep[pq] += sum over generations and angles of dep[k][line(pq, a)], fixed order: one block per
-// lateral tile, 32 lanes per cell x 32 angle slices, then a fixed-order tree over the slices.
+// edep[pq] += sum over generations and angles of dep[k][line(pq, a)], fixed order: one wave per lateral
+// tile; lane (pt, h) sums the slots a = h, h + 2, ... of every generation in turn, then the two halves of
+// a cell are added (the same sum whichever lane adds).  A one-wave block fits beside whatever else is
+// resident on a CU, which matters where the reduction runs next to the transport and angular passes of
+// a batch.
 __device__ __forceinline__ void dose_reduce_body(double *edep, const double *dep, int ngen, int NA, int nslot,
                                                  long NLINE, int NP, int pb)
 {
-    __shared__ double part[32][33];
-    const int pt = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const int lane = threadIdx.x & 63, pt = lane & 31, h = lane >> 5;
     const long base = (long)pb * NA * PBS_PT + pt;
     double s = 0.0;
-    for (int k = 0; k < ngen; ++k)
-        for (int a = sl; a < nslot; a += 32) s += dep[(long)k * NLINE + base + (long)a * PBS_PT];
-    part[sl][pt] = s;
-    __syncthreads();
-    for (int w = 16; w > 0; w >>= 1) {
-        if (sl < w) part[sl][pt] += part[sl + w][pt];
-        __syncthreads();
+    for (int k = 0; k < ngen; ++k) {
+        const double *d = dep + (long)k * NLINE + base;
+#pragma unroll 8
+        for (int a = h; a < nslot; a += 2) s += d[(long)a * PBS_PT];
     }
+    s += __shfl_xor(s, 32);
     const int pq = pb * PBS_PT + pt;
-    if (sl == 0 && pq < NP) edep[pq] += part[0][pt];
+    if (h == 0 && pq < NP) edep[pq] += s;
 }
 
-__global__ __launch_bounds__(1024) void dose_reduce_kernel(double *edep, const double *dep, int ngen, int NA,
-                                                           int nslot, long NLINE, int NP)
+__global__ __launch_bounds__(64) void dose_reduce_kernel(double *edep, const double *dep, int ngen, int NA,
+                                                         int nslot, long NLINE, int NP)
 {
     dose_reduce_body(edep, dep, ngen, NA, nslot, NLINE, NP, blockIdx.x);
 }
@@ -2649,8 +2670,7 @@ hipError_t launch_dose_reduce(double *edep_layer, const double *dep, int ngen, i
                               hipStream_t st)
 {
     const int npb = (NP + PBS_PT - 1) / PBS_PT;
-    hipLaunchKernelGGL(dose_reduce_kernel, dim3(npb), dim3(1024), 0, st, edep_layer, dep, ngen, NA, nslot, NLINE,
-                       NP);
+    hipLaunchKernelGGL(dose_reduce_kernel, dim3(npb), dim3(64), 0, st, edep_layer, dep, ngen, NA, nslot, NLINE, NP);
     return hipGetLastError();
 }
 
@@ -2912,7 +2932,7 @@ void apass_mfma_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh,
         apass_mfma16_body(P, Sh.K, blockIdx.y, pb, half);
 }
 
-__global__ __launch_bounds__(1024) void dose_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
+__global__ __launch_bounds__(64) void dose_batched_kernel(const BeamDev *__restrict__ beams, BatchShape Sh, int s)
 {
     const BeamDev &B = beams[blockIdx.y];
     const int mode = beam_mode(s, B.nz);
@@ -2920,7 +2940,6 @@ __global__ __launch_bounds__(1024) void dose_batched_kernel(const BeamDev *__res
     if (mode & MODE_CLOSE)
         dose_reduce_body(B.edep + (long)(s - 1) * NP, B.dep, Sh.ngen, Sh.NA, epass8_slots(Sh.NOCT), Sh.NLINE, NP,
                          blockIdx.x);
-    __syncthreads();
     if (mode & MODE_OPEN)
         dose_reduce_body(B.edep + (long)s * NP, B.dep + (long)Sh.ngen * Sh.NLINE, Sh.ngen, Sh.NA,
                          epass8_slots(Sh.NOCT), Sh.NLINE, NP, blockIdx.x);
@@ -3049,7 +3068,7 @@ hipError_t launch_batch_step(const BeamDev *beams, int nbeam, const BatchShape &
 #undef PBS_QG
         }
     }
-    hipLaunchKernelGGL(dose_batched_kernel, dim3(Sh.NPB, nbeam), dim3(1024), 0, st, beams, Sh, s);
+    hipLaunchKernelGGL(dose_batched_kernel, dim3(Sh.NPB, nbeam), dim3(64), 0, st, beams, Sh, s);
     if (!sd && march) {
         const hipError_t e = tat(-1, st);
         if (e != hipSuccess) return e;
