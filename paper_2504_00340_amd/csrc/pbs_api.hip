@@ -142,7 +142,7 @@ void apass_mfma_table(int nth, float *t)
     } else if (nth == 16) {
         for (int s = 0; s < 4; ++s)
             for (int lane = 0; lane < 64; ++lane) {
-                const int row = lane % 16, k = 4 * s + lane / 16;
+                const int row = 4 * (lane % 4) + (lane % 16) / 4, k = 4 * s + lane / 16;
                 t[s * 64 + lane] = (row < 15 && k < 15) ? (float)std::sin(M_PI * (row + 1) * (k + 1) / 16.0) : 0.f;
             }
     }

@@ -1667,23 +1667,13 @@ __device__ __forceinline__ void apass_mfma32_body(const AParams<float> &P, const
             const float te = al * (lk + lamE[q]);
             ze[q] = r < 15 ? ze[q] * (1.f + te) * __builtin_amdgcn_rcpf(1.f - te) : 0.f;
         }
-        // modes back through LDS into the operand layout (same wave, same line: in-order LDS)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = 4 * q + r4;
-            L[(k * m + r) * PC + cc] = zo[q];
-            if (r < 15) L[(k * m + 16 + r) * PC + cc] = ze[q];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        // the scaled modes are already the inverse's B operands: element s of lane group r4 holds mode
+        // 4 s + r4, the operand of step s (the permuted rows make the MFMA result layout the operand layout)
         floatx4 u = {0.f, 0.f, 0.f, 0.f}, v = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int r = 4 * s + r4;
-            const float bo = L[(k * m + r) * PC + cc];
-            const float be = r < 15 ? L[(k * m + 16 + r) * PC + cc] : 0.f;
-            u = mfma16(Bo[s], bo, u);
-            v = mfma16(Be[s], be, v);
+            u = mfma16(Bo[s], zo[s], u);
+            v = mfma16(Be[s], ze[s], v);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1734,8 +1724,12 @@ __device__ __forceinline__ void apass_mfma32_body(const AParams<float> &P, const
 // MFMA version for nth = 16 (15 interior nodes), FP32: each 15-point sine transform is one dense
 // 16 x 16 product (the matrix zero-padded), a chain of four v_mfma_f32_16x16x4_f32 whose 16 columns
 // are 16 lateral cells of one angular line; the 15 x 15 x 16 block (14.4 KB) stays in LDS.  The sine
-// matrix is symmetric, so the inverse uses the same operand table with the factor 2/N.
-//   Ktab[s*64 + lane] = S[lane % 16][4 s + lane / 16], S[r][k] = sin(pi (r+1)(k+1) / 16), zero at 15.
+// matrix is symmetric, so the inverse uses the same operand table with the factor 2/N.  As in the
+// 32-node pass the operand rows are permuted, so that result element q of lane group g holds index
+// 4 q + g: a store's lane groups then land in adjacent rows, and the modes of the second index feed
+// the inverse product straight from registers.
+//   Ktab[s*64 + lane] = S[perm(lane % 16)][4 s + lane / 16], S[r][k] = sin(pi (r+1)(k+1) / 16), zero at
+//   15, perm(4 g + q) = 4 q + g.
 __device__ __forceinline__ void apass_mfma16_body(const AParams<float> &P, const float *__restrict__ Ktab, long stack,
                                                   int pb, int half)
 {
@@ -1753,10 +1747,11 @@ __device__ __forceinline__ void apass_mfma16_body(const AParams<float> &P, const
     float A[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) A[s] = Ktab[s * 64 + lane];
+    // result element q of lane group r4 holds index 4 q + r4 (permuted operand rows)
     float lamR[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int r = 4 * r4 + q;
+        const int r = 4 * q + r4;
         lamR[q] = r < m ? P.lam[r] : 0.f;
     }
     const float al = 0.25f * P.h * P.sig[g] * P.rho[(long)pb * PBS_PT + c0 + cc];
@@ -1772,7 +1767,7 @@ __device__ __forceinline__ void apass_mfma16_body(const AParams<float> &P, const
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int r = 4 * r4 + q;
+            const int r = 4 * q + r4;
             if (r < m) L[(r * m + j) * PC + cc] = y[q];
         }
     }
@@ -1791,25 +1786,16 @@ __device__ __forceinline__ void apass_mfma16_body(const AParams<float> &P, const
             const float t = al * (lk + lamR[q]);
             z[q] = z[q] * (1.f + t) * __builtin_amdgcn_rcpf(1.f - t);
         }
-        // modes back through LDS into the operand layout (same wave, same line: in-order LDS)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = 4 * r4 + q;
-            if (r < m) L[(k * m + r) * PC + cc] = z[q];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        // the scaled modes are already the inverse's B operands (element s of lane group r4 is mode 4 s + r4,
+        // the operand of step s; mode 15 is zero: its operand row is)
         floatx4 u = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int r = 4 * s + r4;
-            u = mfma16(A[s], r < m ? L[(k * m + r) * PC + cc] : 0.f, u);
-        }
+        for (int s = 0; s < 4; ++s) u = mfma16(A[s], z[s], u);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int jp = 4 * r4 + q;
+            const int jp = 4 * q + r4;
             if (jp < m) L[(k * m + jp) * PC + cc] = u[q] * sc;
         }
     }
@@ -1826,7 +1812,7 @@ __device__ __forceinline__ void apass_mfma16_body(const AParams<float> &P, const
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int ip = 4 * r4 + q;
+            const int ip = 4 * q + r4;
             if (ip < m) L[(ip * m + j) * PC + cc] = u[q] * sc;
         }
     }
