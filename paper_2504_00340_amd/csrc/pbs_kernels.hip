@@ -1573,15 +1573,17 @@ static hipError_t launch_apass_n(const AParams<T> &P, long nstack, hipStream_t s
 // node, even modes on x_n - x_{32-n}); the inverse uses the transposed blocks with the output
 // butterflies x_n = u + v, x_{32-n} = u - v.  Every block product is a chain of four
 // v_mfma_f32_16x16x4_f32 whose 16 columns are 16 lateral cells of one angular line.  The block's
-// 31 x 31 x 16 values stay in LDS between the transforms; each wave owns whole lines, so the
-// transforms work in place without block-wide barriers.
+// 31 x 31 x 16 values stay in LDS between the passes over the two indices (a block barrier after each);
+// within a pass each wave owns whole lines and works in place.
 // LDS banks: an MFMA result holds rows 4 (lane / 16) + q in lane groups of 16, so writing row r of the
 // result with r = 4 (lane / 16) + q puts the four lane groups of one store 4 rows apart, a multiple of
 // the bank count at every row stride here (4-way conflicts).  The operand rows are therefore permuted,
 // result row 4 g + q holding output index 4 q + g, so one store's lane groups are one row apart; and
 // the modes are kept de-interleaved (odd block in rows 0-15, even block in rows 16-30, in both angular
 // directions), so consecutive odd (even) modes are adjacent.  Every LDS access then reaches 32
-// distinct banks per half wave.
+// distinct banks per half wave.  The same permutation makes a result the next product's operand: element
+// q of lane group g holds index 4 q + g, which lane group g supplies at chain step q, so the modes of the
+// second index go from the forward product to the inverse one in registers.
 //   Ktab[(mat*4 + s)*64 + lane] = A_mat[perm(lane % 16)][4 s + lane / 16] for mat = Sodd, Seven and
 //   A_mat[4 s + lane / 16][perm(lane % 16)] for mat = Sodd^T, Seven^T, perm(4 g + q) = 4 q + g.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
