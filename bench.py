@@ -318,7 +318,7 @@ def main():
                     help="also run one plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU sharding is a design note, "
+        print("bench.py: the library runs on one GPU only (the multi-GPU sharding is a design note, "
               "not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

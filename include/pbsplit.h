@@ -53,7 +53,7 @@ typedef enum {
     PBS_ESTATE = -2,       /* call out of order */
     PBS_ENOMEM = -3,       /* host allocation failed */
     PBS_EDEVICE = -4,      /* a HIP call failed */
-    PBS_EUNSUPPORTED = -5  /* valid request this build does not implement */
+    PBS_EUNSUPPORTED = -5  /* valid request the library does not implement */
 } pbs_status;
 
 enum { PBS_FP32 = 0, PBS_FP64 = 1 };

@@ -1,4 +1,4 @@
-// libpbsplit batch driver: many pencil beams of one shape class marched together.
+// libpbsplit batch planner: many pencil beams of one shape class marched together.
 //
 // Beams share the lateral grid, the angular grid and the number of generations; energy groups,
 // depth steps and step length are per beam.  Beams are grouped into waves (longest first) that fit

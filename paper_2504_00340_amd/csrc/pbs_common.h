@@ -140,7 +140,7 @@ struct BatchTuning {
     int gemm_kind = 0;        // split-BF16 product kernel (QGEMM_*)
     int tpass_wpb = 4;        // transport: planes (waves) per block, 1, 2 or 4
     int apass_pc = 32;        // angular pass: lateral cells per block, 8, 16 or 32
-    int max_nz = 0;           // longest beam of the wave (set by the driver)
+    int max_nz = 0;           // longest beam of the wave (set by the batch planner)
 };
 
 // Side stream of a batch march: each generation's T A T runs there after its energy pass (events per

@@ -1,4 +1,4 @@
-// Host-side context of one beam (shared by the single-beam ABI and the batch driver).
+// Host-side context of one beam (shared by the single-beam ABI and the batch planner).
 #pragma once
 #include <string>
 #include <utility>

@@ -8,7 +8,7 @@ with 1 MeV groups, 4 x 4 lateral cells on +-2 cm and 11 x 11 angular nodes on +-
 stopping-power model.  Measured at 230 MeV with the range fit: BP +1.0 %, P90 +1.1 %, D90 +1.0 %, D20
 +0.9 % (halving dz and the groups moves them by <= 0.7 %); with the paper's Bethe-Bloch form (App. A.1):
 BP -0.18 %, P90 -0.01 %, D90 -0.23 %, D20 -0.34 %.
-The lateral sigma of the 230 MeV column is not pinned: with this build's Highland scattering power the
+The lateral sigma of the 230 MeV column is not pinned: with the Highland scattering power used here the
 result depends on the angular box (0.64 to 0.76 cm at 32 cm for +-0.1 to +-0.15 rad against 0.757).
 """
 import numpy as np
